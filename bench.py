@@ -1,0 +1,198 @@
+#!/usr/bin/env python
+"""Benchmark: log-psi evaluations per second inside the local energy, 432-site Kagome.
+
+One step is one pass of the whole hot path over a batch of 2048 chains on the
+12x12x3 Kagome torus (864 bonds, GCN with 6 tied layers of width 64):
+
+    refresh log psi -> one Metropolis sweep (432 proposals per chain) ->
+    ISGO update (log psi, E_loc over every exchanged configuration, weights,
+    reverse pass) -> SGD update
+
+``value`` = local-energy log-psi evaluations (the library's exact count) per
+second of whole-step wall time, BF16 layer products.  Per-kernel durations come
+from HIP events the library records on its stream; the roofline entry is for
+the dominant kernel, k_eloc.  The CPU baseline times the FP64 oracle on a
+bounded prefix of the same batch, and its outputs give the error columns.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "log-psi evals/sec in E_loc (432-site Kagome), BF16 vs FP32 vs FP64 at stated err"
+PEAK = {"bf16": 2.5e15, "fp32": 157.3e12, "fp64": 78.6e12}   # MI355X dense MFMA, FLOP/s
+
+
+def flops_per_eval(n, n_edges, F, L):
+    """Algorithmic FLOPs of one log-psi evaluation: per layer the [M|H] W product
+    (2 N 2F F) and the aggregation (2 per stored adjacency entry per feature), plus
+    the two-head readout.  tanh is not counted."""
+    return L * (2 * n * 2 * F * F + 2 * (2 * n_edges) * F) + 2 * 2 * n * F
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="kagome432_L6F64")
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32", "fp64"])
+    ap.add_argument("--compare", default="fp32,fp64", help="other precisions timed on E_loc alone")
+    ap.add_argument("--compare-batch", type=int, default=512)
+    ap.add_argument("--eloc-reps", type=int, default=3)
+    ap.add_argument("--cpu-samples", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="headline steps only (for profilers)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as w
+    from paper_2011_12453_amd import GNA
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    p = w.preset(args.workload)
+    n, e = p.build_graph()
+    F, L, B = p.n_features, p.n_layers, p.batch
+    theta_np = w.glorot_theta(F, L, True, seed=p.theta_seed)
+    spins_np = w.random_sz0_spins(B, n, p.spin_seed)
+    fpe = flops_per_eval(n, len(e), F, L)
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+
+    # ---------------- headline: whole step ----------------
+    g = GNA(n, e, F, L, tied=True, precision=args.precision, max_batch=B, device=dev)
+    theta = torch.from_numpy(theta_np).to(dev)
+    spins = torch.from_numpy(spins_np).to(dev)
+    lp = torch.empty((B, 2), dtype=torch.float64, device=dev)
+    alpha = 1e-3
+    seed = 20201124
+
+    def step(k):
+        g.logpsi(theta, spins, out=lp)
+        g.metropolis_sweep(theta, spins, lp, n_sweeps=1, seed=seed, counter_base=k * n)
+        grad, stats, _ = g.isgo_grad(theta, spins, lp)
+        g.sgd_update(theta, grad, alpha)
+        return stats
+
+    log(f"[bench] {p.name}: N={n} |E|={len(e)} F={F} L={L} B={B} {args.precision}; warmup {args.warmup}")
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    g.profile_read()                 # discard
+    g.profile_enable(True)
+    stats_list = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        stats_list.append(step(args.warmup + k))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = g.profile_read()
+    g.profile_enable(False)
+    stats_all = torch.stack(stats_list).cpu().numpy()
+    evals = float(stats_all[:, 6].sum())
+    elapsed = t1 - t0
+    value = evals / elapsed
+    log(f"[bench] {args.steps} steps in {elapsed:.3f}s; {evals:.0f} E_loc evals; {value:.4g} evals/s")
+    log("[bench] kernels: " + ", ".join(f"{k} {v[1] / max(v[0], 1):.3f}ms x{v[0]}" for k, v in sorted(prof.items())))
+
+    # dominant kernel k_eloc: algorithmic FLOPs per launch / mean launch time
+    swapped = evals - args.steps * B           # k_logpsi does the B base evaluations
+    kl, kms = prof.get("k_eloc", (0, 0.0))
+    eloc_ms = kms / max(kl, 1)
+    achieved = (swapped / max(kl, 1)) * fpe / (eloc_ms * 1e-3) if kl else 0.0
+    roofline = {"bound": "mfma", "kernel": "k_eloc", "achieved": achieved / 1e12,
+                "peak": PEAK[args.precision] / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / PEAK[args.precision], "traffic": None,
+                "launch_ms": eloc_ms, "flops_per_eval": fpe}
+
+    # ---------------- E_loc alone, every precision ----------------
+    per_prec = {}
+    eloc_out = {}
+    for prec in [args.precision] + [q for q in args.compare.split(",") if q and q != args.precision]:
+        if args.quick and prec != args.precision:
+            continue
+        Bp = B if prec == args.precision else min(B, args.compare_batch)
+        gp = g if prec == args.precision else GNA(n, e, F, L, tied=True, precision=prec, max_batch=Bp, device=dev)
+        th0 = torch.from_numpy(theta_np).to(dev)
+        sp0 = torch.from_numpy(spins_np[:Bp]).to(dev)
+        el, nev = gp.local_energy(th0, sp0)        # warm
+        torch.cuda.synchronize()
+        gp.profile_read()
+        gp.profile_enable(True)
+        ta = time.perf_counter()
+        for _ in range(args.eloc_reps):
+            el, nev = gp.local_energy(th0, sp0)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        pr = gp.profile_read()
+        gp.profile_enable(False)
+        ne = int(nev.item())
+        rate = ne * args.eloc_reps / (tb - ta)
+        kl2, kms2 = pr.get("k_eloc", (1, 0.0))
+        per_prec[prec] = {"evals_per_s": rate, "batch": Bp, "evals_per_call": ne,
+                          "k_eloc_ms": kms2 / max(kl2, 1),
+                          "mfma_frac": (ne - Bp) * fpe / (kms2 / max(kl2, 1) * 1e-3) / PEAK[prec]}
+        eloc_out[prec] = el.cpu().numpy()
+        log(f"[bench] E_loc {prec}: B={Bp} {rate:.4g} evals/s, k_eloc {kms2 / max(kl2, 1):.2f} ms")
+        if gp is not g:
+            gp.close()
+
+    # ---------------- CPU baseline (FP64 oracle) and error columns ----------------
+    cpu = None
+    if not args.no_cpu_baseline and not args.quick:
+        import oracle
+        try:
+            from threadpoolctl import threadpool_info
+            threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        except Exception:
+            threads = os.cpu_count()
+        S = args.cpu_samples
+        sub = spins_np[:S]
+        tc = time.perf_counter()
+        ref = oracle.local_energy(theta_np, sub, n, e, F, L)
+        tcpu = time.perf_counter() - tc
+        ne_cpu = oracle.n_evals(sub, e)
+        cpu = {"value": ne_cpu / tcpu, "unit": "evals/s", "cores": threads, "kind": "oracle",
+               "sample": f"first {S} of {B} configurations ({ne_cpu} log-psi evals, {tcpu:.1f}s)"}
+        for prec, el in eloc_out.items():
+            got = el[:S]
+            es, rs = got[:, 0].mean() / n, ref.real.mean() / n
+            per_prec[prec]["err_energy_per_site"] = abs(es - rs) / max(abs(rs), 1e-2)
+            per_prec[prec]["err_eloc_max_rel"] = float(np.max(np.abs(got[:, 0] - ref.real) +
+                                                              np.abs(got[:, 1] - ref.imag)) / np.max(np.abs(ref)))
+        log(f"[bench] oracle: {cpu['value']:.4g} evals/s on {threads} threads")
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.precision, "data": "synthetic",
+        "config": {"workload": p.name, "lattice": "12x12x3 kagome torus", "sites": n, "bonds": len(e),
+                   "layers": L, "features": F, "tied": True, "batch": B,
+                   "step": "logpsi + 1 Metropolis sweep + ISGO update (logpsi, E_loc, stats, VJP) + SGD",
+                   "evals_per_step": evals / args.steps},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "precisions": per_prec,
+        "kernels_ms_per_step": {k: v[1] / args.steps for k, v in sorted(prof.items())},
+    }
+    print(json.dumps(out))
+    g.close()
+
+
+if __name__ == "__main__":
+    main()

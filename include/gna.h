@@ -1,0 +1,177 @@
+/*
+ * gna.h - C ABI of the graph-neural-ansatz variational Monte Carlo hot path on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * What the library computes (the paper: "Scalable variational Monte Carlo with
+ * graph neural ansatz", Yang, Hu, Li; NeurIPS 2020 ML4PS workshop):
+ *
+ *   ansatz (Section 2, Eq. 1):  H0_i = tanh(onehot(x_i) W_e + b_e),
+ *        H^{l+1} = tanh([A_hat H^l ; H^l] W + b),  A_hat = D^-1/2 A D^-1/2,
+ *        z = sum_i [H^L_i ; onehot(x_i)],  log psi = (v_a.z + c_a) + i (v_p.z + c_p)
+ *        (the two-head complex form the paper names in Section 5);
+ *   local energy (Section 3, E_x = sum_x' H_xx' Psi_x'/Psi_x) of the spin-1/2
+ *        Heisenberg model:  E(s) = sum_<ij> [Jz s_i s_j/4
+ *                                 + (Jxy/2)[s_i != s_j] psi(s^ij)/psi(s)];
+ *   Metropolis spin-swap sampling of |psi|^2 (Section 3);
+ *   ISGO gradient (Section 3, Eq. 3): samples drawn under psi_old reused with
+ *        self-normalised weights p_x ~ n_x |psi_x|^2 / |psi_old,x|^2 and
+ *        g = sum_x 2 p_x [Re(E_x - E) d log|psi_x| + Im(E_x - E) d phase_x].
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Spins are int8 values in {-1, +1}, row-major [B][n_sites]; s = 2x - 1 for
+ *   the paper's occupation x in {0, 1}.
+ * - theta is the flat FP64 parameter vector, gna_num_params() long, laid out as
+ *     W_e[2][F], b_e[F], W[nW][2F][F], b[nW][F], v_a[F+2], c_a, v_p[F+2], c_p
+ *   with nW = 1 when layers share W, b (tied, Section 2) and nW = L otherwise.
+ *   Rows 0..F-1 of W multiply the neighbour message A_hat H, rows F..2F-1 the
+ *   node's own row H.  Row 0 of W_e is the embedding of x = 0 (s = -1).
+ * - log psi values are FP64 pairs [B][2] = (log|psi|, phase).
+ * - Every pointer argument of the compute calls is a DEVICE pointer owned by the
+ *   caller.  The library never frees or keeps them past the call.
+ * - Every compute call only enqueues work on the context's stream and returns;
+ *   none allocates device memory, synchronises, or copies device data to the
+ *   host.  Results are valid once the stream has reached them.
+ * - Argument and graph checks are synchronous: on failure the call returns a
+ *   nonzero status, enqueues nothing, and gna_last_error() describes why.
+ *   A launch failure returns GNA_HIP_ERROR.  Numerical trouble (non-finite
+ *   values) is not an error status; gna_isgo_grad reports it in stats[7].
+ * - One context must not be used from two host threads at once.
+ * - B = 0 is valid for every call: nothing is computed, outputs that are
+ *   reductions (grad, stats, n_evals) are still written.
+ */
+#ifndef GNA_H
+#define GNA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gna_ctx gna_ctx;
+typedef int32_t gna_status;
+
+enum {
+  GNA_OK = 0,
+  GNA_INVALID_ARG = 1,   /* bad pointer, size, batch above max_batch, ... */
+  GNA_BAD_GRAPH = 2,     /* endpoint out of range, self-loop, repeated bond */
+  GNA_UNSUPPORTED = 3,   /* shape outside what the kernels are built for */
+  GNA_OUT_OF_MEMORY = 4, /* workspace allocation failed in gna_init */
+  GNA_HIP_ERROR = 5      /* a HIP runtime call or kernel launch failed */
+};
+
+/* Arithmetic of the layer products (Eq. 1).  The log-psi differences, the local
+ * energy sums, the ISGO weights and statistics are FP64 in every mode.
+ *   GNA_FP64: everything FP64 (MFMA f64).
+ *   GNA_FP32: operands, aggregation and tanh FP32, FP32 MFMA accumulation.
+ *   GNA_BF16: weights and inter-layer embeddings rounded to bfloat16 as MFMA
+ *             operands; aggregation, accumulation and tanh in FP32; the readout
+ *             sum is taken in FP64 from the FP32 last-layer output.          */
+enum { GNA_FP64 = 0, GNA_FP32 = 1, GNA_BF16 = 2 };
+
+typedef struct {
+  int32_t n_sites;          /* N >= 2 */
+  int32_t n_edges;          /* |E| >= 0 */
+  const int32_t *edges;     /* HOST pointer [n_edges][2], copied by gna_init;
+                               0 <= i, j < N, i != j, no repeated unordered pair.
+                               Periodic boundaries are part of the edge list. */
+  int32_t n_features;       /* F: 16, 32 or 64 */
+  int32_t n_layers;         /* L: 0 .. 16 applications of Eq. 1 */
+  int32_t tied;             /* 1: one W, b shared by all layers (the paper's
+                               choice, Section 2); 0: one per layer */
+  int32_t precision;        /* GNA_FP64 / GNA_FP32 / GNA_BF16 */
+  double jz, jxy;           /* Heisenberg couplings; the isotropic model is 1, 1 */
+  int32_t max_batch;        /* largest B any call will pass (sizes the workspace) */
+  int32_t reserved1;        /* must be 0 */
+  int64_t act_budget_bytes; /* device bytes the reverse pass may use for stored
+                               per-layer activations; 0 = library default.  The
+                               reverse pass recomputes activations per sample, so
+                               this bounds its concurrency, not its result. */
+  void *stream;             /* hipStream_t every call enqueues on (NULL = default) */
+} gna_config;
+
+/* Validate cfg, copy the graph, build A_hat, and allocate the device workspace.
+ * On success *out owns everything; release it with gna_destroy.  On failure
+ * *out is NULL and gna_last_error(NULL) describes the problem.              */
+gna_status gna_init(const gna_config *cfg, gna_ctx **out);
+
+/* Free the context and its workspace (waits for the context's stream first).
+ * NULL is ignored. */
+void gna_destroy(gna_ctx *ctx);
+
+/* Length of theta for this context's F, L and weight sharing. */
+int64_t gna_num_params(const gna_ctx *ctx);
+
+/* Text of the last error on ctx (or of the last failed gna_init when ctx is
+ * NULL).  Valid until the next call on the same context. */
+const char *gna_last_error(const gna_ctx *ctx);
+
+/* Change the stream later calls enqueue on. */
+gna_status gna_set_stream(gna_ctx *ctx, void *stream);
+
+/* log psi(s) of Eq. 1 plus the two-head readout, for B configurations.
+ * theta: [P] FP64; spins: [B][N] int8; logpsi: [B][2] FP64 output.          */
+gna_status gna_logpsi(gna_ctx *ctx, const double *theta, const int8_t *spins,
+                      int32_t B, double *logpsi);
+
+/* Heisenberg local energy of each configuration (Section 3's E_x), complex:
+ * eloc [B][2] FP64 = (Re, Im).  log psi(s) and log psi(s^ij) for every
+ * anti-aligned bond are evaluated in-kernel with the same arithmetic, so the
+ * differences cancel exactly outside the swapped sites' receptive field.
+ * n_evals (device int64, may be NULL) receives B + sum_x #anti-aligned bonds,
+ * the number of log-psi evaluations performed.                            */
+gna_status gna_local_energy(gna_ctx *ctx, const double *theta, const int8_t *spins,
+                            int32_t B, double *eloc, int64_t *n_evals);
+
+/* n_sweeps * N Metropolis proposals per chain (one chain per row; Section 3's
+ * Markov chain for |psi|^2).  Proposal k of chain b draws one Philox4x32-10
+ * block with counter (low32(t), high32(t), b, 0), t = counter_base + k, and key
+ * (low32(seed), high32(seed)); word 0 picks bond (w0 * n_edges) >> 32, word 1
+ * gives u = (w1 + 0.5) 2^-32.  An aligned bond is an identity step; otherwise
+ * the swap is accepted iff u < exp(2 Re[log psi(s^ij) - log psi(s)]).
+ * spins [B][N] and logpsi [B][2] are read and updated in place; logpsi must
+ * hold the chains' current values (e.g. from gna_logpsi on this context).
+ * n_accept: [B] int32 output (accepted swaps), may be NULL.                */
+gna_status gna_metropolis_sweep(gna_ctx *ctx, const double *theta, int8_t *spins,
+                                double *logpsi, int32_t B, int32_t n_sweeps,
+                                uint64_t seed, uint64_t counter_base, int32_t *n_accept);
+
+/* Reverse pass: grad[P] = sum_x cot[x][0] d log|psi(s_x)|/dtheta
+ *                         + cot[x][1] d phase(s_x)/dtheta   (overwritten).
+ * Computed in FP64 for every precision mode; per-layer activations are
+ * recomputed per sample, never stored for the whole batch.  cot: [B][2].   */
+gna_status gna_logpsi_vjp(gna_ctx *ctx, const double *theta, const int8_t *spins,
+                          int32_t B, const double *cot, double *grad);
+
+/* One ISGO update's gradient (Eq. 3) for samples drawn under an earlier theta:
+ * new log psi, local energies under the new psi, self-normalised weights
+ *   r_x = n_x exp(2 Re(lp_new - lp_old) - m),  m = max_x 2 Re(lp_new - lp_old),
+ *   p_x = r_x / sum r,  E = sum p_x E_x,
+ * then grad = reverse pass with cotangents 2 p_x (Re(E_x - E), Im(E_x - E)).
+ * logpsi_old: [B][2]; counts: [B] FP64 multiplicities or NULL (all 1);
+ * grad: [P] output; stats: [8] output = {Re E, Im E, sum p|E_x - E|^2,
+ *   ESS = (sum r)^2 / sum r^2, sum r, m, n_evals, nonfinite flag (0/1)};
+ * eloc: [B][2] output or NULL.                                             */
+gna_status gna_isgo_grad(gna_ctx *ctx, const double *theta, const int8_t *spins,
+                         const double *logpsi_old, const double *counts, int32_t B,
+                         double *grad, double *stats, double *eloc);
+
+/* Section 3's update theta <- theta - alpha * grad, in place on the device. */
+gna_status gna_sgd_update(gna_ctx *ctx, double *theta, const double *grad, double alpha);
+
+/* Kernel timing for benchmarks: while enabled, every kernel the context launches
+ * is bracketed by two HIP events recorded on the context's stream.
+ * gna_profile_read waits for the stream, then returns, per kernel name, the
+ * number of launches and their summed duration in milliseconds since the last
+ * read (max_entries rows of names[64 chars], launches, total_ms); the return value
+ * is the number of distinct kernels, or -1 on error.  Reading clears the record. */
+gna_status gna_profile_enable(gna_ctx *ctx, int32_t on);
+int32_t gna_profile_read(gna_ctx *ctx, int32_t max_entries, char *names,
+                         int64_t *launches, double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GNA_H */

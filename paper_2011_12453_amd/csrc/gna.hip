@@ -1,0 +1,1099 @@
+// gna.hip - HIP (gfx950) implementation of the C ABI declared in include/gna.h.
+//
+// Kernels:
+//   k_prepare        FP64 theta -> MFMA weight fragments, bias, embedding table
+//   k_logpsi         log psi of each sample (Eq. 1 + two-head readout)
+//   k_eloc           log psi of every bond-exchanged configuration, FP64
+//                    compensated sums of psi(s^ij)/psi(s) per (sample, bond chunk)
+//   k_eloc_finalize  diagonal term + chunk partials -> E_loc, evaluation count
+//   k_sweep          Metropolis spin-swap chains (Philox4x32-10 draws)
+//   k_isgo_stats     ISGO weights, energy, variance, ESS, cotangents (FP64)
+//   k_vjp / k_vjp_reduce   reverse pass in FP64, deterministic reduction
+//   k_sgd            theta -= alpha * grad
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <set>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "gna.h"
+#include "gna_kernels.h"
+
+using namespace gna;
+
+namespace {
+
+// ===========================================================================
+// Device kernels
+// ===========================================================================
+
+// Build the per-precision device weights from FP64 theta.
+//   wfrag[w][s][t][lane][j] = W[w][blk*F + kk][row_feature(16t + lane%16)],
+//   s < F/KS: message block (blk 0), else self block (blk 1);
+//   kk = KS*(s mod F/KS) + (VEC == 1 ? lane/16 : 4*(lane/16) + j).
+template <class P, int F>
+__global__ void k_prepare(const double* __restrict__ theta, int nW, void* wfrag, void* bias, void* emb) {
+  using T = typename P::T;
+  using Acc = typename P::Acc;
+  constexpr int KSB = F / P::KS, MT = F / 16, VEC = P::VEC;
+  const double* We = theta;
+  const double* be = theta + 2 * F;
+  const double* W = theta + 3 * F;
+  const double* b = W + (size_t)nW * 2 * F * F;
+  T* wf = reinterpret_cast<T*>(wfrag);
+  const int per_layer = 2 * F * F;
+  const int total = nW * per_layer;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    int r = e;
+    const int j = r % VEC; r /= VEC;
+    const int lane = r % 64; r /= 64;
+    const int t = r % MT; r /= MT;
+    const int s = r % (2 * KSB); r /= (2 * KSB);
+    const int w = r;
+    const int blk = s / KSB, ss = s % KSB;
+    const int kk = P::KS * ss + (VEC == 1 ? lane / 16 : 4 * (lane / 16) + j);
+    const int f = P::row_feature(16 * t + lane % 16);
+    const double v = W[(size_t)w * per_layer + (size_t)(blk * F + kk) * F + f];
+    wf[e] = P::from_acc((Acc)v);
+  }
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid < nW * F) reinterpret_cast<Acc*>(bias)[tid] = (Acc)b[tid];
+  if (tid < 2 * F) {
+    const int x = tid / F, f = tid % F;
+    reinterpret_cast<T*>(emb)[tid] = P::from_acc((Acc)tanh(We[x * F + f] + be[f]));
+  }
+}
+
+template <class P, int F, int TPW, int NCH>
+__global__ __launch_bounds__(TPW == 1 ? 1024 : 512) void k_logpsi(Net net, const int8_t* __restrict__ spins, int B,
+                                                 double* __restrict__ out) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  Smem<P> s(net.g, smem);
+  stage_graph<P>(net, s);
+  if (net.tied) stage_weights<P, F>(net, s, 0);
+  __syncthreads();
+  for (int b = blockIdx.x; b < B; b += gridDim.x) {
+    load_spins<P>(net, s, spins + (size_t)b * net.n);
+    double la = 0, ph = 0;
+    eval_config<P, F, TPW, NCH>(net, s, -1, -1, la, ph);
+    if (threadIdx.x == 0) {
+      out[2 * (size_t)b] = la;
+      out[2 * (size_t)b + 1] = ph;
+    }
+  }
+}
+
+__device__ __forceinline__ void neumaier(double& sum, double& comp, double x) {
+  const double t = sum + x;
+  comp += (fabs(sum) >= fabs(x)) ? ((sum - t) + x) : ((x - t) + sum);
+  sum = t;
+}
+
+// partial[item] = {sum re, comp re, sum im, comp im} of psi(s^ij)/psi(s) over the
+// anti-aligned bonds of chunk c of sample b (item = b * n_chunks + c), in bond order.
+template <class P, int F, int TPW, int NCH>
+__global__ __launch_bounds__(TPW == 1 ? 1024 : 512) void k_eloc(Net net, const int8_t* __restrict__ spins, int B,
+                                               const double* __restrict__ base, int n_chunks, int chunk,
+                                               double* __restrict__ partial, int* __restrict__ cnt) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  Smem<P> s(net.g, smem);
+  stage_graph<P>(net, s);
+  if (net.tied) stage_weights<P, F>(net, s, 0);
+  __syncthreads();
+  const int items = B * n_chunks;
+  for (int it = blockIdx.x; it < items; it += gridDim.x) {
+    const int b = it / n_chunks, c = it % n_chunks;
+    load_spins<P>(net, s, spins + (size_t)b * net.n);
+    const double lb = base[2 * (size_t)b], pb = base[2 * (size_t)b + 1];
+    double sr = 0, cr = 0, si = 0, ci = 0;
+    int ne = 0;
+    const int e0 = c * chunk, e1 = min(net.ne, e0 + chunk);
+    for (int e = e0; e < e1; ++e) {
+      const int2 ij = net.edges[e];
+      if (s.sp[ij.x] == s.sp[ij.y]) continue;   // uniform across the workgroup
+      double la = 0, ph = 0;
+      eval_config<P, F, TPW, NCH>(net, s, ij.x, ij.y, la, ph);
+      if (threadIdx.x == 0) {
+        const double m = exp(la - lb);
+        double sn, cs;
+        sincos(ph - pb, &sn, &cs);
+        neumaier(sr, cr, m * cs);
+        neumaier(si, ci, m * sn);
+        ++ne;
+      }
+    }
+    if (threadIdx.x == 0) {
+      double* o = partial + 4 * (size_t)it;
+      o[0] = sr; o[1] = cr; o[2] = si; o[3] = ci;
+      cnt[it] = ne;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_zero_i64(long long* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+__global__ void k_eloc_finalize(const int8_t* __restrict__ spins, int N, const int2* __restrict__ edges,
+                                int E, double jz, double jxy, int B, int n_chunks,
+                                const double* __restrict__ partial, const int* __restrict__ cnt,
+                                double* __restrict__ eloc, long long* n_evals) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const int8_t* sb = spins + (size_t)b * N;
+  long long diag = 0;
+  for (int e = 0; e < E; ++e) diag += (int)sb[edges[e].x] * (int)sb[edges[e].y];
+  double sr = 0, cr = 0, si = 0, ci = 0;
+  long long ne = 1;
+  for (int c = 0; c < n_chunks; ++c) {
+    const double* o = partial + 4 * ((size_t)b * n_chunks + c);
+    neumaier(sr, cr, o[0]);
+    cr += o[1];
+    neumaier(si, ci, o[2]);
+    ci += o[3];
+    ne += cnt[(size_t)b * n_chunks + c];
+  }
+  eloc[2 * (size_t)b] = 0.25 * jz * (double)diag + 0.5 * jxy * (sr + cr);
+  eloc[2 * (size_t)b + 1] = 0.5 * jxy * (si + ci);
+  if (n_evals) atomicAdd(reinterpret_cast<unsigned long long*>(n_evals), (unsigned long long)ne);
+}
+
+template <class P, int F, int TPW, int NCH>
+__global__ __launch_bounds__(TPW == 1 ? 1024 : 512) void k_sweep(Net net, int8_t* __restrict__ spins, double* __restrict__ logpsi,
+                                                int B, int n_sweeps, unsigned long long seed,
+                                                unsigned long long counter_base, int* __restrict__ n_accept) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  Smem<P> s(net.g, smem);
+  stage_graph<P>(net, s);
+  if (net.tied) stage_weights<P, F>(net, s, 0);
+  __syncthreads();
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  const long long total = (long long)n_sweeps * net.n;
+  for (int b = blockIdx.x; b < B; b += gridDim.x) {
+    load_spins<P>(net, s, spins + (size_t)b * net.n);
+    double lr = logpsi[2 * (size_t)b], li = logpsi[2 * (size_t)b + 1];
+    int acc = 0;
+    for (long long t = 0; t < total; ++t) {
+      const unsigned long long step = counter_base + (unsigned long long)t;
+      uint32_t c[4] = {(uint32_t)step, (uint32_t)(step >> 32), (uint32_t)b, 0u};
+      philox4x32_10(c, k0, k1);
+      const int e = (int)(((unsigned long long)c[0] * (unsigned long long)net.ne) >> 32);
+      const double u = ((double)c[1] + 0.5) * 2.3283064365386963e-10;   // 2^-32
+      const int2 ij = net.edges[e];
+      if (s.sp[ij.x] == s.sp[ij.y]) continue;                             // identity step
+      double la = 0, ph = 0;
+      eval_config<P, F, TPW, NCH>(net, s, ij.x, ij.y, la, ph);
+      if (threadIdx.x == 0) {
+        if (u < exp(2.0 * (la - lr))) {
+          const int8_t tmp = s.sp[ij.x];
+          s.sp[ij.x] = s.sp[ij.y];
+          s.sp[ij.y] = tmp;
+          lr = la;
+          li = ph;
+          ++acc;
+        }
+      }
+      __syncthreads();
+    }
+    for (int k = threadIdx.x; k < net.n; k += blockDim.x) spins[(size_t)b * net.n + k] = s.sp[k];
+    if (threadIdx.x == 0) {
+      logpsi[2 * (size_t)b] = lr;
+      logpsi[2 * (size_t)b + 1] = li;
+      if (n_accept) n_accept[b] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// ISGO statistics (single workgroup of 1024 threads, FP64, fixed reduction order)
+// ---------------------------------------------------------------------------
+constexpr int kStatThreads = 1024;
+
+__device__ void two_sum_merge(double& s, double& c, double s2, double c2) {
+  const double t = s + s2;
+  const double e = (fabs(s) >= fabs(s2)) ? ((s - t) + s2) : ((s2 - t) + s);
+  s = t;
+  c = c + c2 + e;
+}
+
+// block-wide compensated sum of (s, c) pairs; result valid in thread 0
+__device__ double block_sum(double s, double c, double* sh_s, double* sh_c) {
+  const int tid = threadIdx.x;
+  sh_s[tid] = s;
+  sh_c[tid] = c;
+  __syncthreads();
+  for (int st = kStatThreads / 2; st > 0; st >>= 1) {
+    if (tid < st) {
+      double a = sh_s[tid], ac = sh_c[tid];
+      two_sum_merge(a, ac, sh_s[tid + st], sh_c[tid + st]);
+      sh_s[tid] = a;
+      sh_c[tid] = ac;
+    }
+    __syncthreads();
+  }
+  const double r = sh_s[0] + sh_c[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kStatThreads) void k_isgo_stats(
+    int B, const double* __restrict__ lp_old, const double* __restrict__ lp_new,
+    const double* __restrict__ eloc, const double* __restrict__ counts, const long long* __restrict__ n_evals,
+    double* __restrict__ stats, double* __restrict__ cot) {
+  __shared__ double sh_s[kStatThreads], sh_c[kStatThreads];
+  __shared__ double bc[8];
+  const int tid = threadIdx.x;
+  const int per = (B + kStatThreads - 1) / kStatThreads;
+  const int a0 = min(B, tid * per), a1 = min(B, a0 + per);
+  // 1. max shift and finiteness
+  double mloc = -INFINITY;
+  int bad = 0;
+  for (int x = a0; x < a1; ++x) {
+    const double d = 2.0 * (lp_new[2 * x] - lp_old[2 * x]);
+    const double n = counts ? counts[x] : 1.0;
+    if (!isfinite(d) || !isfinite(eloc[2 * x]) || !isfinite(eloc[2 * x + 1]) || !isfinite(n)) bad = 1;
+    mloc = fmax(mloc, d);
+  }
+  sh_s[tid] = mloc;
+  sh_c[tid] = (double)bad;
+  __syncthreads();
+  for (int st = kStatThreads / 2; st > 0; st >>= 1) {
+    if (tid < st) {
+      sh_s[tid] = fmax(sh_s[tid], sh_s[tid + st]);
+      sh_c[tid] = fmax(sh_c[tid], sh_c[tid + st]);
+    }
+    __syncthreads();
+  }
+  const double m = (B > 0) ? sh_s[0] : 0.0;
+  const double nonfinite = sh_c[0];
+  __syncthreads();
+  // 2. sums of r, r E, r^2
+  double s0 = 0, c0 = 0, sre = 0, cre = 0, sim = 0, cim = 0, sq = 0, cq = 0;
+  for (int x = a0; x < a1; ++x) {
+    const double n = counts ? counts[x] : 1.0;
+    const double r = n * exp(2.0 * (lp_new[2 * x] - lp_old[2 * x]) - m);
+    neumaier(s0, c0, r);
+    neumaier(sre, cre, r * eloc[2 * x]);
+    neumaier(sim, cim, r * eloc[2 * x + 1]);
+    neumaier(sq, cq, r * r);
+  }
+  const double S = block_sum(s0, c0, sh_s, sh_c);
+  const double SR = block_sum(sre, cre, sh_s, sh_c);
+  const double SI = block_sum(sim, cim, sh_s, sh_c);
+  const double Q = block_sum(sq, cq, sh_s, sh_c);
+  if (tid == 0) {
+    bc[0] = S;
+    bc[1] = SR / S;
+    bc[2] = SI / S;
+  }
+  __syncthreads();
+  const double Ssum = bc[0], er = bc[1], ei = bc[2];
+  // 3. variance and cotangents
+  double sv = 0, cv = 0;
+  for (int x = a0; x < a1; ++x) {
+    const double n = counts ? counts[x] : 1.0;
+    const double r = n * exp(2.0 * (lp_new[2 * x] - lp_old[2 * x]) - m);
+    const double p = r / Ssum;
+    const double dr = eloc[2 * x] - er, di = eloc[2 * x + 1] - ei;
+    neumaier(sv, cv, r * (dr * dr + di * di));
+    cot[2 * x] = 2.0 * p * dr;
+    cot[2 * x + 1] = 2.0 * p * di;
+  }
+  const double V = block_sum(sv, cv, sh_s, sh_c);
+  if (tid == 0) {
+    const bool empty = (B == 0);
+    stats[0] = empty ? 0.0 : er;
+    stats[1] = empty ? 0.0 : ei;
+    stats[2] = empty ? 0.0 : V / Ssum;
+    stats[3] = empty ? 0.0 : Ssum * Ssum / Q;
+    stats[4] = Ssum;
+    stats[5] = m;
+    stats[6] = n_evals ? (double)n_evals[0] : 0.0;
+    stats[7] = nonfinite;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Reverse pass (FP64 VALU).  Each workgroup walks samples b = blockIdx.x,
+// blockIdx.x + gridDim.x, ...; it recomputes that sample's forward pass into its
+// own scratch (H^0..H^L, M^1..M^L), runs the reverse pass, and accumulates the
+// gradient into its own row of part[].  k_vjp_reduce sums the rows in order.
+// ---------------------------------------------------------------------------
+struct VjpNet {
+  int n, F, L, tied, dmax, npar;
+  const int* ell_idx;      // [n_pad][dmax], padding -> self with value 0
+  const double* ell_val;   // FP64 A_hat
+  size_t scratch_per_wg;   // doubles
+};
+
+__global__ __launch_bounds__(1024) void k_vjp(VjpNet v, const double* __restrict__ theta,
+                                              const int8_t* __restrict__ spins, int B,
+                                              const double* __restrict__ cot, double* __restrict__ part,
+                                              double* __restrict__ scratch) {
+  const int N = v.n, F = v.F, L = v.L, nW = v.tied ? 1 : L;
+  const int NF = N * F;
+  const double* We = theta;
+  const double* be = theta + 2 * F;
+  const double* W = theta + 3 * F;
+  const double* bb = W + (size_t)nW * 2 * F * F;
+  const double* va = bb + (size_t)nW * F;
+  const double* vp = va + F + 3;
+  double* g = part + (size_t)blockIdx.x * v.npar;
+  double* gWe = g;
+  double* gbe = g + 2 * F;
+  double* gW = g + 3 * F;
+  double* gb = gW + (size_t)nW * 2 * F * F;
+  double* gva = gb + (size_t)nW * F;
+  double* gvp = gva + F + 3;
+  double* Hs = scratch + (size_t)blockIdx.x * v.scratch_per_wg;   // [(L+1)][N][F]
+  double* Ms = Hs + (size_t)(L + 1) * NF;                          // [L][N][F]
+  double* dH = Ms + (size_t)L * NF;                                // [N][F]
+  double* dX = dH + NF;                                            // [N][2F]
+  __shared__ double z[64 + 2];
+  __shared__ double dz[64 + 2];
+  __shared__ int nup;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int k = tid; k < v.npar; k += nt) g[k] = 0.0;
+  __syncthreads();
+  for (int b = blockIdx.x; b < B; b += gridDim.x) {
+    const int8_t* sb = spins + (size_t)b * N;
+    if (tid == 0) nup = 0;
+    __syncthreads();
+    int c = 0;
+    for (int e = tid; e < NF; e += nt) {
+      const int n = e / F, f = e % F;
+      const int x = sb[n] > 0 ? 1 : 0;
+      if (f == 0) c += x;
+      Hs[e] = tanh(We[x * F + f] + be[f]);
+    }
+    if (c) atomicAdd(&nup, c);
+    __syncthreads();
+    for (int l = 0; l < L; ++l) {
+      const double* Hin = Hs + (size_t)l * NF;
+      double* M = Ms + (size_t)l * NF;
+      for (int e = tid; e < NF; e += nt) {
+        const int n = e / F, f = e % F;
+        double m = 0.0;
+        for (int d = 0; d < v.dmax; ++d)
+          m += v.ell_val[n * v.dmax + d] * Hin[v.ell_idx[n * v.dmax + d] * F + f];
+        M[e] = m;
+      }
+      __syncthreads();
+      const double* Wl = W + (size_t)(v.tied ? 0 : l) * 2 * F * F;
+      const double* bl = bb + (size_t)(v.tied ? 0 : l) * F;
+      double* Hout = Hs + (size_t)(l + 1) * NF;
+      for (int e = tid; e < NF; e += nt) {
+        const int n = e / F, f = e % F;
+        double p = bl[f];
+        for (int k = 0; k < F; ++k) p += M[n * F + k] * Wl[k * F + f];
+        for (int k = 0; k < F; ++k) p += Hin[n * F + k] * Wl[(F + k) * F + f];
+        Hout[e] = tanh(p);
+      }
+      __syncthreads();
+    }
+    // readout z = (sum_i H^L_i, n_down, n_up) and head gradients
+    const double ca = cot[2 * (size_t)b], cp = cot[2 * (size_t)b + 1];
+    const double* HL = Hs + (size_t)L * NF;
+    if (tid < F) {
+      double zz = 0.0;
+      for (int n = 0; n < N; ++n) zz += HL[n * F + tid];
+      z[tid] = zz;
+    }
+    if (tid == 0) {
+      z[F] = (double)(N - nup);
+      z[F + 1] = (double)nup;
+    }
+    __syncthreads();
+    if (tid < F + 2) {
+      gva[tid] += ca * z[tid];
+      gvp[tid] += cp * z[tid];
+      dz[tid] = ca * va[tid] + cp * vp[tid];
+    }
+    if (tid == 0) {
+      gva[F + 2] += ca;
+      gvp[F + 2] += cp;
+    }
+    __syncthreads();
+    for (int e = tid; e < NF; e += nt) dH[e] = dz[e % F];
+    __syncthreads();
+    for (int l = L - 1; l >= 0; --l) {
+      const double* Hin = Hs + (size_t)l * NF;
+      const double* Hout = Hs + (size_t)(l + 1) * NF;
+      const double* M = Ms + (size_t)l * NF;
+      const int wi = v.tied ? 0 : l;
+      const double* Wl = W + (size_t)wi * 2 * F * F;
+      double* gWl = gW + (size_t)wi * 2 * F * F;
+      double* gbl = gb + (size_t)wi * F;
+      for (int e = tid; e < NF; e += nt) dH[e] *= (1.0 - Hout[e] * Hout[e]);   // dP
+      __syncthreads();
+      for (int e = tid; e < 2 * F * F; e += nt) {
+        const int k = e / F, f = e % F;
+        const double* X = (k < F) ? M : Hin;
+        const int kk = (k < F) ? k : k - F;
+        double acc = 0.0;
+        for (int n = 0; n < N; ++n) acc += X[n * F + kk] * dH[n * F + f];
+        gWl[e] += acc;
+      }
+      if (tid < F) {
+        double acc = 0.0;
+        for (int n = 0; n < N; ++n) acc += dH[n * F + tid];
+        gbl[tid] += acc;
+      }
+      for (int e = tid; e < N * 2 * F; e += nt) {
+        const int n = e / (2 * F), k = e % (2 * F);
+        double acc = 0.0;
+        for (int f = 0; f < F; ++f) acc += dH[n * F + f] * Wl[k * F + f];
+        dX[e] = acc;
+      }
+      __syncthreads();
+      for (int e = tid; e < NF; e += nt) {
+        const int n = e / F, f = e % F;
+        double acc = dX[n * 2 * F + F + f];
+        for (int d = 0; d < v.dmax; ++d)
+          acc += v.ell_val[n * v.dmax + d] * dX[v.ell_idx[n * v.dmax + d] * 2 * F + f];
+        dH[e] = acc;
+      }
+      __syncthreads();
+    }
+    // embedding
+    if (tid < F) {
+      double a0 = 0.0, a1 = 0.0;
+      for (int n = 0; n < N; ++n) {
+        const double h0 = Hs[n * F + tid];
+        const double dp = dH[n * F + tid] * (1.0 - h0 * h0);
+        if (sb[n] > 0) a1 += dp; else a0 += dp;
+      }
+      gWe[tid] += a0;
+      gWe[F + tid] += a1;
+      gbe[tid] += a0 + a1;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_vjp_reduce(const double* __restrict__ part, int nrows, int npar, double* __restrict__ grad) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= npar) return;
+  double s = 0.0, c = 0.0;
+  for (int r = 0; r < nrows; ++r) neumaier(s, c, part[(size_t)r * npar + k]);
+  grad[k] = s + c;
+}
+
+__global__ void k_sgd(double* theta, const double* grad, double alpha, int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) theta[k] -= alpha * grad[k];
+}
+
+__global__ void k_fill(double* p, double v, int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = v;
+}
+
+// ===========================================================================
+// Host side
+// ===========================================================================
+
+std::mutex g_err_mu;
+std::string g_init_err;
+
+struct Kern {  // kernels of one (precision, F, TPW, NCH) instantiation
+  const void* logpsi = nullptr;
+  const void* eloc = nullptr;
+  const void* sweep = nullptr;
+  void (*prepare)(const double*, int, void*, void*, void*, hipStream_t) = nullptr;
+};
+
+template <class P, int F, int TPW, int NCH>
+Kern make_kern() {
+  Kern k;
+  k.logpsi = reinterpret_cast<const void*>(&k_logpsi<P, F, TPW, NCH>);
+  k.eloc = reinterpret_cast<const void*>(&k_eloc<P, F, TPW, NCH>);
+  k.sweep = reinterpret_cast<const void*>(&k_sweep<P, F, TPW, NCH>);
+  k.prepare = [](const double* th, int nW, void* wf, void* bias, void* emb, hipStream_t st) {
+    const int total = nW * 2 * F * F;
+    const int blocks = std::max(1, std::min(1024, (total + 255) / 256));
+    hipLaunchKernelGGL((k_prepare<P, F>), dim3(blocks), dim3(256), 0, st, th, nW, wf, bias, emb);
+  };
+  return k;
+}
+
+template <class P, int F, int NCH>
+Kern pick_tpw(int tpw) {
+  switch (tpw) {
+    case 1: return make_kern<P, F, 1, NCH>();
+    case 2: return make_kern<P, F, 2, NCH>();
+    default: return make_kern<P, F, 4, NCH>();
+  }
+}
+
+template <class P, int F>
+Kern pick_nch(int tpw, int nch) {
+  if constexpr ((F / P::KS) % 4 == 0) {
+    if (nch == 4) return pick_tpw<P, F, 4>(tpw);
+  }
+  return pick_tpw<P, F, 1>(tpw);
+}
+
+template <class P>
+Kern pick_f(int F, int tpw, int nch) {
+  if (F == 16) return pick_nch<P, 16>(tpw, nch);
+  if (F == 32) return pick_nch<P, 32>(tpw, nch);
+  return pick_nch<P, 64>(tpw, nch);
+}
+
+}  // namespace
+
+struct gna_ctx {
+  int N = 0, E = 0, F = 0, L = 0, tied = 1, prec = 0, max_batch = 0;
+  double jz = 1.0, jxy = 1.0;
+  int64_t act_budget = 0;
+  hipStream_t stream = nullptr;
+  int device = 0, n_cu = 0;
+  int64_t P = 0;
+  std::string err;
+  // geometry
+  int tpw = 1, nch = 1, dmax = 1;
+  Geo geo{};
+  Kern kern{};
+  int grid_logpsi = 1, grid_eloc = 1, grid_sweep = 1;
+  int max_chunks = 1;
+  size_t sz_T = 8, sz_Acc = 8;
+  // device buffers
+  int2* d_edges = nullptr;
+  int* d_idx = nullptr;
+  void* d_val = nullptr;       // Acc precision
+  double* d_val64 = nullptr;   // FP64 A_hat for the reverse pass
+  void* d_wfrag = nullptr;
+  void* d_bias = nullptr;
+  void* d_emb = nullptr;
+  double* d_base = nullptr;     // [max_batch][2]
+  double* d_partial = nullptr;  // [max_batch * max_chunks][4]
+  int* d_cnt = nullptr;         // [max_batch * max_chunks]
+  long long* d_nev = nullptr;   // [1]
+  double* d_cot = nullptr;      // [max_batch][2]
+  double* d_eloc = nullptr;     // [max_batch][2]
+  double* d_vjp_part = nullptr; // [vjp_wg][P]
+  double* d_vjp_scr = nullptr;  // [vjp_wg][scratch_per_wg]
+  int vjp_wg = 1;
+  size_t vjp_scr_per_wg = 0;
+  std::vector<void*> owned;
+  // kernel timing (gna_profile_enable)
+  bool prof_on = false;
+  struct Rec { const char* name; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> ev_pool;
+};
+
+namespace {
+
+gna_status fail(gna_ctx* c, gna_status st, const std::string& msg) {
+  if (c) c->err = msg;
+  return st;
+}
+
+gna_status hip_fail(gna_ctx* c, hipError_t e, const char* what) {
+  return fail(c, GNA_HIP_ERROR, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define GNA_HIP(ctx, call)                                      \
+  do {                                                          \
+    hipError_t e_ = (call);                                     \
+    if (e_ != hipSuccess) return hip_fail((ctx), e_, #call);    \
+  } while (0)
+
+hipEvent_t take_event(gna_ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Scope guard recording start/stop events around one launch when timing is on.
+struct Timed {
+  gna_ctx* c;
+  const char* name;
+  hipEvent_t a = nullptr;
+  Timed(gna_ctx* c_, const char* n) : c(c_), name(n) {
+    if (c->prof_on && (a = take_event(c))) hipEventRecord(a, c->stream);
+  }
+  ~Timed() {
+    if (!a) return;
+    hipEvent_t b = take_event(c);
+    if (!b) return;
+    hipEventRecord(b, c->stream);
+    c->recs.push_back({name, a, b});
+  }
+};
+
+template <class X>
+gna_status dev_alloc(gna_ctx* c, X** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 16;
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, bytes);
+  if (e != hipSuccess) return fail(c, GNA_OUT_OF_MEMORY, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+  c->owned.push_back(q);
+  *p = reinterpret_cast<X*>(q);
+  return GNA_OK;
+}
+
+void free_all(gna_ctx* c) {
+  for (void* p : c->owned) hipFree(p);
+  c->owned.clear();
+}
+
+int64_t param_count(int F, int L, int tied) {
+  const int64_t nW = tied ? 1 : L;
+  return 2LL * F + F + nW * (2LL * F * F + F) + 2LL * (F + 3);
+}
+
+gna_status check_launch(gna_ctx* c, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(c, e, what);
+  return GNA_OK;
+}
+
+gna_status prepare(gna_ctx* c, const double* theta) {
+  Timed tm(c, "k_prepare");
+  c->kern.prepare(theta, c->tied ? 1 : c->L, c->d_wfrag, c->d_bias, c->d_emb, c->stream);
+  return check_launch(c, "k_prepare");
+}
+
+Net make_net(gna_ctx* c, const double* theta) {
+  Net n{};
+  n.n = c->N;
+  n.ne = c->E;
+  n.F = c->F;
+  n.L = c->L;
+  n.tied = c->tied;
+  n.dmax = c->dmax;
+  n.ell_idx = c->d_idx;
+  n.ell_val = c->d_val;
+  n.edges = c->d_edges;
+  n.wfrag = c->d_wfrag;
+  n.bias = c->d_bias;
+  n.emb = c->d_emb;
+  const int nW = c->tied ? 1 : c->L;
+  n.head_a = theta + 3 * c->F + (size_t)nW * (2 * c->F * c->F + c->F);
+  n.head_p = n.head_a + c->F + 3;
+  n.g = c->geo;
+  return n;
+}
+
+gna_status launch(gna_ctx* c, const void* fn, int grid, void** args, const char* what) {
+  Timed tm(c, what);
+  hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(64 * c->geo.wpc), args, (size_t)c->geo.lds_bytes, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, what);
+  return check_launch(c, what);
+}
+
+gna_status run_logpsi(gna_ctx* c, const double* theta, const int8_t* spins, int B, double* out) {
+  if (B == 0) return GNA_OK;
+  Net net = make_net(c, theta);
+  int grid = std::min(B, c->grid_logpsi);
+  void* args[] = {&net, &spins, &B, &out};
+  return launch(c, c->kern.logpsi, grid, args, "k_logpsi");
+}
+
+gna_status run_eloc(gna_ctx* c, const double* theta, const int8_t* spins, int B, const double* base,
+                    double* eloc, long long* nev) {
+  {
+    Timed tm(c, "k_zero_i64");
+    hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, c->stream, nev, 1);
+  }
+  if (gna_status st = check_launch(c, "k_zero_i64")) return st;
+  if (B == 0) return GNA_OK;
+  // bonds per work item: enough items to balance the persistent grid
+  const long long work = (long long)B * std::max(1, c->E);
+  long long chunk = work / (16LL * c->grid_eloc);
+  chunk = std::max<long long>(16, std::min<long long>(chunk, std::max(1, c->E)));
+  int n_chunks = (int)((std::max(1, c->E) + chunk - 1) / chunk);
+  if (n_chunks > c->max_chunks) {
+    n_chunks = c->max_chunks;
+    chunk = (c->E + n_chunks - 1) / n_chunks;
+  }
+  int ichunk = (int)chunk;
+  Net net = make_net(c, theta);
+  const int items = B * n_chunks;
+  int grid = std::min(items, c->grid_eloc);
+  double* partial = c->d_partial;
+  int* cnt = c->d_cnt;
+  void* args[] = {&net, &spins, &B, &base, &n_chunks, &ichunk, &partial, &cnt};
+  if (gna_status st = launch(c, c->kern.eloc, grid, args, "k_eloc")) return st;
+  Timed tm(c, "k_eloc_finalize");
+  hipLaunchKernelGGL(k_eloc_finalize, dim3((B + 255) / 256), dim3(256), 0, c->stream, spins, c->N,
+                     c->d_edges, c->E, c->jz, c->jxy, B, n_chunks, partial, cnt, eloc, nev);
+  return check_launch(c, "k_eloc_finalize");
+}
+
+gna_status run_vjp(gna_ctx* c, const double* theta, const int8_t* spins, int B, const double* cot, double* grad) {
+  VjpNet v{};
+  v.n = c->N;
+  v.F = c->F;
+  v.L = c->L;
+  v.tied = c->tied;
+  v.dmax = c->dmax;
+  v.npar = (int)c->P;
+  v.ell_idx = c->d_idx;
+  v.ell_val = c->d_val64;
+  v.scratch_per_wg = c->vjp_scr_per_wg;
+  const int grid = std::max(1, std::min(B, c->vjp_wg));
+  {
+    Timed tm(c, "k_vjp");
+    hipLaunchKernelGGL(k_vjp, dim3(grid), dim3(256), 0, c->stream, v, theta, spins, B, cot, c->d_vjp_part,
+                     c->d_vjp_scr);
+  }
+  if (gna_status st = check_launch(c, "k_vjp")) return st;
+  Timed tm(c, "k_vjp_reduce");
+  hipLaunchKernelGGL(k_vjp_reduce, dim3((v.npar + 255) / 256), dim3(256), 0, c->stream, c->d_vjp_part, grid,
+                     v.npar, grad);
+  return check_launch(c, "k_vjp_reduce");
+}
+
+bool valid_ptr(const void* p) { return p != nullptr; }
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
+  auto init_fail = [&](gna_status st, const std::string& m) {
+    std::lock_guard<std::mutex> lk(g_err_mu);
+    g_init_err = m;
+    return st;
+  };
+  if (!out) return init_fail(GNA_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!cfg) return init_fail(GNA_INVALID_ARG, "cfg is NULL");
+  const int N = cfg->n_sites, E = cfg->n_edges, F = cfg->n_features, L = cfg->n_layers;
+  if (N < 2 || N > 4096) return init_fail(GNA_INVALID_ARG, "n_sites must be in [2, 4096]");
+  if (E < 0) return init_fail(GNA_INVALID_ARG, "n_edges must be >= 0");
+  if (E > 0 && !cfg->edges) return init_fail(GNA_INVALID_ARG, "edges is NULL");
+  if (F != 16 && F != 32 && F != 64) return init_fail(GNA_UNSUPPORTED, "n_features must be 16, 32 or 64");
+  if (L < 0 || L > 16) return init_fail(GNA_UNSUPPORTED, "n_layers must be in [0, 16]");
+  if (cfg->tied != 0 && cfg->tied != 1) return init_fail(GNA_INVALID_ARG, "tied must be 0 or 1");
+  if (cfg->precision < GNA_FP64 || cfg->precision > GNA_BF16) return init_fail(GNA_INVALID_ARG, "unknown precision");
+  if (cfg->reserved1 != 0) return init_fail(GNA_INVALID_ARG, "reserved fields must be 0");
+  if (cfg->max_batch < 0) return init_fail(GNA_INVALID_ARG, "max_batch must be >= 0");
+  if (cfg->act_budget_bytes < 0) return init_fail(GNA_INVALID_ARG, "act_budget_bytes must be >= 0");
+  if (!std::isfinite(cfg->jz) || !std::isfinite(cfg->jxy)) return init_fail(GNA_INVALID_ARG, "couplings must be finite");
+  // graph validation (host, before any device call)
+  std::vector<int> deg(N, 0);
+  std::set<std::pair<int, int>> seen;
+  for (int e = 0; e < E; ++e) {
+    int a = cfg->edges[2 * e], b = cfg->edges[2 * e + 1];
+    if (a < 0 || a >= N || b < 0 || b >= N)
+      return init_fail(GNA_BAD_GRAPH, "edge " + std::to_string(e) + " has an endpoint out of range");
+    if (a == b) return init_fail(GNA_BAD_GRAPH, "edge " + std::to_string(e) + " is a self-loop");
+    if (!seen.insert({std::min(a, b), std::max(a, b)}).second)
+      return init_fail(GNA_BAD_GRAPH, "edge " + std::to_string(e) + " repeats a bond");
+    ++deg[a];
+    ++deg[b];
+  }
+  int dmax = 1;
+  for (int d : deg) dmax = std::max(dmax, d);
+
+  gna_ctx* c = new gna_ctx();
+  c->N = N; c->E = E; c->F = F; c->L = L; c->tied = cfg->tied; c->prec = cfg->precision;
+  c->jz = cfg->jz; c->jxy = cfg->jxy; c->max_batch = cfg->max_batch;
+  c->act_budget = cfg->act_budget_bytes ? cfg->act_budget_bytes : (int64_t)2 << 30;
+  c->stream = reinterpret_cast<hipStream_t>(cfg->stream);
+  c->P = param_count(F, L, cfg->tied);
+  c->dmax = dmax;
+  c->sz_T = (c->prec == GNA_FP64) ? 8 : (c->prec == GNA_FP32 ? 4 : 2);
+  c->sz_Acc = (c->prec == GNA_FP64) ? 8 : 4;
+
+  auto bail = [&](gna_status st, const std::string& m) {
+    free_all(c);
+    delete c;
+    return init_fail(st, m);
+  };
+  hipError_t he = hipGetDevice(&c->device);
+  if (he != hipSuccess) return bail(GNA_HIP_ERROR, std::string("hipGetDevice: ") + hipGetErrorString(he));
+  hipDeviceProp_t prop;
+  he = hipGetDeviceProperties(&prop, c->device);
+  if (he != hipSuccess) return bail(GNA_HIP_ERROR, std::string("hipGetDeviceProperties: ") + hipGetErrorString(he));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return bail(GNA_UNSUPPORTED, std::string("built for gfx950, device is ") + prop.gcnArchName);
+  c->n_cu = prop.multiProcessorCount;
+  const size_t lds_max = prop.sharedMemPerBlock;
+
+  // ---- geometry: tiles per wave, waves per workgroup, gather chunks, buffers
+  Geo& g = c->geo;
+  g.ntiles = (N + 15) / 16;
+  g.npad = 16 * g.ntiles;
+  const char* env_tpw = std::getenv("GNA_TILES_PER_WAVE");
+  int tpw = 0;
+  if (env_tpw) tpw = std::atoi(env_tpw);
+  // kernels with more than one tile per wave are built for at most 8 waves
+  auto max_waves = [](int t) { return t == 1 ? kMaxWaves : kMaxWaves / 2; };
+  if (tpw != 1 && tpw != 2 && tpw != 4) {
+    tpw = 1;
+    while (tpw < 4 && (g.ntiles + tpw - 1) / tpw > max_waves(tpw)) tpw *= 2;
+  }
+  g.wpc = (g.ntiles + tpw - 1) / tpw;
+  if (g.wpc > max_waves(tpw)) return bail(GNA_UNSUPPORTED, "n_sites too large for one workgroup (max 512)");
+  c->tpw = tpw;
+  const size_t w_bytes = (size_t)2 * F * F * c->sz_T;
+  auto layout = [&](int nch, int nbuf) -> size_t {
+    const int cs = (F / 4) / nch;
+    g.nbuf = nbuf;
+    g.row_elems = (int)((4 * cs * c->sz_T + kRowPadBytes) / c->sz_T);
+    g.buf_elems = g.npad * g.row_elems;
+    size_t o = 0;
+    auto al = [](size_t x) { return (x + 15) & ~(size_t)15; };
+    g.off_w = (int)o; o = al(o + w_bytes);
+    g.off_h = (int)o; o = al(o + (size_t)nbuf * g.buf_elems * c->sz_T);
+    g.off_sp = (int)o; o = al(o + g.npad);
+    g.off_idx = (int)o; o = al(o + (size_t)g.npad * dmax * 4);
+    g.off_val = (int)o; o = al(o + (size_t)g.npad * dmax * c->sz_Acc);
+    g.off_red = (int)o; o = al(o + kRedSlots * 8);
+    g.lds_bytes = (int)o;
+    return o + 64;  // static shared scalars
+  };
+  int nch = 0;
+  const int cand[4][2] = {{1, 2}, {1, 1}, {4, 2}, {4, 1}};
+  for (auto& cd : cand) {
+    const int ks = (c->prec == GNA_BF16) ? 16 : 4;  // features per MFMA k-step
+    if (cd[0] == 4 && (F / ks) % 4 != 0) continue;
+    if (layout(cd[0], cd[1]) <= lds_max) { nch = cd[0]; break; }
+  }
+  if (!nch) return bail(GNA_UNSUPPORTED, "configuration does not fit in LDS");
+  c->nch = nch;
+  switch (c->prec) {
+    case GNA_FP64: c->kern = pick_f<PF64>(F, tpw, nch); break;
+    case GNA_FP32: c->kern = pick_f<PF32>(F, tpw, nch); break;
+    default: c->kern = pick_f<PBF16>(F, tpw, nch); break;
+  }
+  const int threads = 64 * g.wpc;
+  auto occ = [&](const void* fn) {
+    hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, g.lds_bytes);
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, threads, g.lds_bytes) != hipSuccess || nb < 1) nb = 1;
+    (void)hipGetLastError();
+    return nb;
+  };
+  c->grid_logpsi = c->n_cu * occ(c->kern.logpsi);
+  c->grid_eloc = c->n_cu * occ(c->kern.eloc);
+  c->grid_sweep = c->n_cu * occ(c->kern.sweep);
+  c->max_chunks = std::max(1, (E + 15) / 16);
+
+  // ---- host graph tables: ELL (padding points at the node itself with value 0)
+  std::vector<int> idx((size_t)g.npad * dmax);
+  std::vector<double> val((size_t)g.npad * dmax, 0.0);
+  std::vector<int> fill(g.npad, 0);
+  for (int n = 0; n < g.npad; ++n)
+    for (int d = 0; d < dmax; ++d) idx[(size_t)n * dmax + d] = n;
+  std::vector<int> hedges(2 * (size_t)std::max(E, 1), 0);
+  for (int e = 0; e < E; ++e) {
+    const int a = cfg->edges[2 * e], b = cfg->edges[2 * e + 1];
+    hedges[2 * e] = a;
+    hedges[2 * e + 1] = b;
+    const double w = 1.0 / std::sqrt((double)deg[a] * (double)deg[b]);
+    idx[(size_t)a * dmax + fill[a]] = b; val[(size_t)a * dmax + fill[a]] = w; ++fill[a];
+    idx[(size_t)b * dmax + fill[b]] = a; val[(size_t)b * dmax + fill[b]] = w; ++fill[b];
+  }
+  std::vector<float> val32(val.begin(), val.end());
+
+  gna_status st = GNA_OK;
+  const size_t MB = (size_t)std::max(1, c->max_batch);
+  if ((st = dev_alloc(c, &c->d_edges, hedges.size() * 4)) ||
+      (st = dev_alloc(c, &c->d_idx, idx.size() * 4)) ||
+      (st = dev_alloc(c, &c->d_val64, val.size() * 8)) ||
+      (st = dev_alloc(c, &c->d_val, val.size() * c->sz_Acc)) ||
+      (st = dev_alloc(c, &c->d_wfrag, (size_t)(c->tied ? 1 : L) * w_bytes)) ||
+      (st = dev_alloc(c, &c->d_bias, (size_t)(c->tied ? 1 : std::max(L, 1)) * F * c->sz_Acc)) ||
+      (st = dev_alloc(c, &c->d_emb, (size_t)2 * F * c->sz_T)) ||
+      (st = dev_alloc(c, &c->d_base, MB * 2 * 8)) ||
+      (st = dev_alloc(c, &c->d_partial, MB * c->max_chunks * 4 * 8)) ||
+      (st = dev_alloc(c, &c->d_cnt, MB * c->max_chunks * 4)) ||
+      (st = dev_alloc(c, &c->d_nev, 8)) ||
+      (st = dev_alloc(c, &c->d_cot, MB * 2 * 8)) ||
+      (st = dev_alloc(c, &c->d_eloc, MB * 2 * 8)))
+    return bail(st, c->err);
+  // reverse-pass scratch: per workgroup (L+1) H, L M, dH and dX planes
+  c->vjp_scr_per_wg = (size_t)N * F * ((L + 1) + L + 1 + 2);
+  {
+    const int64_t per = (int64_t)c->vjp_scr_per_wg * 8 + c->P * 8;
+    int64_t wg = c->act_budget / std::max<int64_t>(per, 1);
+    wg = std::max<int64_t>(1, std::min<int64_t>(wg, std::min<int64_t>(2 * c->n_cu, MB)));
+    c->vjp_wg = (int)wg;
+  }
+  if ((st = dev_alloc(c, &c->d_vjp_part, (size_t)c->vjp_wg * c->P * 8)) ||
+      (st = dev_alloc(c, &c->d_vjp_scr, (size_t)c->vjp_wg * c->vjp_scr_per_wg * 8)))
+    return bail(st, c->err);
+  he = hipMemcpy(c->d_edges, hedges.data(), hedges.size() * 4, hipMemcpyHostToDevice);
+  if (he == hipSuccess) he = hipMemcpy(c->d_idx, idx.data(), idx.size() * 4, hipMemcpyHostToDevice);
+  if (he == hipSuccess) he = hipMemcpy(c->d_val64, val.data(), val.size() * 8, hipMemcpyHostToDevice);
+  if (he == hipSuccess)
+    he = (c->sz_Acc == 8) ? hipMemcpy(c->d_val, val.data(), val.size() * 8, hipMemcpyHostToDevice)
+                          : hipMemcpy(c->d_val, val32.data(), val32.size() * 4, hipMemcpyHostToDevice);
+  if (he != hipSuccess) return bail(GNA_HIP_ERROR, std::string("hipMemcpy: ") + hipGetErrorString(he));
+  *out = c;
+  return GNA_OK;
+}
+
+void gna_destroy(gna_ctx* ctx) {
+  if (!ctx) return;
+  hipStreamSynchronize(ctx->stream);
+  for (auto& r : ctx->recs) {
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
+  free_all(ctx);
+  delete ctx;
+}
+
+int64_t gna_num_params(const gna_ctx* ctx) { return ctx ? ctx->P : -1; }
+
+const char* gna_last_error(const gna_ctx* ctx) {
+  if (!ctx) {
+    std::lock_guard<std::mutex> lk(g_err_mu);
+    return g_init_err.c_str();
+  }
+  return ctx->err.c_str();
+}
+
+gna_status gna_set_stream(gna_ctx* ctx, void* stream) {
+  if (!ctx) return GNA_INVALID_ARG;
+  ctx->stream = reinterpret_cast<hipStream_t>(stream);
+  return GNA_OK;
+}
+
+static gna_status check_batch(gna_ctx* c, int B) {
+  if (B < 0) return fail(c, GNA_INVALID_ARG, "B must be >= 0");
+  if (B > c->max_batch) return fail(c, GNA_INVALID_ARG, "B exceeds max_batch");
+  return GNA_OK;
+}
+
+gna_status gna_logpsi(gna_ctx* c, const double* theta, const int8_t* spins, int32_t B, double* logpsi) {
+  if (!c) return GNA_INVALID_ARG;
+  if (gna_status st = check_batch(c, B)) return st;
+  if (!valid_ptr(theta) || (B > 0 && (!valid_ptr(spins) || !valid_ptr(logpsi))))
+    return fail(c, GNA_INVALID_ARG, "NULL pointer argument");
+  if (B == 0) return GNA_OK;
+  if (gna_status st = prepare(c, theta)) return st;
+  return run_logpsi(c, theta, spins, B, logpsi);
+}
+
+gna_status gna_local_energy(gna_ctx* c, const double* theta, const int8_t* spins, int32_t B, double* eloc,
+                            int64_t* n_evals) {
+  if (!c) return GNA_INVALID_ARG;
+  if (gna_status st = check_batch(c, B)) return st;
+  if (!valid_ptr(theta) || (B > 0 && (!valid_ptr(spins) || !valid_ptr(eloc))))
+    return fail(c, GNA_INVALID_ARG, "NULL pointer argument");
+  if (gna_status st = prepare(c, theta)) return st;
+  if (gna_status st = run_logpsi(c, theta, spins, B, c->d_base)) return st;
+  long long* nev = n_evals ? reinterpret_cast<long long*>(n_evals) : c->d_nev;
+  return run_eloc(c, theta, spins, B, c->d_base, eloc, nev);
+}
+
+gna_status gna_metropolis_sweep(gna_ctx* c, const double* theta, int8_t* spins, double* logpsi, int32_t B,
+                                int32_t n_sweeps, uint64_t seed, uint64_t counter_base, int32_t* n_accept) {
+  if (!c) return GNA_INVALID_ARG;
+  if (gna_status st = check_batch(c, B)) return st;
+  if (n_sweeps < 0) return fail(c, GNA_INVALID_ARG, "n_sweeps must be >= 0");
+  if (!valid_ptr(theta) || (B > 0 && (!valid_ptr(spins) || !valid_ptr(logpsi))))
+    return fail(c, GNA_INVALID_ARG, "NULL pointer argument");
+  if (c->E == 0 && n_sweeps > 0) return fail(c, GNA_INVALID_ARG, "graph has no bonds to propose");
+  if (B == 0) return GNA_OK;
+  if (gna_status st = prepare(c, theta)) return st;
+  Net net = make_net(c, theta);
+  int grid = std::min(B, c->grid_sweep);
+  int Bv = B, ns = n_sweeps;
+  unsigned long long sd = seed, cb = counter_base;
+  int* acc = n_accept;
+  void* args[] = {&net, &spins, &logpsi, &Bv, &ns, &sd, &cb, &acc};
+  return launch(c, c->kern.sweep, grid, args, "k_sweep");
+}
+
+gna_status gna_logpsi_vjp(gna_ctx* c, const double* theta, const int8_t* spins, int32_t B, const double* cot,
+                          double* grad) {
+  if (!c) return GNA_INVALID_ARG;
+  if (gna_status st = check_batch(c, B)) return st;
+  if (!valid_ptr(theta) || !valid_ptr(grad) || (B > 0 && (!valid_ptr(spins) || !valid_ptr(cot))))
+    return fail(c, GNA_INVALID_ARG, "NULL pointer argument");
+  return run_vjp(c, theta, spins, B, cot, grad);
+}
+
+gna_status gna_isgo_grad(gna_ctx* c, const double* theta, const int8_t* spins, const double* logpsi_old,
+                         const double* counts, int32_t B, double* grad, double* stats, double* eloc) {
+  if (!c) return GNA_INVALID_ARG;
+  if (gna_status st = check_batch(c, B)) return st;
+  if (!valid_ptr(theta) || !valid_ptr(grad) || !valid_ptr(stats) ||
+      (B > 0 && (!valid_ptr(spins) || !valid_ptr(logpsi_old))))
+    return fail(c, GNA_INVALID_ARG, "NULL pointer argument");
+  if (gna_status st = prepare(c, theta)) return st;
+  if (gna_status st = run_logpsi(c, theta, spins, B, c->d_base)) return st;
+  double* el = eloc ? eloc : c->d_eloc;
+  if (gna_status st = run_eloc(c, theta, spins, B, c->d_base, el, c->d_nev)) return st;
+  {
+    Timed tm(c, "k_isgo_stats");
+    hipLaunchKernelGGL(k_isgo_stats, dim3(1), dim3(kStatThreads), 0, c->stream, B, logpsi_old, c->d_base, el,
+                     counts, c->d_nev, stats, c->d_cot);
+  }
+  if (gna_status st = check_launch(c, "k_isgo_stats")) return st;
+  return run_vjp(c, theta, spins, B, c->d_cot, grad);
+}
+
+gna_status gna_sgd_update(gna_ctx* c, double* theta, const double* grad, double alpha) {
+  if (!c) return GNA_INVALID_ARG;
+  if (!valid_ptr(theta) || !valid_ptr(grad)) return fail(c, GNA_INVALID_ARG, "NULL pointer argument");
+  if (!std::isfinite(alpha)) return fail(c, GNA_INVALID_ARG, "alpha must be finite");
+  const int n = (int)c->P;
+  Timed tm(c, "k_sgd");
+  hipLaunchKernelGGL(k_sgd, dim3((n + 255) / 256), dim3(256), 0, c->stream, theta, grad, alpha, n);
+  return check_launch(c, "k_sgd");
+}
+
+gna_status gna_profile_enable(gna_ctx* c, int32_t on) {
+  if (!c) return GNA_INVALID_ARG;
+  c->prof_on = (on != 0);
+  return GNA_OK;
+}
+
+int32_t gna_profile_read(gna_ctx* c, int32_t max_entries, char* names, int64_t* launches, double* total_ms) {
+  if (!c || max_entries < 0 || (max_entries > 0 && (!names || !launches || !total_ms))) return -1;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return -1;
+  std::vector<std::pair<std::string, std::pair<int64_t, double>>> agg;
+  for (auto& r : c->recs) {
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, r.a, r.b);
+    size_t k = 0;
+    while (k < agg.size() && agg[k].first != r.name) ++k;
+    if (k == agg.size()) agg.push_back({r.name, {0, 0.0}});
+    agg[k].second.first += 1;
+    agg[k].second.second += ms;
+    c->ev_pool.push_back(r.a);
+    c->ev_pool.push_back(r.b);
+  }
+  c->recs.clear();
+  const int n = (int)agg.size();
+  for (int k = 0; k < n && k < max_entries; ++k) {
+    std::strncpy(names + 64 * k, agg[k].first.c_str(), 63);
+    names[64 * k + 63] = 0;
+    launches[k] = agg[k].second.first;
+    total_ms[k] = agg[k].second.second;
+  }
+  return n;
+}
+
+}  // extern "C"

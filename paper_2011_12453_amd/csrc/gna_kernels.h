@@ -1,0 +1,432 @@
+// Device-side building blocks of the GNA hot path for gfx950: precision traits
+// for the MFMA layer products, the Philox4x32-10 generator, and the per-
+// configuration evaluator of Eq. 1 shared by the forward, local-energy and
+// sampler kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gna {
+
+typedef __attribute__((ext_vector_type(4))) float f4;
+typedef __attribute__((ext_vector_type(4))) double d4;
+typedef __attribute__((ext_vector_type(4))) short s4;
+
+constexpr int kMaxWaves = 16;           // 1024 threads per workgroup
+constexpr int kRowPadBytes = 16;        // LDS row padding of the gather buffer
+
+// ---------------------------------------------------------------------------
+// tanh for the FP32/BF16 modes: tanh(x) = 1 - 2 / (exp(2x) + 1), evaluated with
+// the hardware base-2 exponential and reciprocal (absolute error a few 1e-7;
+// saturates correctly: exp overflow gives 1, underflow gives -1).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float tanh_f32(float x) {
+  const float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);  // 2 log2(e)
+  return __builtin_fmaf(-2.0f, __builtin_amdgcn_rcpf(e + 1.0f), 1.0f);
+}
+
+// round-to-nearest-even float -> bfloat16 bits (finite inputs)
+__device__ __forceinline__ unsigned short f32_to_bf16(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(unsigned short b) {
+  return __uint_as_float(((unsigned)b) << 16);
+}
+
+// ---------------------------------------------------------------------------
+// Precision traits.  The layer product of Eq. 1 is computed transposed,
+// P^T = W^T [M | H]^T: the MFMA's A operand is W^T (rows = output features),
+// its B operand holds 16 nodes (columns) of the activations.  Lane l of a wave
+// owns node column l%16 and lane group q = l/16.  Per node tile a lane holds
+// F/4 "slots" of features; slot i of lane group q carries logical feature
+// lc(q, i), both as an MFMA result and as the next layer's B operand, so the
+// activations never leave registers between layers.  row_feature(m) is the
+// logical output feature the weight fragment must place in physical A row m
+// for that to hold (it follows from each instruction's result layout).
+// ---------------------------------------------------------------------------
+struct PF64 {  // v_mfma_f64_16x16x4f64: D[4r + l/16][l%16], B[l/16][l%16]
+  using T = double;
+  using Acc = double;
+  using CF = d4;
+  static constexpr int KS = 4, VEC = 1;
+  __device__ static CF mfma(const T* a, const T* b, CF c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], c, 0, 0, 0);
+  }
+  __host__ __device__ static int lc(int q, int i) { return 4 * i + q; }
+  __host__ __device__ static int row_feature(int m) { return m; }
+  __device__ static T from_acc(Acc v) { return v; }
+  __device__ static Acc to_acc(T v) { return v; }
+  __device__ static Acc act(Acc x) { return tanh(x); }
+};
+
+struct PF32 {  // v_mfma_f32_16x16x4f32: D[4(l/16) + r][l%16], B[l/16][l%16]
+  using T = float;
+  using Acc = float;
+  using CF = f4;
+  static constexpr int KS = 4, VEC = 1;
+  __device__ static CF mfma(const T* a, const T* b, CF c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[0], c, 0, 0, 0);
+  }
+  __host__ __device__ static int lc(int q, int i) { return 4 * i + q; }
+  __host__ __device__ static int row_feature(int m) {
+    return 16 * (m / 16) + 4 * (m % 4) + (m % 16) / 4;
+  }
+  __device__ static T from_acc(Acc v) { return v; }
+  __device__ static Acc to_acc(T v) { return v; }
+  __device__ static Acc act(Acc x) { return tanh_f32(x); }
+};
+
+struct PBF16 {  // v_mfma_f32_16x16x16_bf16: D[4(l/16) + r][l%16], B[4(l/16) + j][l%16]
+  using T = unsigned short;  // bfloat16 bits
+  using Acc = float;
+  using CF = f4;
+  static constexpr int KS = 16, VEC = 4;
+  __device__ static CF mfma(const T* a, const T* b, CF c) {
+    s4 av = {(short)a[0], (short)a[1], (short)a[2], (short)a[3]};
+    s4 bv = {(short)b[0], (short)b[1], (short)b[2], (short)b[3]};
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, c, 0, 0, 0);
+  }
+  __host__ __device__ static int lc(int q, int i) { return 16 * (i / 4) + 4 * q + (i % 4); }
+  __host__ __device__ static int row_feature(int m) { return m; }
+  __device__ static T from_acc(Acc v) { return f32_to_bf16(v); }
+  __device__ static Acc to_acc(T v) { return bf16_to_f32(v); }
+  __device__ static Acc act(Acc x) { return tanh_f32(x); }
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): 10 rounds of two 32x32->64 products,
+// XOR recombination with the key, key advanced by Weyl constants between rounds.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+    c[1] = (uint32_t)p1;
+    c[3] = (uint32_t)p0;
+    c[0] = n0;
+    c[2] = n2;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launch geometry and LDS layout (byte offsets into dynamic shared memory).
+// ---------------------------------------------------------------------------
+struct Geo {
+  int wpc;        // waves per workgroup; the workgroup evaluates one configuration
+  int ntiles;     // ceil(N / 16) node tiles
+  int npad;       // 16 * ntiles
+  int nbuf;       // 1 or 2 gather buffers
+  int row_elems;  // gather-buffer row stride in elements of T
+  int buf_elems;  // elements of T per gather buffer
+  int off_w, off_h, off_sp, off_idx, off_val, off_red;
+  int lds_bytes;
+};
+
+struct Net {
+  int n, ne, F, L, tied, dmax;
+  const int* ell_idx;      // [npad][dmax] neighbour ids (padding points at the node itself)
+  const void* ell_val;     // [npad][dmax] A_hat values in Acc precision (padding 0)
+  const int2* edges;       // [ne] bond endpoints
+  const void* wfrag;       // [nW][2F/KS][F/16][64][VEC] weight fragments, T
+  const void* bias;        // [nW][F] logical order, Acc
+  const void* emb;         // [2][F] tanh(W_e[x] + b_e), T, logical order
+  const double* head_a;    // v_a[F+2], c_a (FP64, inside theta)
+  const double* head_p;    // v_p[F+2], c_p
+  Geo g;
+};
+
+// fixed-order FP64 wavefront sum (same order for every configuration)
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// vectorised LDS copy of N elements of T (alignment 16 B or of the chunk size)
+template <class T, int N>
+__device__ __forceinline__ void lds_read(const T* __restrict__ src, T (&dst)[N]) {
+  constexpr int B = N * (int)sizeof(T);
+  if constexpr (B % 16 == 0) {
+    const uint4* s = reinterpret_cast<const uint4*>(src);
+#pragma unroll
+    for (int k = 0; k < B / 16; ++k) reinterpret_cast<uint4*>(dst)[k] = s[k];
+  } else if constexpr (B % 8 == 0) {
+    const uint2* s = reinterpret_cast<const uint2*>(src);
+#pragma unroll
+    for (int k = 0; k < B / 8; ++k) reinterpret_cast<uint2*>(dst)[k] = s[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < N; ++k) dst[k] = src[k];
+  }
+}
+template <class T, int N>
+__device__ __forceinline__ void lds_write(T* __restrict__ dst, const T* src) {
+  constexpr int B = N * (int)sizeof(T);
+  if constexpr (B % 16 == 0) {
+#pragma unroll
+    for (int k = 0; k < B / 16; ++k)
+      reinterpret_cast<uint4*>(dst)[k] = reinterpret_cast<const uint4*>(src)[k];
+  } else if constexpr (B % 8 == 0) {
+#pragma unroll
+    for (int k = 0; k < B / 8; ++k)
+      reinterpret_cast<uint2*>(dst)[k] = reinterpret_cast<const uint2*>(src)[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < N; ++k) dst[k] = src[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-workgroup view of LDS.
+// ---------------------------------------------------------------------------
+template <class P>
+struct Smem {
+  using T = typename P::T;
+  using Acc = typename P::Acc;
+  T* w;          // one layer's weight fragments
+  T* h;          // gather buffer(s)
+  int8_t* sp;    // spins of the current sample
+  int* idx;      // ELL neighbour ids
+  Acc* val;      // ELL values
+  double* red;   // [2 * kMaxWaves] readout partials + scalars
+  __device__ Smem(const Geo& g, unsigned char* base)
+      : w(reinterpret_cast<T*>(base + g.off_w)),
+        h(reinterpret_cast<T*>(base + g.off_h)),
+        sp(reinterpret_cast<int8_t*>(base + g.off_sp)),
+        idx(reinterpret_cast<int*>(base + g.off_idx)),
+        val(reinterpret_cast<Acc*>(base + g.off_val)),
+        red(reinterpret_cast<double*>(base + g.off_red)) {}
+};
+
+// red[] scalar slots after the 2*kMaxWaves partials
+constexpr int kRedNup = 2 * kMaxWaves;      // number of up spins (as double)
+constexpr int kRedFlag = 2 * kMaxWaves + 1; // sampler accept flag / broadcast
+constexpr int kRedSlots = 2 * kMaxWaves + 4;
+
+// Copy one layer's weight fragments global -> LDS (whole workgroup).
+template <class P, int F>
+__device__ void stage_weights(const Net& net, const Smem<P>& s, int layer) {
+  using T = typename P::T;
+  constexpr int n = 2 * F * F;  // elements per layer
+  const T* src = reinterpret_cast<const T*>(net.wfrag) + (size_t)layer * n;
+  if constexpr ((n * sizeof(T)) % 16 == 0) {
+    const uint4* s4p = reinterpret_cast<const uint4*>(src);
+    uint4* d4p = reinterpret_cast<uint4*>(s.w);
+    for (int k = threadIdx.x; k < (int)(n * sizeof(T) / 16); k += blockDim.x) d4p[k] = s4p[k];
+  } else {
+    for (int k = threadIdx.x; k < n; k += blockDim.x) s.w[k] = src[k];
+  }
+}
+
+// Copy the ELL adjacency global -> LDS (whole workgroup).
+template <class P>
+__device__ void stage_graph(const Net& net, const Smem<P>& s) {
+  using Acc = typename P::Acc;
+  const int n = net.g.npad * net.dmax;
+  const Acc* v = reinterpret_cast<const Acc*>(net.ell_val);
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    s.idx[k] = net.ell_idx[k];
+    s.val[k] = v[k];
+  }
+}
+
+// Load one sample's spins into LDS and count its up spins into red[kRedNup].
+// Ends with a barrier.
+template <class P>
+__device__ void load_spins(const Net& net, const Smem<P>& s, const int8_t* __restrict__ src) {
+  __shared__ int nup;
+  if (threadIdx.x == 0) nup = 0;
+  __syncthreads();
+  int c = 0;
+  for (int k = threadIdx.x; k < net.g.npad; k += blockDim.x) {
+    const int8_t v = (k < net.n) ? src[k] : (int8_t)-1;
+    s.sp[k] = v;
+    c += (k < net.n && v > 0) ? 1 : 0;
+  }
+  if (c) atomicAdd(&nup, c);
+  __syncthreads();
+  if (threadIdx.x == 0) s.red[kRedNup] = (double)nup;
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Evaluate log psi of the configuration in s.sp with sites si and sj exchanged
+// (si < 0: no exchange).  Whole workgroup; the result is returned to thread 0
+// only.  Node tile k of wave w is tile w + k * wpc.  Every call performs the
+// same arithmetic in the same order for a node whose receptive field holds the
+// same spins, so log psi differences cancel exactly outside it.
+//   TPW: node tiles per wave; NCH: feature chunks of the gather buffer.
+// ---------------------------------------------------------------------------
+template <class P, int F, int TPW, int NCH>
+__device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
+                            double& out_la, double& out_ph) {
+  using T = typename P::T;
+  using Acc = typename P::Acc;
+  using CF = typename P::CF;
+  constexpr int NS = F / 4;           // slots per lane per tile
+  constexpr int MT = F / 16;          // output 16-feature tiles
+  constexpr int KSB = F / P::KS;      // MFMA k-steps per F-wide block
+  constexpr int CS = NS / NCH;        // slots per gather chunk
+  constexpr int KSC = KSB / NCH;      // k-steps per gather chunk
+  constexpr int VEC = P::VEC;
+  static_assert(F % 16 == 0 && NS % NCH == 0 && KSB % NCH == 0, "bad shape");
+
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int q = lane >> 4, col = lane & 15;
+  const Geo& g = net.g;
+  const int wpc = g.wpc;
+
+  int node[TPW];
+  bool tile_ok[TPW], real[TPW];
+  T h[TPW][NS];
+  const T* emb = reinterpret_cast<const T*>(net.emb);
+#pragma unroll
+  for (int k = 0; k < TPW; ++k) {
+    const int tile = wv + k * wpc;
+    tile_ok[k] = tile < g.ntiles;
+    node[k] = tile * 16 + col;
+    real[k] = tile_ok[k] && node[k] < net.n;
+    int x = 0;
+    if (real[k]) {
+      const int nd = node[k];
+      const int8_t sv = (nd == si) ? s.sp[sj] : ((nd == sj) ? s.sp[si] : s.sp[nd]);
+      x = sv > 0 ? 1 : 0;
+    }
+#pragma unroll
+    for (int i = 0; i < NS; ++i) h[k][i] = real[k] ? emb[x * F + P::lc(q, i)] : P::from_acc((Acc)0);
+  }
+
+  double pa = 0.0, pp = 0.0;
+  const T* wl = s.w;
+  for (int l = 0; l < net.L; ++l) {
+    if (!net.tied) {
+      __syncthreads();
+      stage_weights<P, F>(net, s, l);
+      __syncthreads();
+    }
+    const Acc* bias = reinterpret_cast<const Acc*>(net.bias) + (net.tied ? 0 : l) * F;
+    CF acc[TPW][MT];
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      CF bv;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) bv[r] = bias[P::lc(q, 4 * t + r)];
+#pragma unroll
+      for (int k = 0; k < TPW; ++k) acc[k][t] = bv;
+    }
+    // message block: gather A_hat H from LDS chunk by chunk
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+      const int buf = (g.nbuf == 2) ? ((l * NCH + ch) & 1) : 0;
+      T* hb = s.h + buf * g.buf_elems;
+      if (g.nbuf == 1) __syncthreads();
+#pragma unroll
+      for (int k = 0; k < TPW; ++k)
+        if (tile_ok[k]) lds_write<T, CS>(hb + node[k] * g.row_elems + q * CS, &h[k][ch * CS]);
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < TPW; ++k) {
+        if (!tile_ok[k]) continue;
+        Acc m[CS];
+#pragma unroll
+        for (int i = 0; i < CS; ++i) m[i] = (Acc)0;
+        const int* ip = s.idx + node[k] * net.dmax;
+        const Acc* vp = s.val + node[k] * net.dmax;
+        for (int d = 0; d < net.dmax; ++d) {
+          const int nb = ip[d];
+          const Acc a = vp[d];
+          T row[CS];
+          lds_read<T, CS>(hb + nb * g.row_elems + q * CS, row);
+#pragma unroll
+          for (int i = 0; i < CS; ++i) m[i] += a * P::to_acc(row[i]);
+        }
+#pragma unroll
+        for (int st = 0; st < KSC; ++st) {
+          T bfr[VEC];
+#pragma unroll
+          for (int j = 0; j < VEC; ++j) bfr[j] = P::from_acc(m[st * VEC + j]);
+#pragma unroll
+          for (int t = 0; t < MT; ++t) {
+            const T* a = wl + (((ch * KSC + st) * MT + t) * 64 + lane) * VEC;
+            acc[k][t] = P::mfma(a, bfr, acc[k][t]);
+          }
+        }
+      }
+    }
+    // self block: the node's own row, straight from registers
+#pragma unroll
+    for (int st = 0; st < KSB; ++st) {
+#pragma unroll
+      for (int t = 0; t < MT; ++t) {
+        T a[VEC];
+        const T* ap = wl + (((KSB + st) * MT + t) * 64 + lane) * VEC;
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) a[j] = ap[j];
+#pragma unroll
+        for (int k = 0; k < TPW; ++k)
+          if (tile_ok[k]) acc[k][t] = P::mfma(a, &h[k][st * VEC], acc[k][t]);
+      }
+    }
+    const bool last = (l == net.L - 1);
+#pragma unroll
+    for (int k = 0; k < TPW; ++k) {
+#pragma unroll
+      for (int t = 0; t < MT; ++t) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const Acc v = P::act(acc[k][t][r]);
+          h[k][4 * t + r] = P::from_acc(v);
+          if (last && real[k]) {
+            const int f = P::lc(q, 4 * t + r);
+            pa += net.head_a[f] * (double)v;
+            pp += net.head_p[f] * (double)v;
+          }
+        }
+      }
+    }
+  }
+  if (net.L == 0) {
+#pragma unroll
+    for (int k = 0; k < TPW; ++k)
+      if (real[k])
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+          const int f = P::lc(q, i);
+          pa += net.head_a[f] * (double)P::to_acc(h[k][i]);
+          pp += net.head_p[f] * (double)P::to_acc(h[k][i]);
+        }
+  }
+  pa = wave_sum(pa);
+  pp = wave_sum(pp);
+  if (lane == 0) {
+    s.red[wv] = pa;
+    s.red[kMaxWaves + wv] = pp;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, p = 0.0;
+    for (int w = 0; w < wpc; ++w) {
+      a += s.red[w];
+      p += s.red[kMaxWaves + w];
+    }
+    const int F2 = net.F;
+    const double nup = s.red[kRedNup], ndn = (double)net.n - nup;
+    a += net.head_a[F2] * ndn + net.head_a[F2 + 1] * nup + net.head_a[F2 + 2];
+    p += net.head_p[F2] * ndn + net.head_p[F2 + 1] * nup + net.head_p[F2 + 2];
+    out_la = a;
+    out_ph = p;
+  }
+  __syncthreads();
+}
+
+}  // namespace gna

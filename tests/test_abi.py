@@ -1,0 +1,101 @@
+"""The C-ABI library loads, exports every entry point declared in include/gna.h,
+and rejects invalid configurations synchronously, before touching a device
+(these run without a GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gna.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(gna_[a-z_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2011_12453_amd.binding import library_path, load_library
+    if not os.path.exists(library_path()):
+        pytest.fail("libgna.so is not built; run __graft_entry__.build()")
+    return load_library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert {"gna_init", "gna_logpsi", "gna_local_energy", "gna_metropolis_sweep", "gna_isgo_grad",
+            "gna_logpsi_vjp", "gna_destroy"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_config_struct_matches_header_layout():
+    from paper_2011_12453_amd.binding import _Config
+    # int32 x2, ptr, int32 x4, double x2, int32 x2, int64, ptr: no implicit padding
+    assert ctypes.sizeof(_Config) == 4 * 2 + 8 + 4 * 4 + 8 * 2 + 4 * 2 + 8 + 8
+    assert _Config.jz.offset == 32 and _Config.stream.offset == 64
+
+
+def _cfg(**kw):
+    from paper_2011_12453_amd.binding import _Config
+    import workloads as w
+    n, e = w.kagome(2, 2)
+    e = np.ascontiguousarray(kw.pop("edges", e), dtype=np.int32)
+    base = dict(n_sites=n, n_edges=len(e), n_features=16, n_layers=2, tied=1, precision=0,
+                jz=1.0, jxy=1.0, max_batch=16, reserved1=0, act_budget_bytes=0)
+    base.update(kw)
+    c = _Config()
+    for k, v in base.items():
+        setattr(c, k, v)
+    c.edges = e.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    c.stream = None
+    return c, e
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("n_sites", 1, 1), ("n_features", 24, 3), ("n_layers", -1, 3), ("n_layers", 17, 3),
+    ("precision", 7, 1), ("tied", 2, 1), ("reserved1", 1, 1), ("max_batch", -1, 1),
+    ("jz", float("nan"), 1),
+])
+def test_bad_config_rejected_before_device(lib, field, value, status):
+    c, keep = _cfg(**{field: value})
+    out = ctypes.c_void_p()
+    st = lib.gna_init(ctypes.byref(c), ctypes.byref(out))
+    assert st == status and not out.value
+    assert len(lib.gna_last_error(None)) > 0
+
+
+@pytest.mark.parametrize("edges,msg", [
+    (np.array([[0, 12]]), b"out of range"), (np.array([[3, 3]]), b"self-loop"),
+    (np.array([[0, 1], [1, 0]]), b"repeats"), (np.array([[-1, 2]]), b"out of range"),
+])
+def test_bad_graph_rejected(lib, edges, msg):
+    c, keep = _cfg(edges=edges)
+    out = ctypes.c_void_p()
+    assert lib.gna_init(ctypes.byref(c), ctypes.byref(out)) == 2
+    assert msg in lib.gna_last_error(None)
+
+
+def test_null_arguments(lib):
+    out = ctypes.c_void_p()
+    assert lib.gna_init(None, ctypes.byref(out)) == 1
+    c, keep = _cfg()
+    assert lib.gna_init(ctypes.byref(c), None) == 1
+    assert lib.gna_num_params(None) == -1
+    assert lib.gna_logpsi(None, None, None, 0, None) == 1
+    lib.gna_destroy(None)
+
+
+def test_product_path_has_no_oracle_or_fallback():
+    # the binding and the library sources never reach the CPU oracle
+    pkg = os.path.join(ROOT, "paper_2011_12453_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, f

@@ -1,0 +1,294 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Tolerances (energy per site, relative, |e - e*| / max(|e*|, 1e-2)): FP64 1e-10,
+FP32 1e-5, BF16 1e-3.  Per-sample bounds are looser for the reduced precisions
+and are stated at each assertion with the reason.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda", 0)
+EPS_SITE = {"fp64": 1e-10, "fp32": 1e-5, "bf16": 1e-3}
+
+
+def _ctx(n, e, F, L, tied=True, prec="fp64", max_batch=256, **kw):
+    from paper_2011_12453_amd import GNA
+    print(f"[gpu] ctx N={n} E={len(e)} F={F} L={L} tied={tied} prec={prec}", file=sys.stderr, flush=True)
+    return GNA(n, e, F, L, tied=tied, precision=prec, max_batch=max_batch, device=DEV, **kw)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _site_err(got, ref, n):
+    e, r = np.mean(got) / n, np.mean(ref) / n
+    return abs(e - r) / max(abs(r), 1e-2)
+
+
+CASES = [
+    # name, graph builder, F, L, tied, B
+    ("kagome12", lambda: w.kagome(2, 2), 16, 2, True, 64),
+    ("kagome108", lambda: w.kagome(6, 6), 32, 4, True, 12),
+    ("tri144", lambda: w.triangular(12, 12), 32, 4, True, 6),
+    ("er100", lambda: w.erdos_renyi_connected(100, 0.06, 0), 32, 4, True, 12),
+    ("kagome12_untied", lambda: w.kagome(2, 2), 16, 3, False, 32),
+    ("tri36_F64_untied", lambda: w.triangular(6, 6), 64, 2, False, 8),
+]
+
+
+def _compare(case, prec, theta_kind):
+    name, build, F, L, tied, B = case
+    n, e = build()
+    if theta_kind == "glorot":      # the workloads' initialisation: Glorot-normal, zero biases
+        theta = w.glorot_theta(F, L, tied, seed=0)
+    else:                           # stress: larger weights and random biases, psi far from uniform
+        theta = w.glorot_theta(F, L, tied, seed=0, weight_scale=1.5, bias_std=0.3)
+    spins = w.random_sz0_spins(B, n, 1000 + B)
+    g = _ctx(n, e, F, L, tied, prec, max_batch=B)
+    th, sp = _dev(theta), _dev(spins)
+    lp = g.logpsi(th, sp).cpu().numpy()
+    el, nev = g.local_energy(th, sp)
+    el = el.cpu().numpy()
+    g.close()
+    lp_ref = oracle.logpsi(theta, spins, n, e, F, L, tied)
+    el_ref = oracle.local_energy(theta, spins, n, e, F, L, tied)
+    assert int(nev.item()) == oracle.n_evals(spins, e)            # integer work: exact
+    scale = max(1.0, np.max(np.abs(lp_ref)))
+    lp_err = np.max(np.abs(lp - lp_ref)) / scale
+    el_err = np.max(np.abs(el[:, 0] - el_ref.real) + np.abs(el[:, 1] - el_ref.imag)) / max(1.0, np.max(np.abs(el_ref)))
+    site = _site_err(el[:, 0], el_ref.real, n)
+    print(f"[gpu] {name} {prec} {theta_kind}: logpsi rel {lp_err:.2e}  eloc rel {el_err:.2e}  e/site rel {site:.2e}",
+          file=sys.stderr, flush=True)
+    return lp_err, el_err, site
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_logpsi_and_local_energy_match_oracle(case, prec):
+    lp_err, el_err, site = _compare(case, prec, "glorot")
+    assert site < EPS_SITE[prec]
+    if prec == "fp64":
+        assert lp_err < 1e-12 and el_err < 1e-11
+    elif prec == "fp32":
+        # FP32 activations: ~1e-7 per op, summed over N sites in the readout
+        assert lp_err < 2e-5 and el_err < 1e-4
+    else:
+        # bf16 operands carry 2^-9 relative rounding per activation and weight
+        assert lp_err < 2e-2 and el_err < 1e-2
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("case", CASES[:4], ids=[c[0] for c in CASES[:4]])
+def test_stress_weights_match_oracle(case, prec):
+    # |log psi| spread of several units: each ratio psi(s^ij)/psi(s) carries the
+    # rounding of the swapped sites' receptive field, so bf16 gets a wider bound
+    lp_err, el_err, site = _compare(case, prec, "stress")
+    if prec == "fp64":
+        assert lp_err < 1e-12 and el_err < 1e-11 and site < 1e-10
+    elif prec == "fp32":
+        assert lp_err < 2e-5 and el_err < 1e-4 and site < 1e-5
+    else:
+        assert lp_err < 3e-2 and el_err < 1e-1 and site < 3e-2
+
+
+FULL = [("kagome108_L4F32", "bf16"), ("kagome108_L4F32", "fp32"), ("triangular144_L4F32", "bf16"),
+        ("er100_L4F32", "bf16"), ("kagome432_L6F64", "bf16"), ("kagome432_L6F64", "fp32"),
+        ("kagome432_L6F64", "fp64")]
+
+
+@pytest.mark.parametrize("name,prec", FULL, ids=[f"{a}-{b}" for a, b in FULL])
+def test_full_size_batch_sampled_parity(name, prec):
+    # the whole batch in one launch, as the benchmark runs it; the oracle checks
+    # a few sampled rows one by one, and the batch obeys S_z-sector bounds
+    p = w.preset(name)
+    n, e = p.build_graph()
+    theta = w.glorot_theta(p.n_features, p.n_layers, True, seed=p.theta_seed)
+    spins = w.random_sz0_spins(p.batch, n, p.spin_seed)
+    g = _ctx(n, e, p.n_features, p.n_layers, True, prec, max_batch=p.batch)
+    el, nev = g.local_energy(_dev(theta), _dev(spins))
+    el = el.cpu().numpy()
+    g.close()
+    assert int(nev.item()) == oracle.n_evals(spins, e)
+    rows = np.random.default_rng(0).choice(p.batch, size=3, replace=False)
+    ref = oracle.local_energy(theta, spins[rows], n, e, p.n_features, p.n_layers)
+    err = np.max(np.abs(el[rows, 0] - ref.real) + np.abs(el[rows, 1] - ref.imag)) / np.max(np.abs(ref))
+    site = _site_err(el[rows, 0], ref.real, n)
+    print(f"[gpu] full {name} {prec}: sampled eloc rel {err:.2e} e/site rel {site:.2e}", file=sys.stderr, flush=True)
+    assert site < EPS_SITE[prec]
+    assert err < {"fp64": 1e-11, "fp32": 1e-4, "bf16": 1e-2}[prec]
+    assert np.all(np.isfinite(el))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_zero_heads_give_exact_quarter_bond_energy(prec):
+    # constant psi: every ratio is exactly 1 in any precision, E_loc = |E|/4
+    n, e = w.erdos_renyi_connected(100, 0.06, 0)
+    F, L = 32, 4
+    theta = w.glorot_theta(F, L, True, seed=2, weight_scale=1.5, bias_std=0.3)
+    theta[-2 * (F + 3):] = 0.0
+    spins = np.concatenate([w.random_sz0_spins(6, n, 3), w.random_spins(4, n, 4)])
+    g = _ctx(n, e, F, L, True, prec, max_batch=16)
+    el, _ = g.local_energy(_dev(theta), _dev(spins))
+    el = el.cpu().numpy()
+    assert np.all(el[:, 0] == len(e) / 4) and np.all(el[:, 1] == 0.0)
+    g.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16"])
+def test_edge_cases_empty_single_polarised(prec):
+    n, e = w.kagome(2, 2)
+    F, L = 16, 2
+    theta = w.glorot_theta(F, L, True, seed=1, bias_std=0.2)
+    g = _ctx(n, e, F, L, True, prec, max_batch=8)
+    th = _dev(theta)
+    empty = torch.zeros((0, n), dtype=torch.int8, device=DEV)
+    el, nev = g.local_energy(th, empty)
+    assert el.shape == (0, 2) and int(nev.item()) == 0
+    up = np.ones((1, n), np.int8)
+    el, nev = g.local_energy(th, _dev(up))
+    assert el.cpu().numpy()[0, 0] == len(e) / 4 and int(nev.item()) == 1
+    one = w.random_sz0_spins(1, n, 9)
+    el, nev = g.local_energy(th, _dev(one))
+    ref = oracle.local_energy(theta, one, n, e, F, L)
+    tol = 1e-11 if prec == "fp64" else 3e-2
+    assert abs(el.cpu().numpy()[0, 0] - ref[0].real) < tol * max(1, abs(ref[0]))
+    with pytest.raises(Exception):
+        g.local_energy(th, _dev(w.random_sz0_spins(9, n, 1)))     # above max_batch
+    g.close()
+
+
+def test_anisotropic_couplings():
+    n, e = w.triangular(4, 4)
+    F, L = 16, 2
+    theta = w.glorot_theta(F, L, True, seed=5, weight_scale=1.5, bias_std=0.3)
+    spins = w.random_sz0_spins(16, n, 7)
+    g = _ctx(n, e, F, L, True, "fp64", max_batch=16, jz=0.6, jxy=-1.7)
+    el = g.local_energy(_dev(theta), _dev(spins))[0].cpu().numpy()
+    ref = oracle.local_energy(theta, spins, n, e, F, L, jz=0.6, jxy=-1.7)
+    assert np.max(np.abs(el[:, 0] - ref.real) + np.abs(el[:, 1] - ref.imag)) < 1e-11 * np.max(np.abs(ref))
+    g.close()
+
+
+def test_sampler_fp64_trajectory_matches_oracle():
+    # both sides draw the same Philox4x32-10 stream and decide in FP64
+    n, e = w.kagome(2, 2)
+    F, L = 16, 2
+    theta = w.glorot_theta(F, L, True, seed=3, weight_scale=2.0, bias_std=0.3)
+    s0 = w.random_sz0_spins(64, n, 11)
+    g = _ctx(n, e, F, L, True, "fp64", max_batch=64)
+    th = _dev(theta)
+    sp = _dev(s0)
+    lp = g.logpsi(th, sp)
+    acc = g.metropolis_sweep(th, sp, lp, n_sweeps=3, seed=1234, counter_base=77)
+    fn = lambda c: oracle.logpsi(theta, c, n, e, F, L)
+    rs, rlp, racc = oracle.metropolis_sweeps(fn, s0, fn(s0), e, 3, seed=1234, counter_base=77)
+    assert np.array_equal(sp.cpu().numpy(), rs)
+    assert np.array_equal(acc.cpu().numpy(), racc)
+    assert np.max(np.abs(lp.cpu().numpy() - rlp)) < 1e-11
+    g.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_sampler_reduced_precision_invariants(prec):
+    n, e = w.kagome(6, 6)
+    F, L = 32, 4
+    theta = w.glorot_theta(F, L, True, seed=3, weight_scale=2.0, bias_std=0.3)
+    s0 = w.random_sz0_spins(32, n, 12)
+    g = _ctx(n, e, F, L, True, prec, max_batch=32)
+    th, sp = _dev(theta), _dev(s0)
+    lp = g.logpsi(th, sp)
+    acc = g.metropolis_sweep(th, sp, lp, n_sweeps=1, seed=99)
+    s1 = sp.cpu().numpy()
+    assert np.all(s1.sum(1) == 0)                                    # S_z conserved
+    assert np.all(acc.cpu().numpy() <= n) and acc.sum().item() > 0
+    # the chain's log psi is bitwise the one gna_logpsi gives for its final spins
+    assert torch.equal(lp, g.logpsi(th, sp))
+    g.close()
+
+
+@pytest.mark.parametrize("tied", [True, False])
+def test_vjp_matches_oracle(tied):
+    n, e = w.erdos_renyi_connected(100, 0.06, 0)
+    F, L = 32, 3
+    theta = w.glorot_theta(F, L, tied, seed=4, weight_scale=1.5, bias_std=0.3)
+    spins = w.random_spins(10, n, 5)
+    cot = np.random.default_rng(0).normal(size=(10, 2))
+    g = _ctx(n, e, F, L, tied, "fp64", max_batch=16)
+    got = g.logpsi_vjp(_dev(theta), _dev(spins), _dev(cot)).cpu().numpy()
+    ref = oracle.logpsi_vjp(theta, spins, cot, n, e, F, L, tied)
+    assert np.max(np.abs(got - ref)) < 1e-11 * max(1, np.max(np.abs(ref)))
+    g.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_isgo_grad_matches_oracle(prec):
+    n, e = w.kagome(2, 2)
+    F, L = 16, 2
+    th_old = w.glorot_theta(F, L, True, seed=6, weight_scale=1.5, bias_std=0.3)
+    th_new = th_old + 0.03 * np.random.default_rng(1).normal(size=th_old.size)
+    # bf16 cotangents 2 p (E_x - E) inherit the per-sample E_loc rounding (a few 1e-2
+    # relative at these stress weights), hence the wider gradient bound
+    spins = w.random_sz0_spins(128, n, 21)
+    counts = np.random.default_rng(2).integers(1, 4, size=128).astype(np.float64)
+    lp_old = oracle.logpsi(th_old, spins, n, e, F, L)
+    g = _ctx(n, e, F, L, True, prec, max_batch=128)
+    grad, stats, el = g.isgo_grad(_dev(th_new), _dev(spins), _dev(lp_old), _dev(counts))
+    grad, stats = grad.cpu().numpy(), stats.cpu().numpy()
+    rg, rs, rel = oracle.isgo_grad(th_new, spins, lp_old, n, e, F, L, counts=counts)
+    tol = {"fp64": 1e-10, "fp32": 1e-4, "bf16": 1e-1}[prec]
+    assert np.max(np.abs(grad - rg)) < tol * np.max(np.abs(rg))
+    site_tol = {"fp64": 1e-10, "fp32": 1e-5, "bf16": 3e-2}[prec]
+    assert abs(stats[0] - rs["e_re"]) / n < site_tol * max(abs(rs["e_re"]) / n, 1e-2)
+    if prec == "fp64":
+        assert abs(stats[1] - rs["e_im"]) < 1e-10
+        assert stats[2] == pytest.approx(rs["var"], rel=1e-10)
+        assert stats[3] == pytest.approx(rs["ess"], rel=1e-12)
+        assert stats[4] == pytest.approx(rs["sum_r"], rel=1e-12)
+        assert stats[5] == pytest.approx(rs["shift"], rel=1e-12, abs=1e-12)
+    assert stats[6] == rs["n_evals"] and stats[7] == 0.0
+    g.close()
+
+
+def test_isgo_nonfinite_flag_and_sgd():
+    n, e = w.kagome(2, 2)
+    F, L = 16, 2
+    theta = w.glorot_theta(F, L, True, seed=7, bias_std=0.2)
+    spins = w.random_sz0_spins(16, n, 3)
+    g = _ctx(n, e, F, L, True, "fp64", max_batch=16)
+    th = _dev(theta)
+    lp = g.logpsi(th, _dev(spins))
+    bad = lp.clone()
+    bad[3, 0] = float("nan")
+    _, stats, _ = g.isgo_grad(th, _dev(spins), bad)
+    assert stats[7].item() == 1.0
+    grad, stats, _ = g.isgo_grad(th, _dev(spins), lp)
+    assert stats[3].item() == pytest.approx(16.0, rel=1e-14)          # r = 1: ESS = B
+    th2 = th.clone()
+    g.sgd_update(th2, grad, 0.1)
+    assert torch.allclose(th2, th - 0.1 * grad, rtol=0, atol=1e-15)
+    g.close()
+
+
+def test_autograd_function_backward():
+    from paper_2011_12453_amd import LogPsi
+    n, e = w.kagome(2, 2)
+    F, L = 16, 2
+    theta = w.glorot_theta(F, L, True, seed=8, weight_scale=1.5, bias_std=0.3)
+    spins = w.random_sz0_spins(20, n, 4)
+    g = _ctx(n, e, F, L, True, "fp64", max_batch=32)
+    th = _dev(theta).requires_grad_(True)
+    out = LogPsi.apply(g, th, _dev(spins))
+    wts = torch.randn(20, 2, dtype=torch.float64, device=DEV)
+    (out * wts).sum().backward()
+    ref = oracle.logpsi_vjp(theta, spins, wts.cpu().numpy(), n, e, F, L)
+    assert np.max(np.abs(th.grad.cpu().numpy() - ref)) < 1e-11 * max(1, np.max(np.abs(ref)))
+    g.close()
