@@ -40,14 +40,14 @@ namespace {
 //   kk = KS*(s mod F/KS) + (VEC == 1 ? lane/16 : 4*(lane/16) + j).
 template <class P, int F>
 __global__ void k_prepare(const double* __restrict__ theta, int nW, void* wfrag, void* bias, void* emb) {
-  using T = typename P::T;
+  using WT = typename P::WT;
   using Acc = typename P::Acc;
   constexpr int KSB = F / P::KS, MT = F / 16, VEC = P::VEC;
   const double* We = theta;
   const double* be = theta + 2 * F;
   const double* W = theta + 3 * F;
   const double* b = W + (size_t)nW * 2 * F * F;
-  T* wf = reinterpret_cast<T*>(wfrag);
+  WT* wf = reinterpret_cast<WT*>(wfrag);
   const int per_layer = 2 * F * F;
   const int total = nW * per_layer;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
@@ -61,13 +61,13 @@ __global__ void k_prepare(const double* __restrict__ theta, int nW, void* wfrag,
     const int kk = P::KS * ss + (VEC == 1 ? lane / 16 : 4 * (lane / 16) + j);
     const int f = P::row_feature(16 * t + lane % 16);
     const double v = W[(size_t)w * per_layer + (size_t)(blk * F + kk) * F + f];
-    wf[e] = P::from_acc((Acc)v);
+    wf[e] = P::to_w(P::kScale * v);
   }
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid < nW * F) reinterpret_cast<Acc*>(bias)[tid] = (Acc)b[tid];
+  if (tid < nW * F) reinterpret_cast<Acc*>(bias)[tid] = (Acc)(P::kScale * b[tid]);
   if (tid < 2 * F) {
     const int x = tid / F, f = tid % F;
-    reinterpret_cast<T*>(emb)[tid] = P::from_acc((Acc)tanh(We[x * F + f] + be[f]));
+    reinterpret_cast<Acc*>(emb)[tid] = (Acc)tanh(We[x * F + f] + be[f]);
   }
 }
 
@@ -567,7 +567,7 @@ struct gna_ctx {
   Kern kern{};
   int grid_logpsi = 1, grid_eloc = 1, grid_sweep = 1;
   int max_chunks = 1;
-  size_t sz_T = 8, sz_Acc = 8;
+  size_t sz_W = 8, sz_Acc = 8;
   // device buffers
   int2* d_edges = nullptr;
   int* d_idx = nullptr;
@@ -817,7 +817,7 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
   c->stream = reinterpret_cast<hipStream_t>(cfg->stream);
   c->P = param_count(F, L, cfg->tied);
   c->dmax = dmax;
-  c->sz_T = (c->prec == GNA_FP64) ? 8 : (c->prec == GNA_FP32 ? 4 : 2);
+  c->sz_W = (c->prec == GNA_FP64) ? 8 : (c->prec == GNA_FP32 ? 4 : 2);
   c->sz_Acc = (c->prec == GNA_FP64) ? 8 : 4;
 
   auto bail = [&](gna_status st, const std::string& m) {
@@ -851,16 +851,16 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
   g.wpc = (g.ntiles + tpw - 1) / tpw;
   if (g.wpc > max_waves(tpw)) return bail(GNA_UNSUPPORTED, "n_sites too large for one workgroup (max 512)");
   c->tpw = tpw;
-  const size_t w_bytes = (size_t)2 * F * F * c->sz_T;
+  const size_t w_bytes = (size_t)2 * F * F * c->sz_W;
   auto layout = [&](int nch, int nbuf) -> size_t {
     const int cs = (F / 4) / nch;
     g.nbuf = nbuf;
-    g.row_elems = (int)((4 * cs * c->sz_T + kRowPadBytes) / c->sz_T);
+    g.row_elems = (int)((4 * cs * c->sz_Acc + kRowPadBytes) / c->sz_Acc);
     g.buf_elems = g.npad * g.row_elems;
     size_t o = 0;
     auto al = [](size_t x) { return (x + 15) & ~(size_t)15; };
     g.off_w = (int)o; o = al(o + w_bytes);
-    g.off_h = (int)o; o = al(o + (size_t)nbuf * g.buf_elems * c->sz_T);
+    g.off_h = (int)o; o = al(o + (size_t)nbuf * g.buf_elems * c->sz_Acc);
     g.off_sp = (int)o; o = al(o + g.npad);
     g.off_idx = (int)o; o = al(o + (size_t)g.npad * dmax * 4);
     g.off_val = (int)o; o = al(o + (size_t)g.npad * dmax * c->sz_Acc);
@@ -920,7 +920,7 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
       (st = dev_alloc(c, &c->d_val, val.size() * c->sz_Acc)) ||
       (st = dev_alloc(c, &c->d_wfrag, (size_t)(c->tied ? 1 : L) * w_bytes)) ||
       (st = dev_alloc(c, &c->d_bias, (size_t)(c->tied ? 1 : std::max(L, 1)) * F * c->sz_Acc)) ||
-      (st = dev_alloc(c, &c->d_emb, (size_t)2 * F * c->sz_T)) ||
+      (st = dev_alloc(c, &c->d_emb, (size_t)2 * F * c->sz_Acc)) ||
       (st = dev_alloc(c, &c->d_base, MB * 2 * 8)) ||
       (st = dev_alloc(c, &c->d_partial, MB * c->max_chunks * 4 * 8)) ||
       (st = dev_alloc(c, &c->d_cnt, MB * c->max_chunks * 4)) ||

@@ -17,23 +17,24 @@ constexpr int kMaxWaves = 16;           // 1024 threads per workgroup
 constexpr int kRowPadBytes = 16;        // LDS row padding of the gather buffer
 
 // ---------------------------------------------------------------------------
-// tanh for the FP32/BF16 modes: tanh(x) = 1 - 2 / (exp(2x) + 1), evaluated with
-// the hardware base-2 exponential and reciprocal (absolute error a few 1e-7;
-// saturates correctly: exp overflow gives 1, underflow gives -1).
+// tanh for the FP32/BF16 modes, from its definition tanh(x) = 1 - 2/(exp(2x) + 1).
+// The caller passes y = 2 log2(e) x (the factor is folded into the layer's
+// weights and bias), so exp(2x) is the hardware base-2 exponential of y.
+// Absolute error a few 1e-7; exp overflow gives 1, underflow gives -1.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float tanh_f32(float x) {
-  const float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);  // 2 log2(e)
+constexpr float kTwoLog2e = 2.8853900817779268f;
+
+__device__ __forceinline__ float tanh_from_scaled(float y) {
+  const float e = __builtin_amdgcn_exp2f(y);
   return __builtin_fmaf(-2.0f, __builtin_amdgcn_rcpf(e + 1.0f), 1.0f);
 }
 
-// round-to-nearest-even float -> bfloat16 bits (finite inputs)
-__device__ __forceinline__ unsigned short f32_to_bf16(float f) {
-  unsigned u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-__device__ __forceinline__ float bf16_to_f32(unsigned short b) {
-  return __uint_as_float(((unsigned)b) << 16);
+typedef __attribute__((ext_vector_type(2))) __bf16 bf2;
+
+// round-to-nearest-even float pair -> packed bfloat16 pair (v_cvt_pk_bf16_f32)
+__device__ __forceinline__ unsigned pack_bf16_rne(float a, float b) {
+  bf2 v = {(__bf16)a, (__bf16)b};
+  return __builtin_bit_cast(unsigned, v);
 }
 
 // ---------------------------------------------------------------------------
@@ -46,54 +47,84 @@ __device__ __forceinline__ float bf16_to_f32(unsigned short b) {
 // activations never leave registers between layers.  row_feature(m) is the
 // logical output feature the weight fragment must place in physical A row m
 // for that to hold (it follows from each instruction's result layout).
+//   Acc: activations, aggregation and accumulation type
+//   WT : weight storage type of the A operand
+//   BF : B operand built from VEC activations by make_b
+//   kScale: factor folded into W and b (act() receives the scaled argument)
 // ---------------------------------------------------------------------------
 struct PF64 {  // v_mfma_f64_16x16x4f64: D[4r + l/16][l%16], B[l/16][l%16]
-  using T = double;
   using Acc = double;
+  using WT = double;
+  using BF = double;
   using CF = d4;
   static constexpr int KS = 4, VEC = 1;
-  __device__ static CF mfma(const T* a, const T* b, CF c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], c, 0, 0, 0);
+  static constexpr double kScale = 1.0;
+  __device__ static BF make_b(const Acc* x) { return x[0]; }
+  __device__ static CF mma(const WT* a, const BF& b, CF c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b, c, 0, 0, 0);
   }
   __host__ __device__ static int lc(int q, int i) { return 4 * i + q; }
   __host__ __device__ static int row_feature(int m) { return m; }
-  __device__ static T from_acc(Acc v) { return v; }
-  __device__ static Acc to_acc(T v) { return v; }
+  __device__ static WT to_w(double v) { return v; }
   __device__ static Acc act(Acc x) { return tanh(x); }
 };
 
 struct PF32 {  // v_mfma_f32_16x16x4f32: D[4(l/16) + r][l%16], B[l/16][l%16]
-  using T = float;
   using Acc = float;
+  using WT = float;
+  using BF = float;
   using CF = f4;
   static constexpr int KS = 4, VEC = 1;
-  __device__ static CF mfma(const T* a, const T* b, CF c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[0], c, 0, 0, 0);
+  static constexpr double kScale = (double)kTwoLog2e;
+  __device__ static BF make_b(const Acc* x) { return x[0]; }
+  __device__ static CF mma(const WT* a, const BF& b, CF c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b, c, 0, 0, 0);
   }
   __host__ __device__ static int lc(int q, int i) { return 4 * i + q; }
   __host__ __device__ static int row_feature(int m) {
     return 16 * (m / 16) + 4 * (m % 4) + (m % 16) / 4;
   }
-  __device__ static T from_acc(Acc v) { return v; }
-  __device__ static Acc to_acc(T v) { return v; }
-  __device__ static Acc act(Acc x) { return tanh_f32(x); }
+  __device__ static WT to_w(double v) { return (float)v; }
+  __device__ static Acc act(Acc y) { return tanh_from_scaled(y); }
 };
 
+// BF16 operands.  Weights are rounded to bfloat16 once.  Each activation x is
+// carried as the unevaluated pair hi + lo of two bfloat16 values (hi = x with its
+// low 16 bits cleared, lo = RNE(x - hi)), i.e. about 16 significant bits, and
+// every product is issued as two MFMAs, W.hi + W.lo, accumulated in FP32.
 struct PBF16 {  // v_mfma_f32_16x16x16_bf16: D[4(l/16) + r][l%16], B[4(l/16) + j][l%16]
-  using T = unsigned short;  // bfloat16 bits
   using Acc = float;
+  using WT = unsigned short;  // bfloat16 bits
+  struct BF { s4 hi, lo; };
   using CF = f4;
   static constexpr int KS = 16, VEC = 4;
-  __device__ static CF mfma(const T* a, const T* b, CF c) {
-    s4 av = {(short)a[0], (short)a[1], (short)a[2], (short)a[3]};
-    s4 bv = {(short)b[0], (short)b[1], (short)b[2], (short)b[3]};
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, c, 0, 0, 0);
+  static constexpr double kScale = (double)kTwoLog2e;
+  __device__ static BF make_b(const Acc* x) {
+    unsigned u[4];
+    float r[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      u[j] = __float_as_uint(x[j]) & 0xFFFF0000u;
+      r[j] = x[j] - __uint_as_float(u[j]);
+    }
+    BF b;
+    const unsigned h01 = (u[0] >> 16) | u[1], h23 = (u[2] >> 16) | u[3];
+    const unsigned l01 = pack_bf16_rne(r[0], r[1]), l23 = pack_bf16_rne(r[2], r[3]);
+    b.hi = __builtin_bit_cast(s4, (unsigned long long)h01 | ((unsigned long long)h23 << 32));
+    b.lo = __builtin_bit_cast(s4, (unsigned long long)l01 | ((unsigned long long)l23 << 32));
+    return b;
+  }
+  __device__ static CF mma(const WT* a, const BF& b, CF c) {
+    const s4 av = *reinterpret_cast<const s4*>(a);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, b.hi, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, b.lo, c, 0, 0, 0);
   }
   __host__ __device__ static int lc(int q, int i) { return 16 * (i / 4) + 4 * q + (i % 4); }
   __host__ __device__ static int row_feature(int m) { return m; }
-  __device__ static T from_acc(Acc v) { return f32_to_bf16(v); }
-  __device__ static Acc to_acc(T v) { return bf16_to_f32(v); }
-  __device__ static Acc act(Acc x) { return tanh_f32(x); }
+  __device__ static WT to_w(double v) {
+    return (WT)(pack_bf16_rne((float)v, 0.0f) & 0xFFFFu);
+  }
+  __device__ static Acc act(Acc y) { return tanh_from_scaled(y); }
 };
 
 // ---------------------------------------------------------------------------
@@ -126,8 +157,8 @@ struct Geo {
   int ntiles;     // ceil(N / 16) node tiles
   int npad;       // 16 * ntiles
   int nbuf;       // 1 or 2 gather buffers
-  int row_elems;  // gather-buffer row stride in elements of T
-  int buf_elems;  // elements of T per gather buffer
+  int row_elems;  // gather-buffer row stride in elements of Acc
+  int buf_elems;  // elements of Acc per gather buffer
   int off_w, off_h, off_sp, off_idx, off_val, off_red;
   int lds_bytes;
 };
@@ -137,9 +168,9 @@ struct Net {
   const int* ell_idx;      // [npad][dmax] neighbour ids (padding points at the node itself)
   const void* ell_val;     // [npad][dmax] A_hat values in Acc precision (padding 0)
   const int2* edges;       // [ne] bond endpoints
-  const void* wfrag;       // [nW][2F/KS][F/16][64][VEC] weight fragments, T
-  const void* bias;        // [nW][F] logical order, Acc
-  const void* emb;         // [2][F] tanh(W_e[x] + b_e), T, logical order
+  const void* wfrag;       // [nW][2F/KS][F/16][64][VEC] weight fragments, WT (scaled by kScale)
+  const void* bias;        // [nW][F] logical order, Acc (scaled by kScale)
+  const void* emb;         // [2][F] tanh(W_e[x] + b_e), Acc, logical order
   const double* head_a;    // v_a[F+2], c_a (FP64, inside theta)
   const double* head_p;    // v_p[F+2], c_p
   Geo g;
@@ -191,17 +222,17 @@ __device__ __forceinline__ void lds_write(T* __restrict__ dst, const T* src) {
 // ---------------------------------------------------------------------------
 template <class P>
 struct Smem {
-  using T = typename P::T;
+  using WT = typename P::WT;
   using Acc = typename P::Acc;
-  T* w;          // one layer's weight fragments
-  T* h;          // gather buffer(s)
+  WT* w;         // one layer's weight fragments
+  Acc* h;        // gather buffer(s)
   int8_t* sp;    // spins of the current sample
   int* idx;      // ELL neighbour ids
   Acc* val;      // ELL values
   double* red;   // [2 * kMaxWaves] readout partials + scalars
   __device__ Smem(const Geo& g, unsigned char* base)
-      : w(reinterpret_cast<T*>(base + g.off_w)),
-        h(reinterpret_cast<T*>(base + g.off_h)),
+      : w(reinterpret_cast<WT*>(base + g.off_w)),
+        h(reinterpret_cast<Acc*>(base + g.off_h)),
         sp(reinterpret_cast<int8_t*>(base + g.off_sp)),
         idx(reinterpret_cast<int*>(base + g.off_idx)),
         val(reinterpret_cast<Acc*>(base + g.off_val)),
@@ -216,13 +247,13 @@ constexpr int kRedSlots = 2 * kMaxWaves + 4;
 // Copy one layer's weight fragments global -> LDS (whole workgroup).
 template <class P, int F>
 __device__ void stage_weights(const Net& net, const Smem<P>& s, int layer) {
-  using T = typename P::T;
+  using WT = typename P::WT;
   constexpr int n = 2 * F * F;  // elements per layer
-  const T* src = reinterpret_cast<const T*>(net.wfrag) + (size_t)layer * n;
-  if constexpr ((n * sizeof(T)) % 16 == 0) {
+  const WT* src = reinterpret_cast<const WT*>(net.wfrag) + (size_t)layer * n;
+  if constexpr ((n * sizeof(WT)) % 16 == 0) {
     const uint4* s4p = reinterpret_cast<const uint4*>(src);
     uint4* d4p = reinterpret_cast<uint4*>(s.w);
-    for (int k = threadIdx.x; k < (int)(n * sizeof(T) / 16); k += blockDim.x) d4p[k] = s4p[k];
+    for (int k = threadIdx.x; k < (int)(n * sizeof(WT) / 16); k += blockDim.x) d4p[k] = s4p[k];
   } else {
     for (int k = threadIdx.x; k < n; k += blockDim.x) s.w[k] = src[k];
   }
@@ -270,8 +301,9 @@ __device__ void load_spins(const Net& net, const Smem<P>& s, const int8_t* __res
 template <class P, int F, int TPW, int NCH>
 __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
                             double& out_la, double& out_ph) {
-  using T = typename P::T;
   using Acc = typename P::Acc;
+  using WT = typename P::WT;
+  using BF = typename P::BF;
   using CF = typename P::CF;
   constexpr int NS = F / 4;           // slots per lane per tile
   constexpr int MT = F / 16;          // output 16-feature tiles
@@ -288,8 +320,8 @@ __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
 
   int node[TPW];
   bool tile_ok[TPW], real[TPW];
-  T h[TPW][NS];
-  const T* emb = reinterpret_cast<const T*>(net.emb);
+  Acc h[TPW][NS];
+  const Acc* emb = reinterpret_cast<const Acc*>(net.emb);
 #pragma unroll
   for (int k = 0; k < TPW; ++k) {
     const int tile = wv + k * wpc;
@@ -303,11 +335,11 @@ __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
       x = sv > 0 ? 1 : 0;
     }
 #pragma unroll
-    for (int i = 0; i < NS; ++i) h[k][i] = real[k] ? emb[x * F + P::lc(q, i)] : P::from_acc((Acc)0);
+    for (int i = 0; i < NS; ++i) h[k][i] = real[k] ? emb[x * F + P::lc(q, i)] : (Acc)0;
   }
 
   double pa = 0.0, pp = 0.0;
-  const T* wl = s.w;
+  const WT* wl = s.w;
   for (int l = 0; l < net.L; ++l) {
     if (!net.tied) {
       __syncthreads();
@@ -324,15 +356,33 @@ __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
 #pragma unroll
       for (int k = 0; k < TPW; ++k) acc[k][t] = bv;
     }
+    // self block: the node's own row, straight from registers; each weight
+    // fragment is read once and applied to every tile of the wave
+#pragma unroll
+    for (int st = 0; st < KSB; ++st) {
+      BF b[TPW];
+#pragma unroll
+      for (int k = 0; k < TPW; ++k) b[k] = P::make_b(&h[k][st * VEC]);
+#pragma unroll
+      for (int t = 0; t < MT; ++t) {
+        WT a[VEC];
+        const WT* ap = wl + (((KSB + st) * MT + t) * 64 + lane) * VEC;
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) a[j] = ap[j];
+#pragma unroll
+        for (int k = 0; k < TPW; ++k)
+          if (tile_ok[k]) acc[k][t] = P::mma(a, b[k], acc[k][t]);
+      }
+    }
     // message block: gather A_hat H from LDS chunk by chunk
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) {
       const int buf = (g.nbuf == 2) ? ((l * NCH + ch) & 1) : 0;
-      T* hb = s.h + buf * g.buf_elems;
+      Acc* hb = s.h + buf * g.buf_elems;
       if (g.nbuf == 1) __syncthreads();
 #pragma unroll
       for (int k = 0; k < TPW; ++k)
-        if (tile_ok[k]) lds_write<T, CS>(hb + node[k] * g.row_elems + q * CS, &h[k][ch * CS]);
+        if (tile_ok[k]) lds_write<Acc, CS>(hb + node[k] * g.row_elems + q * CS, &h[k][ch * CS]);
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < TPW; ++k) {
@@ -345,36 +395,20 @@ __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
         for (int d = 0; d < net.dmax; ++d) {
           const int nb = ip[d];
           const Acc a = vp[d];
-          T row[CS];
-          lds_read<T, CS>(hb + nb * g.row_elems + q * CS, row);
+          Acc row[CS];
+          lds_read<Acc, CS>(hb + nb * g.row_elems + q * CS, row);
 #pragma unroll
-          for (int i = 0; i < CS; ++i) m[i] += a * P::to_acc(row[i]);
+          for (int i = 0; i < CS; ++i) m[i] += a * row[i];
         }
 #pragma unroll
         for (int st = 0; st < KSC; ++st) {
-          T bfr[VEC];
-#pragma unroll
-          for (int j = 0; j < VEC; ++j) bfr[j] = P::from_acc(m[st * VEC + j]);
+          const BF b = P::make_b(&m[st * VEC]);
 #pragma unroll
           for (int t = 0; t < MT; ++t) {
-            const T* a = wl + (((ch * KSC + st) * MT + t) * 64 + lane) * VEC;
-            acc[k][t] = P::mfma(a, bfr, acc[k][t]);
+            const WT* a = wl + (((ch * KSC + st) * MT + t) * 64 + lane) * VEC;
+            acc[k][t] = P::mma(a, b, acc[k][t]);
           }
         }
-      }
-    }
-    // self block: the node's own row, straight from registers
-#pragma unroll
-    for (int st = 0; st < KSB; ++st) {
-#pragma unroll
-      for (int t = 0; t < MT; ++t) {
-        T a[VEC];
-        const T* ap = wl + (((KSB + st) * MT + t) * 64 + lane) * VEC;
-#pragma unroll
-        for (int j = 0; j < VEC; ++j) a[j] = ap[j];
-#pragma unroll
-        for (int k = 0; k < TPW; ++k)
-          if (tile_ok[k]) acc[k][t] = P::mfma(a, &h[k][st * VEC], acc[k][t]);
       }
     }
     const bool last = (l == net.L - 1);
@@ -385,7 +419,7 @@ __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const Acc v = P::act(acc[k][t][r]);
-          h[k][4 * t + r] = P::from_acc(v);
+          h[k][4 * t + r] = v;
           if (last && real[k]) {
             const int f = P::lc(q, 4 * t + r);
             pa += net.head_a[f] * (double)v;
@@ -402,8 +436,8 @@ __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
 #pragma unroll
         for (int i = 0; i < NS; ++i) {
           const int f = P::lc(q, i);
-          pa += net.head_a[f] * (double)P::to_acc(h[k][i]);
-          pp += net.head_p[f] * (double)P::to_acc(h[k][i]);
+          pa += net.head_a[f] * (double)h[k][i];
+          pp += net.head_p[f] * (double)h[k][i];
         }
   }
   pa = wave_sum(pa);
