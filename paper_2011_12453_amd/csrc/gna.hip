@@ -25,6 +25,7 @@
 
 #include "gna.h"
 #include "gna_kernels.h"
+#include "gna_vjp.h"
 
 using namespace gna;
 
@@ -323,164 +324,6 @@ __global__ __launch_bounds__(kStatThreads) void k_isgo_stats(
   }
 }
 
-// ---------------------------------------------------------------------------
-// Reverse pass (FP64 VALU).  Each workgroup walks samples b = blockIdx.x,
-// blockIdx.x + gridDim.x, ...; it recomputes that sample's forward pass into its
-// own scratch (H^0..H^L, M^1..M^L), runs the reverse pass, and accumulates the
-// gradient into its own row of part[].  k_vjp_reduce sums the rows in order.
-// ---------------------------------------------------------------------------
-struct VjpNet {
-  int n, F, L, tied, dmax, npar;
-  const int* ell_idx;      // [n_pad][dmax], padding -> self with value 0
-  const double* ell_val;   // FP64 A_hat
-  size_t scratch_per_wg;   // doubles
-};
-
-__global__ __launch_bounds__(1024) void k_vjp(VjpNet v, const double* __restrict__ theta,
-                                              const int8_t* __restrict__ spins, int B,
-                                              const double* __restrict__ cot, double* __restrict__ part,
-                                              double* __restrict__ scratch) {
-  const int N = v.n, F = v.F, L = v.L, nW = v.tied ? 1 : L;
-  const int NF = N * F;
-  const double* We = theta;
-  const double* be = theta + 2 * F;
-  const double* W = theta + 3 * F;
-  const double* bb = W + (size_t)nW * 2 * F * F;
-  const double* va = bb + (size_t)nW * F;
-  const double* vp = va + F + 3;
-  double* g = part + (size_t)blockIdx.x * v.npar;
-  double* gWe = g;
-  double* gbe = g + 2 * F;
-  double* gW = g + 3 * F;
-  double* gb = gW + (size_t)nW * 2 * F * F;
-  double* gva = gb + (size_t)nW * F;
-  double* gvp = gva + F + 3;
-  double* Hs = scratch + (size_t)blockIdx.x * v.scratch_per_wg;   // [(L+1)][N][F]
-  double* Ms = Hs + (size_t)(L + 1) * NF;                          // [L][N][F]
-  double* dH = Ms + (size_t)L * NF;                                // [N][F]
-  double* dX = dH + NF;                                            // [N][2F]
-  __shared__ double z[64 + 2];
-  __shared__ double dz[64 + 2];
-  __shared__ int nup;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int k = tid; k < v.npar; k += nt) g[k] = 0.0;
-  __syncthreads();
-  for (int b = blockIdx.x; b < B; b += gridDim.x) {
-    const int8_t* sb = spins + (size_t)b * N;
-    if (tid == 0) nup = 0;
-    __syncthreads();
-    int c = 0;
-    for (int e = tid; e < NF; e += nt) {
-      const int n = e / F, f = e % F;
-      const int x = sb[n] > 0 ? 1 : 0;
-      if (f == 0) c += x;
-      Hs[e] = tanh(We[x * F + f] + be[f]);
-    }
-    if (c) atomicAdd(&nup, c);
-    __syncthreads();
-    for (int l = 0; l < L; ++l) {
-      const double* Hin = Hs + (size_t)l * NF;
-      double* M = Ms + (size_t)l * NF;
-      for (int e = tid; e < NF; e += nt) {
-        const int n = e / F, f = e % F;
-        double m = 0.0;
-        for (int d = 0; d < v.dmax; ++d)
-          m += v.ell_val[n * v.dmax + d] * Hin[v.ell_idx[n * v.dmax + d] * F + f];
-        M[e] = m;
-      }
-      __syncthreads();
-      const double* Wl = W + (size_t)(v.tied ? 0 : l) * 2 * F * F;
-      const double* bl = bb + (size_t)(v.tied ? 0 : l) * F;
-      double* Hout = Hs + (size_t)(l + 1) * NF;
-      for (int e = tid; e < NF; e += nt) {
-        const int n = e / F, f = e % F;
-        double p = bl[f];
-        for (int k = 0; k < F; ++k) p += M[n * F + k] * Wl[k * F + f];
-        for (int k = 0; k < F; ++k) p += Hin[n * F + k] * Wl[(F + k) * F + f];
-        Hout[e] = tanh(p);
-      }
-      __syncthreads();
-    }
-    // readout z = (sum_i H^L_i, n_down, n_up) and head gradients
-    const double ca = cot[2 * (size_t)b], cp = cot[2 * (size_t)b + 1];
-    const double* HL = Hs + (size_t)L * NF;
-    if (tid < F) {
-      double zz = 0.0;
-      for (int n = 0; n < N; ++n) zz += HL[n * F + tid];
-      z[tid] = zz;
-    }
-    if (tid == 0) {
-      z[F] = (double)(N - nup);
-      z[F + 1] = (double)nup;
-    }
-    __syncthreads();
-    if (tid < F + 2) {
-      gva[tid] += ca * z[tid];
-      gvp[tid] += cp * z[tid];
-      dz[tid] = ca * va[tid] + cp * vp[tid];
-    }
-    if (tid == 0) {
-      gva[F + 2] += ca;
-      gvp[F + 2] += cp;
-    }
-    __syncthreads();
-    for (int e = tid; e < NF; e += nt) dH[e] = dz[e % F];
-    __syncthreads();
-    for (int l = L - 1; l >= 0; --l) {
-      const double* Hin = Hs + (size_t)l * NF;
-      const double* Hout = Hs + (size_t)(l + 1) * NF;
-      const double* M = Ms + (size_t)l * NF;
-      const int wi = v.tied ? 0 : l;
-      const double* Wl = W + (size_t)wi * 2 * F * F;
-      double* gWl = gW + (size_t)wi * 2 * F * F;
-      double* gbl = gb + (size_t)wi * F;
-      for (int e = tid; e < NF; e += nt) dH[e] *= (1.0 - Hout[e] * Hout[e]);   // dP
-      __syncthreads();
-      for (int e = tid; e < 2 * F * F; e += nt) {
-        const int k = e / F, f = e % F;
-        const double* X = (k < F) ? M : Hin;
-        const int kk = (k < F) ? k : k - F;
-        double acc = 0.0;
-        for (int n = 0; n < N; ++n) acc += X[n * F + kk] * dH[n * F + f];
-        gWl[e] += acc;
-      }
-      if (tid < F) {
-        double acc = 0.0;
-        for (int n = 0; n < N; ++n) acc += dH[n * F + tid];
-        gbl[tid] += acc;
-      }
-      for (int e = tid; e < N * 2 * F; e += nt) {
-        const int n = e / (2 * F), k = e % (2 * F);
-        double acc = 0.0;
-        for (int f = 0; f < F; ++f) acc += dH[n * F + f] * Wl[k * F + f];
-        dX[e] = acc;
-      }
-      __syncthreads();
-      for (int e = tid; e < NF; e += nt) {
-        const int n = e / F, f = e % F;
-        double acc = dX[n * 2 * F + F + f];
-        for (int d = 0; d < v.dmax; ++d)
-          acc += v.ell_val[n * v.dmax + d] * dX[v.ell_idx[n * v.dmax + d] * 2 * F + f];
-        dH[e] = acc;
-      }
-      __syncthreads();
-    }
-    // embedding
-    if (tid < F) {
-      double a0 = 0.0, a1 = 0.0;
-      for (int n = 0; n < N; ++n) {
-        const double h0 = Hs[n * F + tid];
-        const double dp = dH[n * F + tid] * (1.0 - h0 * h0);
-        if (sb[n] > 0) a1 += dp; else a0 += dp;
-      }
-      gWe[tid] += a0;
-      gWe[F + tid] += a1;
-      gbe[tid] += a0 + a1;
-    }
-    __syncthreads();
-  }
-}
-
 __global__ void k_vjp_reduce(const double* __restrict__ part, int nrows, int npar, double* __restrict__ grad) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= npar) return;
@@ -551,12 +394,62 @@ Kern pick_f(int F, int tpw, int nch) {
   return pick_nch<P, 64>(tpw, nch);
 }
 
+// reverse-pass kernels of one (precision, F, TPW, NCH) instantiation (FP32 or FP64)
+struct VKern {
+  const void* fwd = nullptr;
+  const void* dx = nullptr;
+  const void* dw = nullptr;
+  const void* tail = nullptr;
+  Kern fk{};   // forward kernels of the same precision (prepare)
+  void (*prepare_bwd)(const double*, int, void*, hipStream_t) = nullptr;
+};
+
+template <class P, int F, int TPW, int NCH>
+VKern make_vkern() {
+  VKern k;
+  k.fwd = reinterpret_cast<const void*>(&k_vjp_fwd<P, F, TPW, NCH>);
+  k.dx = reinterpret_cast<const void*>(&k_vjp_dx<P, F, TPW>);
+  k.dw = reinterpret_cast<const void*>(&k_vjp_dw<P, F>);
+  k.tail = reinterpret_cast<const void*>(&k_vjp_tail<P, F>);
+  k.fk = make_kern<P, F, TPW, NCH>();
+  k.prepare_bwd = [](const double* th, int nW, void* out, hipStream_t st) {
+    const int total = nW * 2 * F * F;
+    const int blocks = std::max(1, std::min(1024, (total + 255) / 256));
+    hipLaunchKernelGGL((k_prepare_bwd<P, F>), dim3(blocks), dim3(256), 0, st, th, nW,
+                       reinterpret_cast<typename P::Acc*>(out));
+  };
+  return k;
+}
+
+template <class P, int F, int NCH>
+VKern vpick_tpw(int tpw) {
+  switch (tpw) {
+    case 1: return make_vkern<P, F, 1, NCH>();
+    case 2: return make_vkern<P, F, 2, NCH>();
+    default: return make_vkern<P, F, 4, NCH>();
+  }
+}
+
+template <class P, int F>
+VKern vpick_nch(int tpw, int nch) {
+  if constexpr ((F / P::KS) % 4 == 0) {
+    if (nch == 4) return vpick_tpw<P, F, 4>(tpw);
+  }
+  return vpick_tpw<P, F, 1>(tpw);
+}
+
+template <class P>
+VKern vpick_f(int F, int tpw, int nch) {
+  if (F == 16) return vpick_nch<P, 16>(tpw, nch);
+  if (F == 32) return vpick_nch<P, 32>(tpw, nch);
+  return vpick_nch<P, 64>(tpw, nch);
+}
+
 }  // namespace
 
 struct gna_ctx {
   int N = 0, E = 0, F = 0, L = 0, tied = 1, prec = 0, max_batch = 0;
   double jz = 1.0, jxy = 1.0;
-  int64_t act_budget = 0;
   hipStream_t stream = nullptr;
   int device = 0, n_cu = 0;
   int64_t P = 0;
@@ -582,10 +475,17 @@ struct gna_ctx {
   long long* d_nev = nullptr;   // [1]
   double* d_cot = nullptr;      // [max_batch][2]
   double* d_eloc = nullptr;     // [max_batch][2]
-  double* d_vjp_part = nullptr; // [vjp_wg][P]
-  double* d_vjp_scr = nullptr;  // [vjp_wg][scratch_per_wg]
-  int vjp_wg = 1;
-  size_t vjp_scr_per_wg = 0;
+  // reverse pass (FP32 for the FP32/BF16 modes, FP64 for FP64)
+  Geo vgeo{};
+  VKern vk{};
+  int vgrid_fwd = 1, vgrid_dx = 1, vjp_rows = 1;
+  void* d_vwfrag = nullptr;
+  void* d_vbias = nullptr;
+  void* d_vemb = nullptr;
+  void* d_wbwd = nullptr;
+  void* d_planes = nullptr;     // [vjp_chunk][nplanes][npad][F] Acc
+  int vjp_chunk = 1, nplanes = 1;
+  double* d_vjp_part = nullptr; // [vjp_rows][P]
   std::vector<void*> owned;
   // kernel timing (gna_profile_enable)
   bool prof_on = false;
@@ -741,26 +641,73 @@ gna_status run_eloc(gna_ctx* c, const double* theta, const int8_t* spins, int B,
 }
 
 gna_status run_vjp(gna_ctx* c, const double* theta, const int8_t* spins, int B, const double* cot, double* grad) {
-  VjpNet v{};
-  v.n = c->N;
-  v.F = c->F;
-  v.L = c->L;
-  v.tied = c->tied;
-  v.dmax = c->dmax;
-  v.npar = (int)c->P;
-  v.ell_idx = c->d_idx;
-  v.ell_val = c->d_val64;
-  v.scratch_per_wg = c->vjp_scr_per_wg;
-  const int grid = std::max(1, std::min(B, c->vjp_wg));
+  const int F = c->F, L = c->L, nW = c->tied ? 1 : L;
+  const int rows = c->vjp_rows;
   {
-    Timed tm(c, "k_vjp");
-    hipLaunchKernelGGL(k_vjp, dim3(grid), dim3(256), 0, c->stream, v, theta, spins, B, cot, c->d_vjp_part,
-                     c->d_vjp_scr);
+    Timed tm(c, "k_fill");
+    hipLaunchKernelGGL(k_fill, dim3((int)((rows * c->P + 255) / 256)), dim3(256), 0, c->stream, c->d_vjp_part, 0.0,
+                       (int)(rows * c->P));
   }
-  if (gna_status st = check_launch(c, "k_vjp")) return st;
+  if (gna_status st = check_launch(c, "k_fill")) return st;
+  if (B > 0) {
+    {
+      Timed tm(c, "k_prepare_vjp");
+      c->vk.fk.prepare(theta, nW, c->d_vwfrag, c->d_vbias, c->d_vemb, c->stream);
+      c->vk.prepare_bwd(theta, nW, c->d_wbwd, c->stream);
+    }
+    if (gna_status st = check_launch(c, "k_prepare_vjp")) return st;
+    Net net = make_net(c, theta);
+    net.wfrag = c->d_vwfrag;
+    net.bias = c->d_vbias;
+    net.emb = c->d_vemb;
+    net.g = c->vgeo;
+    VNet v{};
+    v.n = c->N; v.F = F; v.L = L; v.tied = c->tied; v.dmax = c->dmax;
+    v.npad = c->vgeo.npad; v.ntiles = c->vgeo.ntiles; v.wpc = c->vgeo.wpc;
+    v.ell_idx = c->d_idx; v.ell_val = c->d_val; v.wbwd = c->d_wbwd; v.theta = theta;
+    v.npar = (int)c->P;
+    v.plane = (size_t)c->vgeo.npad * F;
+    v.nplanes = c->nplanes;
+    void* planes = c->d_planes;
+    double* part = c->d_vjp_part;
+    const int vthreads = 64 * c->vgeo.wpc;
+    for (int b0 = 0; b0 < B; b0 += c->vjp_chunk) {
+      int Bc = std::min(c->vjp_chunk, B - b0);
+      int nplanes = c->nplanes;
+      {
+        Timed tm(c, "k_vjp_fwd");
+        void* args[] = {&net, &spins, &b0, &Bc, &planes, &nplanes};
+        hipError_t e = hipLaunchKernel(c->vk.fwd, dim3(std::min(Bc, c->vgrid_fwd)), dim3(vthreads), args,
+                                       (size_t)c->vgeo.lds_bytes, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "k_vjp_fwd");
+      }
+      for (int layer = L - 1; layer >= 0; --layer) {
+        {
+          Timed tm(c, "k_vjp_dx");
+          void* args[] = {&v, &layer, &b0, &Bc, &cot, &planes};
+          hipError_t e = hipLaunchKernel(c->vk.dx, dim3(std::min(Bc, c->vgrid_dx)), dim3(vthreads), args,
+                                         (size_t)2 * F * F * c->sz_Acc, c->stream);
+          if (e != hipSuccess) return hip_fail(c, e, "k_vjp_dx");
+        }
+        {
+          Timed tm(c, "k_vjp_dw");
+          void* args[] = {&v, &layer, &Bc, &planes, &part};
+          hipError_t e = hipLaunchKernel(c->vk.dw, dim3(rows), dim3(256), args, 0, c->stream);
+          if (e != hipSuccess) return hip_fail(c, e, "k_vjp_dw");
+        }
+      }
+      {
+        Timed tm(c, "k_vjp_tail");
+        void* args[] = {&v, &b0, &Bc, &spins, &cot, &planes, &part};
+        hipError_t e = hipLaunchKernel(c->vk.tail, dim3(std::min(rows, Bc)), dim3(256), args, 0, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "k_vjp_tail");
+      }
+      if (gna_status st = check_launch(c, "k_vjp")) return st;
+    }
+  }
   Timed tm(c, "k_vjp_reduce");
-  hipLaunchKernelGGL(k_vjp_reduce, dim3((v.npar + 255) / 256), dim3(256), 0, c->stream, c->d_vjp_part, grid,
-                     v.npar, grad);
+  hipLaunchKernelGGL(k_vjp_reduce, dim3((int)((c->P + 255) / 256)), dim3(256), 0, c->stream, c->d_vjp_part, rows,
+                     (int)c->P, grad);
   return check_launch(c, "k_vjp_reduce");
 }
 
@@ -813,7 +760,6 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
   gna_ctx* c = new gna_ctx();
   c->N = N; c->E = E; c->F = F; c->L = L; c->tied = cfg->tied; c->prec = cfg->precision;
   c->jz = cfg->jz; c->jxy = cfg->jxy; c->max_batch = cfg->max_batch;
-  c->act_budget = cfg->act_budget_bytes ? cfg->act_budget_bytes : (int64_t)2 << 30;
   c->stream = reinterpret_cast<hipStream_t>(cfg->stream);
   c->P = param_count(F, L, cfg->tied);
   c->dmax = dmax;
@@ -928,17 +874,64 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
       (st = dev_alloc(c, &c->d_cot, MB * 2 * 8)) ||
       (st = dev_alloc(c, &c->d_eloc, MB * 2 * 8)))
     return bail(st, c->err);
-  // reverse-pass scratch: per workgroup (L+1) H, L M, dH and dX planes
-  c->vjp_scr_per_wg = (size_t)N * F * ((L + 1) + L + 1 + 2);
+  // reverse pass: FP64 for FP64, FP32 otherwise; its own geometry and weights
   {
-    const int64_t per = (int64_t)c->vjp_scr_per_wg * 8 + c->P * 8;
-    int64_t wg = c->act_budget / std::max<int64_t>(per, 1);
-    wg = std::max<int64_t>(1, std::min<int64_t>(wg, std::min<int64_t>(2 * c->n_cu, MB)));
-    c->vjp_wg = (int)wg;
+    const bool v64 = (c->prec == GNA_FP64);
+    const size_t vw_bytes = (size_t)2 * F * F * (v64 ? 8 : 4);
+    Geo saved = g;
+    int vnch = 0;
+    size_t wb_save = 0;
+    (void)wb_save;
+    // same tile split as the forward; pick chunks / buffers for the FP32/FP64 operands
+    auto vlayout = [&](int nch_, int nbuf) -> size_t {
+      const int cs = (F / 4) / nch_;
+      Geo& h = c->vgeo;
+      h = saved;
+      h.nbuf = nbuf;
+      h.row_elems = (int)((4 * cs * c->sz_Acc + kRowPadBytes) / c->sz_Acc);
+      h.buf_elems = h.npad * h.row_elems;
+      size_t o = 0;
+      auto al = [](size_t x) { return (x + 15) & ~(size_t)15; };
+      h.off_w = (int)o; o = al(o + vw_bytes);
+      h.off_h = (int)o; o = al(o + (size_t)nbuf * h.buf_elems * c->sz_Acc);
+      h.off_sp = (int)o; o = al(o + h.npad);
+      h.off_idx = (int)o; o = al(o + (size_t)h.npad * dmax * 4);
+      h.off_val = (int)o; o = al(o + (size_t)h.npad * dmax * c->sz_Acc);
+      h.off_red = (int)o; o = al(o + kRedSlots * 8);
+      h.lds_bytes = (int)o;
+      return o + 64;
+    };
+    for (auto& cd : cand) {
+      if (cd[0] == 4 && (F / 4) % 4 != 0) continue;
+      if (vlayout(cd[0], cd[1]) <= lds_max) { vnch = cd[0]; break; }
+    }
+    if (!vnch) return bail(GNA_UNSUPPORTED, "reverse pass does not fit in LDS");
+    c->vk = v64 ? vpick_f<PF64>(F, tpw, vnch) : vpick_f<PF32>(F, tpw, vnch);
+    const int vthreads = 64 * c->vgeo.wpc;
+    auto vocc = [&](const void* fn, int lds) {
+      hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+      int nb = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, vthreads, lds) != hipSuccess || nb < 1) nb = 1;
+      (void)hipGetLastError();
+      return nb;
+    };
+    c->vgrid_fwd = c->n_cu * vocc(c->vk.fwd, c->vgeo.lds_bytes);
+    c->vgrid_dx = c->n_cu * vocc(c->vk.dx, (int)vw_bytes);
+    c->vjp_rows = 2 * c->n_cu;
+    c->nplanes = 2 * L + 5;
+    const int64_t per_sample = (int64_t)c->nplanes * c->vgeo.npad * F * (int64_t)c->sz_Acc;
+    const int64_t budget = cfg->act_budget_bytes ? cfg->act_budget_bytes : ((int64_t)16 << 30);
+    int64_t chunk = std::max<int64_t>(1, budget / std::max<int64_t>(per_sample, 1));
+    chunk = std::min<int64_t>(chunk, (int64_t)MB);
+    c->vjp_chunk = (int)chunk;
+    if ((st = dev_alloc(c, &c->d_vwfrag, (size_t)(c->tied ? 1 : std::max(L, 1)) * vw_bytes)) ||
+        (st = dev_alloc(c, &c->d_vbias, (size_t)(c->tied ? 1 : std::max(L, 1)) * F * c->sz_Acc)) ||
+        (st = dev_alloc(c, &c->d_vemb, (size_t)2 * F * c->sz_Acc)) ||
+        (st = dev_alloc(c, &c->d_wbwd, (size_t)(c->tied ? 1 : std::max(L, 1)) * vw_bytes)) ||
+        (st = dev_alloc(c, &c->d_planes, (size_t)chunk * per_sample)) ||
+        (st = dev_alloc(c, &c->d_vjp_part, (size_t)c->vjp_rows * c->P * 8)))
+      return bail(st, c->err);
   }
-  if ((st = dev_alloc(c, &c->d_vjp_part, (size_t)c->vjp_wg * c->P * 8)) ||
-      (st = dev_alloc(c, &c->d_vjp_scr, (size_t)c->vjp_wg * c->vjp_scr_per_wg * 8)))
-    return bail(st, c->err);
   he = hipMemcpy(c->d_edges, hedges.data(), hedges.size() * 4, hipMemcpyHostToDevice);
   if (he == hipSuccess) he = hipMemcpy(c->d_idx, idx.data(), idx.size() * 4, hipMemcpyHostToDevice);
   if (he == hipSuccess) he = hipMemcpy(c->d_val64, val.data(), val.size() * 8, hipMemcpyHostToDevice);

@@ -297,10 +297,14 @@ __device__ void load_spins(const Net& net, const Smem<P>& s, const int8_t* __res
 // same arithmetic in the same order for a node whose receptive field holds the
 // same spins, so log psi differences cancel exactly outside it.
 //   TPW: node tiles per wave; NCH: feature chunks of the gather buffer.
+//   STORE: also write the layer inputs H^0..H^L and messages M^0..M^{L-1} to
+//   `store` as planes of npad x F values, element (node, q, i) at
+//   node * F + q * F/4 + i (slot order); H^l is plane l, M^l plane L + 1 + l.
 // ---------------------------------------------------------------------------
-template <class P, int F, int TPW, int NCH>
+template <class P, int F, int TPW, int NCH, bool STORE = false>
 __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
-                            double& out_la, double& out_ph) {
+                            double& out_la, double& out_ph,
+                            typename P::Acc* __restrict__ store = nullptr) {
   using Acc = typename P::Acc;
   using WT = typename P::WT;
   using BF = typename P::BF;
@@ -340,7 +344,13 @@ __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
 
   double pa = 0.0, pp = 0.0;
   const WT* wl = s.w;
+  const size_t plane = (size_t)g.npad * F;
   for (int l = 0; l < net.L; ++l) {
+    if constexpr (STORE) {
+#pragma unroll
+      for (int k = 0; k < TPW; ++k)
+        if (tile_ok[k]) lds_write<Acc, NS>(store + l * plane + node[k] * F + q * NS, h[k]);
+    }
     if (!net.tied) {
       __syncthreads();
       stage_weights<P, F>(net, s, l);
@@ -400,6 +410,8 @@ __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
 #pragma unroll
           for (int i = 0; i < CS; ++i) m[i] += a * row[i];
         }
+        if constexpr (STORE)
+          lds_write<Acc, CS>(store + (net.L + 1 + l) * plane + node[k] * F + q * NS + ch * CS, m);
 #pragma unroll
         for (int st = 0; st < KSC; ++st) {
           const BF b = P::make_b(&m[st * VEC]);
@@ -428,6 +440,11 @@ __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
         }
       }
     }
+  }
+  if constexpr (STORE) {
+#pragma unroll
+    for (int k = 0; k < TPW; ++k)
+      if (tile_ok[k]) lds_write<Acc, NS>(store + net.L * plane + node[k] * F + q * NS, h[k]);
   }
   if (net.L == 0) {
 #pragma unroll
