@@ -38,7 +38,7 @@ namespace {
 // Build the per-precision device weights from FP64 theta.
 //   wfrag[w][s][t][lane][j] = W[w][blk*F + kk][row_feature(16t + lane%16)],
 //   s < F/KS: message block (blk 0), else self block (blk 1);
-//   kk = KS*(s mod F/KS) + (VEC == 1 ? lane/16 : 4*(lane/16) + j).
+//   kk = KS*(s mod F/KS) + VEC*(lane/16) + j.
 template <class P, int F>
 __global__ void k_prepare(const double* __restrict__ theta, int nW, void* wfrag, void* bias, void* emb) {
   using WT = typename P::WT;
@@ -59,7 +59,7 @@ __global__ void k_prepare(const double* __restrict__ theta, int nW, void* wfrag,
     const int s = r % (2 * KSB); r /= (2 * KSB);
     const int w = r;
     const int blk = s / KSB, ss = s % KSB;
-    const int kk = P::KS * ss + (VEC == 1 ? lane / 16 : 4 * (lane / 16) + j);
+    const int kk = P::KS * ss + VEC * (lane / 16) + j;
     const int f = P::row_feature(16 * t + lane % 16);
     const double v = W[(size_t)w * per_layer + (size_t)(blk * F + kk) * F + f];
     wf[e] = P::to_w(P::kScale * v);
@@ -73,7 +73,7 @@ __global__ void k_prepare(const double* __restrict__ theta, int nW, void* wfrag,
 }
 
 template <class P, int F, int TPW, int NCH>
-__global__ __launch_bounds__(TPW == 1 ? 1024 : 512) void k_logpsi(Net net, const int8_t* __restrict__ spins, int B,
+__global__ __launch_bounds__(512) void k_logpsi(Net net, const int8_t* __restrict__ spins, int B,
                                                  double* __restrict__ out) {
   extern __shared__ __align__(16) unsigned char smem[];
   Smem<P> s(net.g, smem);
@@ -100,7 +100,7 @@ __device__ __forceinline__ void neumaier(double& sum, double& comp, double x) {
 // partial[item] = {sum re, comp re, sum im, comp im} of psi(s^ij)/psi(s) over the
 // anti-aligned bonds of chunk c of sample b (item = b * n_chunks + c), in bond order.
 template <class P, int F, int TPW, int NCH>
-__global__ __launch_bounds__(TPW == 1 ? 1024 : 512) void k_eloc(Net net, const int8_t* __restrict__ spins, int B,
+__global__ __launch_bounds__(512) void k_eloc(Net net, const int8_t* __restrict__ spins, int B,
                                                const double* __restrict__ base, int n_chunks, int chunk,
                                                double* __restrict__ partial, int* __restrict__ cnt) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -169,7 +169,7 @@ __global__ void k_eloc_finalize(const int8_t* __restrict__ spins, int N, const i
 }
 
 template <class P, int F, int TPW, int NCH>
-__global__ __launch_bounds__(TPW == 1 ? 1024 : 512) void k_sweep(Net net, int8_t* __restrict__ spins, double* __restrict__ logpsi,
+__global__ __launch_bounds__(512) void k_sweep(Net net, int8_t* __restrict__ spins, double* __restrict__ logpsi,
                                                 int B, int n_sweeps, unsigned long long seed,
                                                 unsigned long long counter_base, int* __restrict__ n_accept) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -381,7 +381,7 @@ Kern pick_tpw(int tpw) {
 
 template <class P, int F>
 Kern pick_nch(int tpw, int nch) {
-  if constexpr ((F / P::KS) % 4 == 0) {
+  if constexpr ((F / 16) % 4 == 0) {
     if (nch == 4) return pick_tpw<P, F, 4>(tpw);
   }
   return pick_tpw<P, F, 1>(tpw);
@@ -432,7 +432,7 @@ VKern vpick_tpw(int tpw) {
 
 template <class P, int F>
 VKern vpick_nch(int tpw, int nch) {
-  if constexpr ((F / P::KS) % 4 == 0) {
+  if constexpr ((F / 16) % 4 == 0) {
     if (nch == 4) return vpick_tpw<P, F, 4>(tpw);
   }
   return vpick_tpw<P, F, 1>(tpw);
@@ -756,6 +756,7 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
   }
   int dmax = 1;
   for (int d : deg) dmax = std::max(dmax, d);
+  dmax = (dmax + 3) / 4 * 4;   // the gather loop reads neighbours four at a time
 
   gna_ctx* c = new gna_ctx();
   c->N = N; c->E = E; c->F = F; c->L = L; c->tied = cfg->tied; c->prec = cfg->precision;
@@ -788,8 +789,8 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
   const char* env_tpw = std::getenv("GNA_TILES_PER_WAVE");
   int tpw = 0;
   if (env_tpw) tpw = std::atoi(env_tpw);
-  // kernels with more than one tile per wave are built for at most 8 waves
-  auto max_waves = [](int t) { return t == 1 ? kMaxWaves : kMaxWaves / 2; };
+  // the evaluator kernels are built for at most 8 waves (256 VGPRs per lane)
+  auto max_waves = [](int) { return kMaxWaves / 2; };
   if (tpw != 1 && tpw != 2 && tpw != 4) {
     tpw = 1;
     while (tpw < 4 && (g.ntiles + tpw - 1) / tpw > max_waves(tpw)) tpw *= 2;
@@ -811,14 +812,16 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
     g.off_idx = (int)o; o = al(o + (size_t)g.npad * dmax * 4);
     g.off_val = (int)o; o = al(o + (size_t)g.npad * dmax * c->sz_Acc);
     g.off_red = (int)o; o = al(o + kRedSlots * 8);
+    g.off_bias = (int)o; o = al(o + (size_t)(cfg->tied ? 1 : std::max(L, 1)) * F * c->sz_Acc);
+    g.off_emb = (int)o; o = al(o + (size_t)2 * F * c->sz_Acc);
+    g.off_head = (int)o; o = al(o + (size_t)2 * (F + 3) * 8);
     g.lds_bytes = (int)o;
     return o + 64;  // static shared scalars
   };
   int nch = 0;
   const int cand[4][2] = {{1, 2}, {1, 1}, {4, 2}, {4, 1}};
   for (auto& cd : cand) {
-    const int ks = (c->prec == GNA_BF16) ? 16 : 4;  // features per MFMA k-step
-    if (cd[0] == 4 && (F / ks) % 4 != 0) continue;
+    if ((F / 16) % cd[0] != 0) continue;   // message chunks split the output 16-feature tiles
     if (layout(cd[0], cd[1]) <= lds_max) { nch = cd[0]; break; }
   }
   if (!nch) return bail(GNA_UNSUPPORTED, "configuration does not fit in LDS");
@@ -826,7 +829,11 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
   switch (c->prec) {
     case GNA_FP64: c->kern = pick_f<PF64>(F, tpw, nch); break;
     case GNA_FP32: c->kern = pick_f<PF32>(F, tpw, nch); break;
-    default: c->kern = pick_f<PBF16>(F, tpw, nch); break;
+    default:
+      // bf16: the K=32 instruction where F allows, the K=16 one at F = 16
+      c->kern = (F == 16) ? pick_nch<PBF16, 16>(tpw, nch)
+                          : (F == 32 ? pick_nch<PBF16W, 32>(tpw, nch) : pick_nch<PBF16W, 64>(tpw, nch));
+      break;
   }
   const int threads = 64 * g.wpc;
   auto occ = [&](const void* fn) {
@@ -898,11 +905,14 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
       h.off_idx = (int)o; o = al(o + (size_t)h.npad * dmax * 4);
       h.off_val = (int)o; o = al(o + (size_t)h.npad * dmax * c->sz_Acc);
       h.off_red = (int)o; o = al(o + kRedSlots * 8);
+      h.off_bias = (int)o; o = al(o + (size_t)(cfg->tied ? 1 : std::max(L, 1)) * F * c->sz_Acc);
+      h.off_emb = (int)o; o = al(o + (size_t)2 * F * c->sz_Acc);
+      h.off_head = (int)o; o = al(o + (size_t)2 * (F + 3) * 8);
       h.lds_bytes = (int)o;
       return o + 64;
     };
     for (auto& cd : cand) {
-      if (cd[0] == 4 && (F / 4) % 4 != 0) continue;
+      if ((F / 16) % cd[0] != 0) continue;
       if (vlayout(cd[0], cd[1]) <= lds_max) { vnch = cd[0]; break; }
     }
     if (!vnch) return bail(GNA_UNSUPPORTED, "reverse pass does not fit in LDS");

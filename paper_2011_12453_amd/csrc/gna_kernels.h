@@ -55,14 +55,18 @@ __device__ __forceinline__ unsigned pack_bf16_rne(float a, float b) {
 struct PF64 {  // v_mfma_f64_16x16x4f64: D[4r + l/16][l%16], B[l/16][l%16]
   using Acc = double;
   using WT = double;
+  using AF = double;
   using BF = double;
   using CF = d4;
   static constexpr int KS = 4, VEC = 1;
   static constexpr double kScale = 1.0;
   __device__ static BF make_b(const Acc* x) { return x[0]; }
-  __device__ static CF mma(const WT* a, const BF& b, CF c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b, c, 0, 0, 0);
+  __device__ static AF load_a(const WT* p) { return p[0]; }
+  __device__ static CF mma(const AF& a, const BF& b, CF c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  static constexpr int NPART = 1;
+  __device__ static CF mma_part(const AF& a, const BF& b, int, CF c) { return mma(a, b, c); }
   __host__ __device__ static int lc(int q, int i) { return 4 * i + q; }
   __host__ __device__ static int row_feature(int m) { return m; }
   __device__ static WT to_w(double v) { return v; }
@@ -72,14 +76,18 @@ struct PF64 {  // v_mfma_f64_16x16x4f64: D[4r + l/16][l%16], B[l/16][l%16]
 struct PF32 {  // v_mfma_f32_16x16x4f32: D[4(l/16) + r][l%16], B[l/16][l%16]
   using Acc = float;
   using WT = float;
+  using AF = float;
   using BF = float;
   using CF = f4;
   static constexpr int KS = 4, VEC = 1;
   static constexpr double kScale = (double)kTwoLog2e;
   __device__ static BF make_b(const Acc* x) { return x[0]; }
-  __device__ static CF mma(const WT* a, const BF& b, CF c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b, c, 0, 0, 0);
+  __device__ static AF load_a(const WT* p) { return p[0]; }
+  __device__ static CF mma(const AF& a, const BF& b, CF c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  static constexpr int NPART = 1;
+  __device__ static CF mma_part(const AF& a, const BF& b, int, CF c) { return mma(a, b, c); }
   __host__ __device__ static int lc(int q, int i) { return 4 * i + q; }
   __host__ __device__ static int row_feature(int m) {
     return 16 * (m / 16) + 4 * (m % 4) + (m % 16) / 4;
@@ -114,13 +122,65 @@ struct PBF16 {  // v_mfma_f32_16x16x16_bf16: D[4(l/16) + r][l%16], B[4(l/16) + j
     b.lo = __builtin_bit_cast(s4, (unsigned long long)l01 | ((unsigned long long)l23 << 32));
     return b;
   }
-  __device__ static CF mma(const WT* a, const BF& b, CF c) {
-    const s4 av = *reinterpret_cast<const s4*>(a);
-    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, b.hi, c, 0, 0, 0);
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, b.lo, c, 0, 0, 0);
+  using AF = s4;
+  __device__ static AF load_a(const WT* p) { return *reinterpret_cast<const s4*>(p); }
+  __device__ static CF mma(const AF& a, const BF& b, CF c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b.hi, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b.lo, c, 0, 0, 0);
+  }
+  static constexpr int NPART = 2;   // hi, then lo
+  __device__ static CF mma_part(const AF& a, const BF& b, int part, CF c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, part ? b.lo : b.hi, c, 0, 0, 0);
   }
   __host__ __device__ static int lc(int q, int i) { return 16 * (i / 4) + 4 * q + (i % 4); }
   __host__ __device__ static int row_feature(int m) { return m; }
+  __device__ static WT to_w(double v) {
+    return (WT)(pack_bf16_rne((float)v, 0.0f) & 0xFFFFu);
+  }
+  __device__ static Acc act(Acc y) { return tanh_from_scaled(y); }
+};
+
+// The same operands on v_mfma_f32_16x16x32_bf16 (F a multiple of 32):
+// B[8(l/16) + j][l%16], j = 0..7, so slot i of lane group q is feature
+// 32(i/8) + 8q + i%8, and physical A row 16t + 4q + r must compute that
+// feature of slot 4t + r.
+typedef __attribute__((ext_vector_type(8))) __bf16 bf8v;
+struct PBF16W {
+  using Acc = float;
+  using WT = unsigned short;
+  struct BF { bf8v hi, lo; };
+  using CF = f4;
+  static constexpr int KS = 32, VEC = 8;
+  static constexpr double kScale = (double)kTwoLog2e;
+  __device__ static BF make_b(const Acc* x) {
+    unsigned hu[4], lu[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const unsigned u0 = __float_as_uint(x[2 * p]) & 0xFFFF0000u;
+      const unsigned u1 = __float_as_uint(x[2 * p + 1]) & 0xFFFF0000u;
+      hu[p] = (u0 >> 16) | u1;
+      lu[p] = pack_bf16_rne(x[2 * p] - __uint_as_float(u0), x[2 * p + 1] - __uint_as_float(u1));
+    }
+    BF b;
+    b.hi = __builtin_bit_cast(bf8v, uint4{hu[0], hu[1], hu[2], hu[3]});
+    b.lo = __builtin_bit_cast(bf8v, uint4{lu[0], lu[1], lu[2], lu[3]});
+    return b;
+  }
+  using AF = bf8v;
+  __device__ static AF load_a(const WT* p) { return *reinterpret_cast<const bf8v*>(p); }
+  __device__ static CF mma(const AF& a, const BF& b, CF c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b.hi, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b.lo, c, 0, 0, 0);
+  }
+  static constexpr int NPART = 2;   // hi, then lo
+  __device__ static CF mma_part(const AF& a, const BF& b, int part, CF c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, part ? b.lo : b.hi, c, 0, 0, 0);
+  }
+  __host__ __device__ static int lc(int q, int i) { return 32 * (i / 8) + 8 * q + (i % 8); }
+  __host__ __device__ static int row_feature(int m) {
+    const int t = m / 16, q = (m % 16) / 4, r = m % 4;
+    return 32 * (t / 2) + 8 * q + 4 * (t % 2) + r;
+  }
   __device__ static WT to_w(double v) {
     return (WT)(pack_bf16_rne((float)v, 0.0f) & 0xFFFFu);
   }
@@ -160,6 +220,7 @@ struct Geo {
   int row_elems;  // gather-buffer row stride in elements of Acc
   int buf_elems;  // elements of Acc per gather buffer
   int off_w, off_h, off_sp, off_idx, off_val, off_red;
+  int off_bias, off_emb, off_head;   // layer biases [nW][F], embedding [2][F], heads [2][F+3]
   int lds_bytes;
 };
 
@@ -230,13 +291,19 @@ struct Smem {
   int* idx;      // ELL neighbour ids
   Acc* val;      // ELL values
   double* red;   // [2 * kMaxWaves] readout partials + scalars
+  Acc* bias;     // [nW][4][F/4]: layer bias in slot order, lane group q at q*F/4
+  Acc* emb;      // [2][F]
+  double* head;  // v_a[F+2], c_a, v_p[F+2], c_p
   __device__ Smem(const Geo& g, unsigned char* base)
       : w(reinterpret_cast<WT*>(base + g.off_w)),
         h(reinterpret_cast<Acc*>(base + g.off_h)),
         sp(reinterpret_cast<int8_t*>(base + g.off_sp)),
         idx(reinterpret_cast<int*>(base + g.off_idx)),
         val(reinterpret_cast<Acc*>(base + g.off_val)),
-        red(reinterpret_cast<double*>(base + g.off_red)) {}
+        red(reinterpret_cast<double*>(base + g.off_red)),
+        bias(reinterpret_cast<Acc*>(base + g.off_bias)),
+        emb(reinterpret_cast<Acc*>(base + g.off_emb)),
+        head(reinterpret_cast<double*>(base + g.off_head)) {}
 };
 
 // red[] scalar slots after the 2*kMaxWaves partials
@@ -259,7 +326,8 @@ __device__ void stage_weights(const Net& net, const Smem<P>& s, int layer) {
   }
 }
 
-// Copy the ELL adjacency global -> LDS (whole workgroup).
+// Copy the ELL adjacency, the biases, the embedding table and the head weights
+// global -> LDS (whole workgroup).
 template <class P>
 __device__ void stage_graph(const Net& net, const Smem<P>& s) {
   using Acc = typename P::Acc;
@@ -268,6 +336,16 @@ __device__ void stage_graph(const Net& net, const Smem<P>& s) {
   for (int k = threadIdx.x; k < n; k += blockDim.x) {
     s.idx[k] = net.ell_idx[k];
     s.val[k] = v[k];
+  }
+  const int nb = (net.tied ? 1 : net.L) * net.F;
+  for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+    const int lay = k / net.F, e = k % net.F, qq = e / (net.F / 4), i = e % (net.F / 4);
+    s.bias[k] = reinterpret_cast<const Acc*>(net.bias)[lay * net.F + P::lc(qq, i)];
+  }
+  for (int k = threadIdx.x; k < 2 * net.F; k += blockDim.x) s.emb[k] = reinterpret_cast<const Acc*>(net.emb)[k];
+  for (int k = threadIdx.x; k < net.F + 3; k += blockDim.x) {
+    s.head[k] = net.head_a[k];
+    s.head[net.F + 3 + k] = net.head_p[k];
   }
 }
 
@@ -293,13 +371,21 @@ __device__ void load_spins(const Net& net, const Smem<P>& s, const int8_t* __res
 // ---------------------------------------------------------------------------
 // Evaluate log psi of the configuration in s.sp with sites si and sj exchanged
 // (si < 0: no exchange).  Whole workgroup; the result is returned to thread 0
-// only.  Node tile k of wave w is tile w + k * wpc.  Every call performs the
-// same arithmetic in the same order for a node whose receptive field holds the
-// same spins, so log psi differences cancel exactly outside it.
-//   TPW: node tiles per wave; NCH: feature chunks of the gather buffer.
-//   STORE: also write the layer inputs H^0..H^L and messages M^0..M^{L-1} to
-//   `store` as planes of npad x F values, element (node, q, i) at
-//   node * F + q * F/4 + i (slot order); H^l is plane l, M^l plane L + 1 + l.
+// only.  Node tile k of wave w is tile w + k * wpc.
+//
+// Eq. 1 is applied as P = A_hat (H W_msg) + H W_self + b: both products take the
+// node's own activations as the MFMA B operand (built once per tile), the
+// message product G = H W_msg goes through LDS, and the adjacency gather adds
+// A_hat G into the accumulator before tanh.  The message product is split into
+// NCH chunks of output features when the LDS buffer must be smaller.
+//
+// Every call performs the same arithmetic in the same order for a node whose
+// receptive field holds the same spins, so log psi differences cancel exactly
+// outside it.
+//   STORE: also write the layer inputs H^0..H^L and messages M^0..M^{L-1}
+//   (M^l = A_hat H^l, gathered for the reverse pass) to `store` as planes of
+//   npad x F values, element (node, q, i) at node * F + q * F/4 + i (slot
+//   order); H^l is plane l, M^l plane L + 1 + l.
 // ---------------------------------------------------------------------------
 template <class P, int F, int TPW, int NCH, bool STORE = false>
 __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
@@ -307,17 +393,19 @@ __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
                             typename P::Acc* __restrict__ store = nullptr) {
   using Acc = typename P::Acc;
   using WT = typename P::WT;
+  using AF = typename P::AF;
   using BF = typename P::BF;
   using CF = typename P::CF;
   constexpr int NS = F / 4;           // slots per lane per tile
   constexpr int MT = F / 16;          // output 16-feature tiles
   constexpr int KSB = F / P::KS;      // MFMA k-steps per F-wide block
-  constexpr int CS = NS / NCH;        // slots per gather chunk
-  constexpr int KSC = KSB / NCH;      // k-steps per gather chunk
+  constexpr int MTC = MT / NCH;       // output tiles per message chunk
+  constexpr int CS = NS / NCH;        // slots per message chunk
   constexpr int VEC = P::VEC;
-  static_assert(F % 16 == 0 && NS % NCH == 0 && KSB % NCH == 0, "bad shape");
+  static_assert(F % 16 == 0 && KSB >= 1 && MT % NCH == 0, "bad shape");
 
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   const int q = lane >> 4, col = lane & 15;
   const Geo& g = net.g;
   const int wpc = g.wpc;
@@ -325,7 +413,9 @@ __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
   int node[TPW];
   bool tile_ok[TPW], real[TPW];
   Acc h[TPW][NS];
-  const Acc* emb = reinterpret_cast<const Acc*>(net.emb);
+  const Acc* emb = s.emb;
+  const double* head_a = s.head;
+  const double* head_p = s.head + F + 3;
 #pragma unroll
   for (int k = 0; k < TPW; ++k) {
     const int tile = wv + k * wpc;
@@ -345,6 +435,8 @@ __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
   double pa = 0.0, pp = 0.0;
   const WT* wl = s.w;
   const size_t plane = (size_t)g.npad * F;
+  // weight fragment of output tile t at k-step st of block blk (0 message, 1 self)
+  auto afrag = [&](int blk, int st, int t) { return wl + (((blk * KSB + st) * MT + t) * 64 + lane) * VEC; };
   for (int l = 0; l < net.L; ++l) {
     if constexpr (STORE) {
 #pragma unroll
@@ -356,88 +448,175 @@ __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
       stage_weights<P, F>(net, s, l);
       __syncthreads();
     }
-    const Acc* bias = reinterpret_cast<const Acc*>(net.bias) + (net.tied ? 0 : l) * F;
+    const Acc* bias = s.bias + (net.tied ? 0 : l) * F + q * NS;   // this lane group's slots
+    // B operands of every tile of the wave, built once per layer (split types
+    // only; FP32/FP64 operands are the activations themselves)
+    constexpr bool SPLIT = (P::NPART == 2);
+    BF bfr[SPLIT ? TPW : 1][SPLIT ? KSB : 1];
+    if constexpr (SPLIT) {
+#pragma unroll
+      for (int k = 0; k < TPW; ++k)
+#pragma unroll
+        for (int st = 0; st < KSB; ++st) bfr[k][st] = P::make_b(&h[k][st * VEC]);
+    }
+    auto bop = [&](int k, int st) -> BF {
+      if constexpr (SPLIT) return bfr[k][st];
+      else return P::make_b(&h[k][st * VEC]);
+    };
     CF acc[TPW][MT];
-#pragma unroll
-    for (int t = 0; t < MT; ++t) {
-      CF bv;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) bv[r] = bias[P::lc(q, 4 * t + r)];
-#pragma unroll
-      for (int k = 0; k < TPW; ++k) acc[k][t] = bv;
-    }
-    // self block: the node's own row, straight from registers; each weight
-    // fragment is read once and applied to every tile of the wave
-#pragma unroll
-    for (int st = 0; st < KSB; ++st) {
-      BF b[TPW];
-#pragma unroll
-      for (int k = 0; k < TPW; ++k) b[k] = P::make_b(&h[k][st * VEC]);
-#pragma unroll
-      for (int t = 0; t < MT; ++t) {
-        WT a[VEC];
-        const WT* ap = wl + (((KSB + st) * MT + t) * 64 + lane) * VEC;
-#pragma unroll
-        for (int j = 0; j < VEC; ++j) a[j] = ap[j];
-#pragma unroll
-        for (int k = 0; k < TPW; ++k)
-          if (tile_ok[k]) acc[k][t] = P::mma(a, b[k], acc[k][t]);
-      }
-    }
-    // message block: gather A_hat H from LDS chunk by chunk
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) {
       const int buf = (g.nbuf == 2) ? ((l * NCH + ch) & 1) : 0;
       Acc* hb = s.h + buf * g.buf_elems;
-      if (g.nbuf == 1) __syncthreads();
+      if (g.nbuf == 1) __syncthreads();           // the previous gather is done
+      if constexpr (SPLIT) {
+      // Output tiles outermost: each weight fragment is read once and applied to
+      // every tile; the hi and lo halves of a product are issued tile after tile.
 #pragma unroll
-      for (int k = 0; k < TPW; ++k)
-        if (tile_ok[k]) lds_write<Acc, CS>(hb + node[k] * g.row_elems + q * CS, &h[k][ch * CS]);
+      for (int t = 0; t < MT; ++t) {
+        const bool self_t = (ch == 0);            // self product once, in the first chunk
+        const bool msg_t = (t / MTC == ch);       // message product of this chunk's tiles
+        if (self_t) {
+          CF bt;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) bt[r] = bias[4 * t + r];
+#pragma unroll
+          for (int st = 0; st < KSB; ++st) {
+            const AF a = P::load_a(afrag(1, st, t));
+#pragma unroll
+            for (int part = 0; part < P::NPART; ++part)
+#pragma unroll
+              for (int k = 0; k < TPW; ++k)
+                if (tile_ok[k])
+                  acc[k][t] = P::mma_part(a, bop(k, st), part, (st == 0 && part == 0) ? bt : acc[k][t]);
+          }
+        }
+        if (msg_t) {
+          CF gacc[TPW];
+#pragma unroll
+          for (int st = 0; st < KSB; ++st) {
+            const AF a = P::load_a(afrag(0, st, t));
+#pragma unroll
+            for (int part = 0; part < P::NPART; ++part)
+#pragma unroll
+              for (int k = 0; k < TPW; ++k)
+                if (tile_ok[k])
+                  gacc[k] = P::mma_part(a, bop(k, st), part, (st == 0 && part == 0) ? CF{0, 0, 0, 0} : gacc[k]);
+          }
+#pragma unroll
+          for (int k = 0; k < TPW; ++k)
+            if (tile_ok[k]) {
+              Acc gm[4] = {gacc[k][0], gacc[k][1], gacc[k][2], gacc[k][3]};
+              lds_write<Acc, 4>(hb + node[k] * g.row_elems + q * CS + 4 * (t - ch * MTC), gm);
+            }
+        }
+      }
+      } else {
+      // one-word fragments: tiles outermost keeps the live set small
+#pragma unroll
+      for (int k = 0; k < TPW; ++k) {
+        if (!tile_ok[k]) continue;
+        if (ch == 0) {
+#pragma unroll
+          for (int t = 0; t < MT; ++t) {
+            CF a;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a[r] = bias[4 * t + r];
+#pragma unroll
+            for (int st = 0; st < KSB; ++st) a = P::mma(P::load_a(afrag(1, st, t)), bop(k, st), a);
+            acc[k][t] = a;
+          }
+        }
+        Acc gm[CS];
+#pragma unroll
+        for (int tc = 0; tc < MTC; ++tc) {
+          CF a = CF{0, 0, 0, 0};
+#pragma unroll
+          for (int st = 0; st < KSB; ++st) a = P::mma(P::load_a(afrag(0, st, ch * MTC + tc)), bop(k, st), a);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) gm[4 * tc + r] = a[r];
+        }
+        lds_write<Acc, CS>(hb + node[k] * g.row_elems + q * CS, gm);
+      }
+      }
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < TPW; ++k) {
         if (!tile_ok[k]) continue;
+        const int* ip = s.idx + node[k] * net.dmax;
+        const Acc* vp = s.val + node[k] * net.dmax;
         Acc m[CS];
 #pragma unroll
         for (int i = 0; i < CS; ++i) m[i] = (Acc)0;
-        const int* ip = s.idx + node[k] * net.dmax;
-        const Acc* vp = s.val + node[k] * net.dmax;
-        for (int d = 0; d < net.dmax; ++d) {
-          const int nb = ip[d];
-          const Acc a = vp[d];
-          Acc row[CS];
-          lds_read<Acc, CS>(hb + nb * g.row_elems + q * CS, row);
+        // the neighbour list is padded to a multiple of 4 (zero weights)
+        for (int d = 0; d < net.dmax; d += 4) {
+          Acc row[4][CS];
 #pragma unroll
-          for (int i = 0; i < CS; ++i) m[i] += a * row[i];
-        }
-        if constexpr (STORE)
-          lds_write<Acc, CS>(store + (net.L + 1 + l) * plane + node[k] * F + q * NS + ch * CS, m);
+          for (int u = 0; u < 4; ++u) lds_read<Acc, CS>(hb + ip[d + u] * g.row_elems + q * CS, row[u]);
 #pragma unroll
-        for (int st = 0; st < KSC; ++st) {
-          const BF b = P::make_b(&m[st * VEC]);
+          for (int u = 0; u < 4; ++u) {
+            const Acc a = vp[d + u];
 #pragma unroll
-          for (int t = 0; t < MT; ++t) {
-            const WT* a = wl + (((ch * KSC + st) * MT + t) * 64 + lane) * VEC;
-            acc[k][t] = P::mma(a, b, acc[k][t]);
+            for (int i = 0; i < CS; ++i) m[i] += a * row[u][i];
           }
         }
+#pragma unroll
+        for (int tc = 0; tc < MTC; ++tc)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[k][ch * MTC + tc][r] += m[4 * tc + r];
       }
+    }
+    if constexpr (STORE) {
+      // the reverse pass needs M^l = A_hat H^l itself: gather H^l (one more LDS round)
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) {
+        const int buf = (g.nbuf == 2) ? ((l * NCH + ch + 1) & 1) : 0;
+        Acc* hb = s.h + buf * g.buf_elems;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < TPW; ++k)
+          if (tile_ok[k]) lds_write<Acc, CS>(hb + node[k] * g.row_elems + q * CS, &h[k][ch * CS]);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < TPW; ++k) {
+          if (!tile_ok[k]) continue;
+          Acc m[CS];
+#pragma unroll
+          for (int i = 0; i < CS; ++i) m[i] = (Acc)0;
+          for (int d = 0; d < net.dmax; ++d) {
+            Acc row[CS];
+            lds_read<Acc, CS>(hb + s.idx[node[k] * net.dmax + d] * g.row_elems + q * CS, row);
+            const Acc a = s.val[node[k] * net.dmax + d];
+#pragma unroll
+            for (int i = 0; i < CS; ++i) m[i] += a * row[i];
+          }
+          lds_write<Acc, CS>(store + (net.L + 1 + l) * plane + node[k] * F + q * NS + ch * CS, m);
+        }
+      }
+      __syncthreads();
     }
     const bool last = (l == net.L - 1);
 #pragma unroll
     for (int k = 0; k < TPW; ++k) {
+      // readout partial of this node in Acc: identical inputs give identical
+      // partials, so unchanged nodes still cancel exactly in log psi differences
+      Acc ta = 0, tp = 0;
 #pragma unroll
       for (int t = 0; t < MT; ++t) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const Acc v = P::act(acc[k][t][r]);
           h[k][4 * t + r] = v;
-          if (last && real[k]) {
+          if (last) {
             const int f = P::lc(q, 4 * t + r);
-            pa += net.head_a[f] * (double)v;
-            pp += net.head_p[f] * (double)v;
+            ta += (Acc)head_a[f] * v;
+            tp += (Acc)head_p[f] * v;
           }
         }
+      }
+      if (last && real[k]) {
+        pa += (double)ta;
+        pp += (double)tp;
       }
     }
   }
@@ -453,8 +632,8 @@ __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
 #pragma unroll
         for (int i = 0; i < NS; ++i) {
           const int f = P::lc(q, i);
-          pa += net.head_a[f] * (double)h[k][i];
-          pp += net.head_p[f] * (double)h[k][i];
+          pa += head_a[f] * (double)h[k][i];
+          pp += head_p[f] * (double)h[k][i];
         }
   }
   pa = wave_sum(pa);
@@ -470,10 +649,9 @@ __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
       a += s.red[w];
       p += s.red[kMaxWaves + w];
     }
-    const int F2 = net.F;
     const double nup = s.red[kRedNup], ndn = (double)net.n - nup;
-    a += net.head_a[F2] * ndn + net.head_a[F2 + 1] * nup + net.head_a[F2 + 2];
-    p += net.head_p[F2] * ndn + net.head_p[F2 + 1] * nup + net.head_p[F2 + 2];
+    a += head_a[F] * ndn + head_a[F + 1] * nup + head_a[F + 2];
+    p += head_p[F] * ndn + head_p[F + 1] * nup + head_p[F + 2];
     out_la = a;
     out_ph = p;
   }

@@ -58,7 +58,7 @@ __global__ void k_prepare_bwd(const double* __restrict__ theta, int nW, typename
 
 // Forward recompute storing the planes of samples [b0, b0 + Bc).
 template <class P, int F, int TPW, int NCH>
-__global__ __launch_bounds__(TPW == 1 ? 1024 : 512) void k_vjp_fwd(Net net, const int8_t* __restrict__ spins,
+__global__ __launch_bounds__(512) void k_vjp_fwd(Net net, const int8_t* __restrict__ spins,
                                                                    int b0, int Bc, typename P::Acc* planes,
                                                                    int nplanes) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(TPW == 1 ? 1024 : 512) void k_vjp_fwd(Net net, cons
 // One layer of the reverse pass for samples [b0, b0 + Bc): dP, dX = dP W^T, and
 // dH of the layer input.  layer == L-1 seeds dH^L from the cotangents.
 template <class P, int F, int TPW>
-__global__ __launch_bounds__(TPW == 1 ? 1024 : 512) void k_vjp_dx(VNet v, int layer, int b0, int Bc,
+__global__ __launch_bounds__(512) void k_vjp_dx(VNet v, int layer, int b0, int Bc,
                                                                   const double* __restrict__ cot,
                                                                   typename P::Acc* planes) {
   using Acc = typename P::Acc;
@@ -134,8 +134,7 @@ __global__ __launch_bounds__(TPW == 1 ? 1024 : 512) void k_vjp_dx(VNet v, int la
       for (int st = 0; st < KSB; ++st) {
 #pragma unroll
         for (int t = 0; t < 2 * MT; ++t) {
-          const Acc* a = wfr + ((t * KSB + st) * 64 + lane);
-          dx[t] = P::mma(a, dp[st], dx[t]);
+          dx[t] = P::mma(wfr[(t * KSB + st) * 64 + lane], dp[st], dx[t]);
         }
       }
       Acc xm[NS];
@@ -218,7 +217,7 @@ __global__ __launch_bounds__(256) void k_vjp_dw(VNet v, int layer, int Bc, const
       const int pl = (tm < MT) ? (v.L + 1 + layer) : layer;   // M^l or H^l
       const Acc af = pb[(size_t)pl * v.plane + off + 16 * (tm % MT) + col];
 #pragma unroll
-      for (int t = 0; t < MT; ++t) acc[a][t] = P::mma(&af, bf[t], acc[a][t]);
+      for (int t = 0; t < MT; ++t) acc[a][t] = P::mma(af, bf[t], acc[a][t]);
     }
   }
   // scatter to theta layout: position p = qq*NS + i holds logical feature lc(qq, i)
