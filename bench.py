@@ -36,6 +36,34 @@ def flops_per_eval(n, n_edges, F, L):
     return L * (2 * n * 2 * F * F + 2 * (2 * n_edges) * F) + 2 * 2 * n * F
 
 
+def source_hash() -> str:
+    """sha256[:16] of the HIP sources, to tie stored counter readings to a build."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2011_12453_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(workload: str, precision: str):
+    """HBM bytes per k_eloc launch from the committed FETCH_SIZE/WRITE_SIZE summary,
+    or None when there is none for this workload or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"k_eloc_{workload.split('_')[0]}_{precision}_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "source_sha256_16"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_sha256_16") != source_hash():
+        return None
+    return int(vals["traffic_bytes_per_launch"]) if "traffic_bytes_per_launch" in vals else None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -49,6 +77,8 @@ def main():
     ap.add_argument("--cpu-samples", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline steps only (for profilers)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -71,6 +101,16 @@ def main():
     spins_np = w.random_sz0_spins(B, n, p.spin_seed)
     fpe = flops_per_eval(n, len(e), F, L)
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
+
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: 3 copies of {nbytes} bytes")
+        del src, dst
 
     # ---------------- headline: whole step ----------------
     g = GNA(n, e, F, L, tied=True, precision=args.precision, max_batch=B, device=dev)
@@ -116,7 +156,8 @@ def main():
     achieved = (swapped / max(kl, 1)) * fpe / (eloc_ms * 1e-3) if kl else 0.0
     roofline = {"bound": "mfma", "kernel": "k_eloc", "achieved": achieved / 1e12,
                 "peak": PEAK[args.precision] / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK[args.precision], "traffic": None,
+                "frac": achieved / PEAK[args.precision],
+                "traffic": stored_traffic(p.name, args.precision),
                 "launch_ms": eloc_ms, "flops_per_eval": fpe}
 
     # ---------------- E_loc alone, every precision ----------------
