@@ -797,6 +797,10 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
   }
   g.wpc = (g.ntiles + tpw - 1) / tpw;
   if (g.wpc > max_waves(tpw)) return bail(GNA_UNSUPPORTED, "n_sites too large for one workgroup (max 512)");
+  // every wave owns exactly tpw tiles: padding nodes (zero adjacency, left out of the
+  // readout) fill the last ones, so the kernels need no per-tile branches
+  g.ntiles = g.wpc * tpw;
+  g.npad = 16 * g.ntiles;
   c->tpw = tpw;
   const size_t w_bytes = (size_t)2 * F * F * c->sz_W;
   auto layout = [&](int nch, int nbuf) -> size_t {

@@ -214,8 +214,8 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32
 // ---------------------------------------------------------------------------
 struct Geo {
   int wpc;        // waves per workgroup; the workgroup evaluates one configuration
-  int ntiles;     // ceil(N / 16) node tiles
-  int npad;       // 16 * ntiles
+  int ntiles;     // node tiles: wpc * TPW >= ceil(N / 16), every wave owns TPW of them
+  int npad;       // 16 * ntiles (nodes past N are padding with zero adjacency)
   int nbuf;       // 1 or 2 gather buffers
   int row_elems;  // gather-buffer row stride in elements of Acc
   int buf_elems;  // elements of Acc per gather buffer
@@ -419,7 +419,7 @@ __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
 #pragma unroll
   for (int k = 0; k < TPW; ++k) {
     const int tile = wv + k * wpc;
-    tile_ok[k] = tile < g.ntiles;
+    tile_ok[k] = true;   // ntiles == wpc * TPW: every tile slot holds a tile
     node[k] = tile * 16 + col;
     real[k] = tile_ok[k] && node[k] < net.n;
     int x = 0;
@@ -548,8 +548,9 @@ __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
         Acc m[CS];
 #pragma unroll
         for (int i = 0; i < CS; ++i) m[i] = (Acc)0;
-        // the neighbour list is padded to a multiple of 4 (zero weights)
-        for (int d = 0; d < net.dmax; d += 4) {
+        // the neighbour list is padded to a multiple of 4 (zero weights); degree-4
+        // graphs (Kagome) take the straight-line path
+        auto gather4 = [&](int d) {
           Acc row[4][CS];
 #pragma unroll
           for (int u = 0; u < 4; ++u) lds_read<Acc, CS>(hb + ip[d + u] * g.row_elems + q * CS, row[u]);
@@ -559,6 +560,11 @@ __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
 #pragma unroll
             for (int i = 0; i < CS; ++i) m[i] += a * row[u][i];
           }
+        };
+        if (net.dmax == 4) {
+          gather4(0);
+        } else {
+          for (int d = 0; d < net.dmax; d += 4) gather4(d);
         }
 #pragma unroll
         for (int tc = 0; tc < MTC; ++tc)
