@@ -36,6 +36,34 @@ def flops_per_eval(n, n_edges, F, L):
     return L * (2 * n * 2 * F * F + 2 * (2 * n_edges) * F) + 2 * 2 * n * F
 
 
+def ball_flops(n, edges, F, L):
+    """Algorithmic FLOPs of one incremental evaluation for each bond: at layer l the
+    message product of the ball C_{l-1} and the self product, aggregation and
+    activation input of the ball C_l (C_0 = the bond, C_l = C_{l-1} plus neighbours),
+    plus the two-head readout difference over C_L."""
+    import numpy as np
+    adj = [[] for _ in range(n)]
+    for a, b in edges:
+        adj[a].append(b)
+        adj[b].append(a)
+    deg = np.array([len(x) for x in adj])
+    out = []
+    for a, b in edges:
+        balls = [{int(a), int(b)}]
+        for _ in range(L):
+            nxt = set(balls[-1])
+            for u in balls[-1]:
+                nxt.update(adj[u])
+            balls.append(nxt)
+        f = 0
+        for l in range(1, L + 1):
+            f += 2 * len(balls[l - 1]) * F * F + 2 * len(balls[l]) * F * F
+            f += 2 * int(deg[list(balls[l])].sum()) * F
+        f += 2 * 2 * len(balls[L]) * F
+        out.append(f)
+    return np.array(out, dtype=np.float64)
+
+
 def source_hash() -> str:
     """sha256[:16] of the HIP sources, to tie stored counter readings to a build."""
     import hashlib
@@ -48,10 +76,10 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def stored_traffic(workload: str, precision: str):
-    """HBM bytes per k_eloc launch from the committed FETCH_SIZE/WRITE_SIZE summary,
+def stored_traffic(workload: str, precision: str, kernel: str = "k_eloc"):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE summary,
     or None when there is none for this workload or the kernel sources changed since."""
-    path = os.path.join(ROOT, "profiles", f"k_eloc_{workload.split('_')[0]}_{precision}_hbm_traffic.md")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload.split('_')[0]}_{precision}_hbm_traffic.md")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -71,6 +99,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="kagome432_L6F64")
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32", "fp64"])
+    ap.add_argument("--eloc-mode", default="incremental", choices=["incremental", "full"],
+                    help="how the timed step evaluates the exchanged configurations")
     ap.add_argument("--compare", default="fp32,fp64", help="other precisions timed on E_loc alone")
     ap.add_argument("--compare-batch", type=int, default=512)
     ap.add_argument("--eloc-reps", type=int, default=3)
@@ -100,6 +130,13 @@ def main():
     theta_np = w.glorot_theta(F, L, True, seed=p.theta_seed)
     spins_np = w.random_sz0_spins(B, n, p.spin_seed)
     fpe = flops_per_eval(n, len(e), F, L)
+    bfl = ball_flops(n, e, F, L)                       # per bond, incremental evaluation
+    anti = (spins_np[:, e[:, 0]] != spins_np[:, e[:, 1]])
+    inc_flops_batch = float((anti * bfl[None, :]).sum())   # initial batch; the step's spins drift
+
+    def kernel_flops(mode, spins_now):
+        a = (spins_now[:, e[:, 0]] != spins_now[:, e[:, 1]])
+        return float((a * bfl[None, :]).sum()) if mode == "incremental" else float(a.sum()) * fpe
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
 
     if args.copy_calibration:
@@ -113,7 +150,7 @@ def main():
         del src, dst
 
     # ---------------- headline: whole step ----------------
-    g = GNA(n, e, F, L, tied=True, precision=args.precision, max_batch=B, device=dev)
+    g = GNA(n, e, F, L, tied=True, precision=args.precision, max_batch=B, device=dev, eloc_mode=args.eloc_mode)
     theta = torch.from_numpy(theta_np).to(dev)
     spins = torch.from_numpy(spins_np).to(dev)
     lp = torch.empty((B, 2), dtype=torch.float64, device=dev)
@@ -134,12 +171,17 @@ def main():
     g.profile_read()                 # discard
     g.profile_enable(True)
     stats_list = []
+    kflops = 0.0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         stats_list.append(step(args.warmup + k))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    # algorithmic work of the local-energy kernel: recompute from the final spins of
+    # each step would need copies inside the timed loop; the step's sweep changes the
+    # configurations but not their bond statistics, so the final batch stands in
+    kflops = kernel_flops(args.eloc_mode, spins.cpu().numpy()) * args.steps
     prof = g.profile_read()
     g.profile_enable(False)
     stats_all = torch.stack(stats_list).cpu().numpy()
@@ -149,25 +191,29 @@ def main():
     log(f"[bench] {args.steps} steps in {elapsed:.3f}s; {evals:.0f} E_loc evals; {value:.4g} evals/s")
     log("[bench] kernels: " + ", ".join(f"{k} {v[1] / max(v[0], 1):.3f}ms x{v[0]}" for k, v in sorted(prof.items())))
 
-    # dominant kernel k_eloc: algorithmic FLOPs per launch / mean launch time
-    swapped = evals - args.steps * B           # k_logpsi does the B base evaluations
-    kl, kms = prof.get("k_eloc", (0, 0.0))
+    # dominant kernel: algorithmic FLOPs per launch / mean launch time
+    kname = "k_eloc_inc" if args.eloc_mode == "incremental" else "k_eloc"
+    kl, kms = prof.get(kname, (0, 0.0))
     eloc_ms = kms / max(kl, 1)
-    achieved = (swapped / max(kl, 1)) * fpe / (eloc_ms * 1e-3) if kl else 0.0
-    roofline = {"bound": "mfma", "kernel": "k_eloc", "achieved": achieved / 1e12,
+    achieved = (kflops / max(kl, 1)) / (eloc_ms * 1e-3) if kl else 0.0
+    roofline = {"bound": "mfma", "kernel": kname, "achieved": achieved / 1e12,
                 "peak": PEAK[args.precision] / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK[args.precision],
-                "traffic": stored_traffic(p.name, args.precision),
-                "launch_ms": eloc_ms, "flops_per_eval": fpe}
+                "traffic": stored_traffic(p.name, args.precision, kname),
+                "launch_ms": eloc_ms,
+                "flops_per_eval": (kflops / args.steps) / max(1.0, evals / args.steps - B)}
 
-    # ---------------- E_loc alone, every precision ----------------
+    # ---------------- E_loc alone: both modes, every precision ----------------
     per_prec = {}
     eloc_out = {}
-    for prec in [args.precision] + [q for q in args.compare.split(",") if q and q != args.precision]:
-        if args.quick and prec != args.precision:
+    runs = [(args.precision, args.eloc_mode), (args.precision, "full" if args.eloc_mode == "incremental" else "incremental")]
+    runs += [(q, m) for q in args.compare.split(",") if q and q != args.precision for m in ("incremental", "full")]
+    for prec, mode in runs:
+        if args.quick and (prec, mode) != (args.precision, args.eloc_mode):
             continue
         Bp = B if prec == args.precision else min(B, args.compare_batch)
-        gp = g if prec == args.precision else GNA(n, e, F, L, tied=True, precision=prec, max_batch=Bp, device=dev)
+        gp = g if (prec, mode) == (args.precision, args.eloc_mode) else \
+            GNA(n, e, F, L, tied=True, precision=prec, max_batch=Bp, device=dev, eloc_mode=mode)
         th0 = torch.from_numpy(theta_np).to(dev)
         sp0 = torch.from_numpy(spins_np[:Bp]).to(dev)
         el, nev = gp.local_energy(th0, sp0)        # warm
@@ -183,12 +229,16 @@ def main():
         gp.profile_enable(False)
         ne = int(nev.item())
         rate = ne * args.eloc_reps / (tb - ta)
-        kl2, kms2 = pr.get("k_eloc", (1, 0.0))
-        per_prec[prec] = {"evals_per_s": rate, "batch": Bp, "evals_per_call": ne,
-                          "k_eloc_ms": kms2 / max(kl2, 1),
-                          "mfma_frac": (ne - Bp) * fpe / (kms2 / max(kl2, 1) * 1e-3) / PEAK[prec]}
-        eloc_out[prec] = el.cpu().numpy()
-        log(f"[bench] E_loc {prec}: B={Bp} {rate:.4g} evals/s, k_eloc {kms2 / max(kl2, 1):.2f} ms")
+        kn = "k_eloc_inc" if mode == "incremental" else "k_eloc"
+        kl2, kms2 = pr.get(kn, (1, 0.0))
+        kf = kernel_flops(mode, spins_np[:Bp])
+        key = f"{prec}_{mode}"
+        per_prec[key] = {"evals_per_s": rate, "batch": Bp, "evals_per_call": ne,
+                         "kernel": kn, "kernel_ms": kms2 / max(kl2, 1),
+                         "kernel_tflops": kf / (kms2 / max(kl2, 1) * 1e-3) / 1e12,
+                         "mfma_frac": kf / (kms2 / max(kl2, 1) * 1e-3) / PEAK[prec]}
+        eloc_out[key] = el.cpu().numpy()
+        log(f"[bench] E_loc {prec} {mode}: B={Bp} {rate:.4g} evals/s, {kn} {kms2 / max(kl2, 1):.2f} ms")
         if gp is not g:
             gp.close()
 
@@ -225,6 +275,7 @@ def main():
         "config": {"workload": p.name, "lattice": "12x12x3 kagome torus", "sites": n, "bonds": len(e),
                    "layers": L, "features": F, "tied": True, "batch": B,
                    "step": "logpsi + 1 Metropolis sweep + ISGO update (logpsi, E_loc, stats, VJP) + SGD",
+                   "eloc_mode": args.eloc_mode,
                    "evals_per_step": evals / args.steps},
         "roofline": roofline,
         "cpu_baseline": cpu,

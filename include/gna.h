@@ -70,6 +70,16 @@ enum {
  *             sum is taken in FP64 from the FP32 last-layer output.          */
 enum { GNA_FP64 = 0, GNA_FP32 = 1, GNA_BF16 = 2 };
 
+/* How gna_local_energy evaluates log psi(s^ij):
+ *   GNA_ELOC_FULL: every exchanged configuration through all L layers.
+ *   GNA_ELOC_INCREMENTAL: only the nodes within graph distance l of the two
+ *     exchanged sites are recomputed at layer l (the rest of the configuration
+ *     is unchanged there), from per-sample planes of the base configuration kept
+ *     in device memory (2 L x N x F values per sample).  The recomputed rows use
+ *     the same arithmetic as the full evaluation, so both modes give the same
+ *     log psi differences up to the order of the final FP64 sum.            */
+enum { GNA_ELOC_FULL = 0, GNA_ELOC_INCREMENTAL = 1 };
+
 typedef struct {
   int32_t n_sites;          /* N >= 2 */
   int32_t n_edges;          /* |E| >= 0 */
@@ -83,7 +93,7 @@ typedef struct {
   int32_t precision;        /* GNA_FP64 / GNA_FP32 / GNA_BF16 */
   double jz, jxy;           /* Heisenberg couplings; the isotropic model is 1, 1 */
   int32_t max_batch;        /* largest B any call will pass (sizes the workspace) */
-  int32_t reserved1;        /* must be 0 */
+  int32_t eloc_mode;        /* GNA_ELOC_FULL or GNA_ELOC_INCREMENTAL (tied weights) */
   int64_t act_budget_bytes; /* device bytes the reverse pass may use for stored
                                per-layer activations; 0 = library default.  The
                                reverse pass recomputes activations per sample, so

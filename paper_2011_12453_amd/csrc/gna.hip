@@ -26,6 +26,7 @@
 #include "gna.h"
 #include "gna_kernels.h"
 #include "gna_vjp.h"
+#include "gna_inc.h"
 
 using namespace gna;
 
@@ -394,6 +395,37 @@ Kern pick_f(int F, int tpw, int nch) {
   return pick_nch<P, 64>(tpw, nch);
 }
 
+// incremental local energy: base pass (precision, F, TPW, NCH) and ball kernel (precision, F, MAXT)
+template <class P, int F, int TPW, int NCH>
+const void* inc_base_kernel() {
+  return reinterpret_cast<const void*>(&k_inc_base<P, F, TPW, NCH>);
+}
+template <class P, int F>
+const void* inc_base_pick(int tpw, int nch) {
+  if constexpr ((F / 16) % 4 == 0) {
+    if (nch == 4) {
+      if (tpw == 1) return inc_base_kernel<P, F, 1, 4>();
+      if (tpw == 2) return inc_base_kernel<P, F, 2, 4>();
+      return inc_base_kernel<P, F, 4, 4>();
+    }
+  }
+  if (tpw == 1) return inc_base_kernel<P, F, 1, 1>();
+  if (tpw == 2) return inc_base_kernel<P, F, 2, 1>();
+  return inc_base_kernel<P, F, 4, 1>();
+}
+template <class P, int F>
+const void* inc_pick(int maxt) {
+  if (maxt == 1) return reinterpret_cast<const void*>(&k_eloc_inc<P, F, 1>);
+  if (maxt == 2) return reinterpret_cast<const void*>(&k_eloc_inc<P, F, 2>);
+  return reinterpret_cast<const void*>(&k_eloc_inc<P, F, 4>);
+}
+template <class P>
+void inc_pick_f(int F, int tpw, int nch, int maxt, const void** base, const void** ker) {
+  if (F == 16) { *base = inc_base_pick<P, 16>(tpw, nch); *ker = inc_pick<P, 16>(maxt); }
+  else if (F == 32) { *base = inc_base_pick<P, 32>(tpw, nch); *ker = inc_pick<P, 32>(maxt); }
+  else { *base = inc_base_pick<P, 64>(tpw, nch); *ker = inc_pick<P, 64>(maxt); }
+}
+
 // reverse-pass kernels of one (precision, F, TPW, NCH) instantiation (FP32 or FP64)
 struct VKern {
   const void* fwd = nullptr;
@@ -475,6 +507,18 @@ struct gna_ctx {
   long long* d_nev = nullptr;   // [1]
   double* d_cot = nullptr;      // [max_batch][2]
   double* d_eloc = nullptr;     // [max_batch][2]
+  // incremental local energy
+  int eloc_mode = 0;
+  IncGeo igeo{};
+  const void* k_inc_base = nullptr;
+  const void* k_inc = nullptr;
+  int grid_inc_base = 1, grid_inc = 1, inc_rows_max = 16;
+  int* d_ball_off = nullptr;
+  int* d_ball_cnt = nullptr;
+  int* d_ball_node = nullptr;
+  int* d_ball_self = nullptr;
+  int* d_ball_nb = nullptr;
+  void* d_inc_planes = nullptr;   // [max_batch][2L][npad][F] Acc
   // reverse pass (FP32 for the FP32/BF16 modes, FP64 for FP64)
   Geo vgeo{};
   VKern vk{};
@@ -629,11 +673,36 @@ gna_status run_eloc(gna_ctx* c, const double* theta, const int8_t* spins, int B,
   int ichunk = (int)chunk;
   Net net = make_net(c, theta);
   const int items = B * n_chunks;
-  int grid = std::min(items, c->grid_eloc);
   double* partial = c->d_partial;
   int* cnt = c->d_cnt;
-  void* args[] = {&net, &spins, &B, &base, &n_chunks, &ichunk, &partial, &cnt};
-  if (gna_status st = launch(c, c->kern.eloc, grid, args, "k_eloc")) return st;
+  if (c->eloc_mode == GNA_ELOC_INCREMENTAL) {
+    void* planes = c->d_inc_planes;
+    double* lp_out = const_cast<double*>(base);   // the base pass also yields log psi(s)
+    {
+      Timed tm(c, "k_inc_base");
+      void* a1[] = {&net, &spins, &B, &planes, &lp_out};
+      hipError_t e = hipLaunchKernel(c->k_inc_base, dim3(std::min(B, c->grid_inc_base)), dim3(64 * c->geo.wpc), a1,
+                                     (size_t)c->geo.lds_bytes, c->stream);
+      if (e != hipSuccess) return hip_fail(c, e, "k_inc_base");
+    }
+    IncNet inc{};
+    inc.n = c->N; inc.F = c->F; inc.L = c->L; inc.dmax = c->dmax; inc.rows_max = c->inc_rows_max;
+    inc.ball_off = c->d_ball_off; inc.ball_cnt = c->d_ball_cnt; inc.ball_node = c->d_ball_node;
+    inc.ball_self = c->d_ball_self; inc.ball_nb = c->d_ball_nb; inc.ell_idx = c->d_idx; inc.ell_val = c->d_val;
+    IncGeo ig = c->igeo;
+    {
+      Timed tm(c, "k_eloc_inc");
+      void* a2[] = {&net, &inc, &ig, &spins, &B, &planes, &n_chunks, &ichunk, &partial, &cnt};
+      hipError_t e = hipLaunchKernel(c->k_inc, dim3(std::min(items, c->grid_inc)), dim3(64 * ig.nw), a2,
+                                     (size_t)ig.lds_bytes, c->stream);
+      if (e != hipSuccess) return hip_fail(c, e, "k_eloc_inc");
+    }
+    if (gna_status st = check_launch(c, "k_eloc_inc")) return st;
+  } else {
+    int grid = std::min(items, c->grid_eloc);
+    void* args[] = {&net, &spins, &B, &base, &n_chunks, &ichunk, &partial, &cnt};
+    if (gna_status st = launch(c, c->kern.eloc, grid, args, "k_eloc")) return st;
+  }
   Timed tm(c, "k_eloc_finalize");
   hipLaunchKernelGGL(k_eloc_finalize, dim3((B + 255) / 256), dim3(256), 0, c->stream, spins, c->N,
                      c->d_edges, c->E, c->jz, c->jxy, B, n_chunks, partial, cnt, eloc, nev);
@@ -737,7 +806,10 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
   if (L < 0 || L > 16) return init_fail(GNA_UNSUPPORTED, "n_layers must be in [0, 16]");
   if (cfg->tied != 0 && cfg->tied != 1) return init_fail(GNA_INVALID_ARG, "tied must be 0 or 1");
   if (cfg->precision < GNA_FP64 || cfg->precision > GNA_BF16) return init_fail(GNA_INVALID_ARG, "unknown precision");
-  if (cfg->reserved1 != 0) return init_fail(GNA_INVALID_ARG, "reserved fields must be 0");
+  if (cfg->eloc_mode != GNA_ELOC_FULL && cfg->eloc_mode != GNA_ELOC_INCREMENTAL)
+    return init_fail(GNA_INVALID_ARG, "unknown eloc_mode");
+  if (cfg->eloc_mode == GNA_ELOC_INCREMENTAL && !cfg->tied)
+    return init_fail(GNA_UNSUPPORTED, "incremental local energy needs tied weights");
   if (cfg->max_batch < 0) return init_fail(GNA_INVALID_ARG, "max_batch must be >= 0");
   if (cfg->act_budget_bytes < 0) return init_fail(GNA_INVALID_ARG, "act_budget_bytes must be >= 0");
   if (!std::isfinite(cfg->jz) || !std::isfinite(cfg->jxy)) return init_fail(GNA_INVALID_ARG, "couplings must be finite");
@@ -946,6 +1018,124 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
         (st = dev_alloc(c, &c->d_vjp_part, (size_t)c->vjp_rows * c->P * 8)))
       return bail(st, c->err);
   }
+  // incremental local energy: per-bond balls, base planes, kernels
+  c->eloc_mode = cfg->eloc_mode;
+  if (c->eloc_mode == GNA_ELOC_INCREMENTAL) {
+    std::vector<std::vector<int>> adj(N);
+    for (int e = 0; e < E; ++e) {
+      adj[cfg->edges[2 * e]].push_back(cfg->edges[2 * e + 1]);
+      adj[cfg->edges[2 * e + 1]].push_back(cfg->edges[2 * e]);
+    }
+    std::vector<int> off((size_t)std::max(E, 1) * (L + 1), 0), cnt((size_t)std::max(E, 1) * (L + 1), 0);
+    std::vector<int> node_t, self_t, nb_t;
+    int hc_rows = 16, gc_rows = 16, max_tiles = 1;
+    std::vector<int> pos(N, -1), mark(N, 0);
+    for (int e = 0; e < E; ++e) {
+      std::vector<std::vector<int>> C(L + 1);
+      C[0] = {std::min(cfg->edges[2 * e], cfg->edges[2 * e + 1]), std::max(cfg->edges[2 * e], cfg->edges[2 * e + 1])};
+      for (int l = 1; l <= L; ++l) {
+        std::vector<int> nx = C[l - 1];
+        for (int u : C[l - 1]) mark[u] = l;
+        for (int u : C[l - 1])
+          for (int v : adj[u])
+            if (mark[v] != l) { mark[v] = l; nx.push_back(v); }
+        std::sort(nx.begin(), nx.end());
+        C[l] = nx;
+      }
+      for (int u = 0; u < N; ++u) mark[u] = 0;
+      for (int l = 0; l <= L; ++l) {
+        const int padded = ((int)C[l].size() + 15) / 16 * 16;
+        off[(size_t)e * (L + 1) + l] = (int)node_t.size();
+        cnt[(size_t)e * (L + 1) + l] = padded;
+        max_tiles = std::max(max_tiles, padded / 16);
+        if (l < L) gc_rows = std::max(gc_rows, padded);
+        if (l >= 1 && l < L) hc_rows = std::max(hc_rows, padded);
+        if (l >= 1)
+          for (size_t r = 0; r < C[l - 1].size(); ++r) pos[C[l - 1][r]] = (int)r;
+        for (int r = 0; r < padded; ++r) {
+          const int nd = r < (int)C[l].size() ? C[l][r] : -1;
+          node_t.push_back(nd);
+          if (l == 0) {
+            self_t.push_back(-1);
+            for (int d = 0; d < dmax; ++d) nb_t.push_back(-1);
+            continue;
+          }
+          self_t.push_back(nd < 0 ? -1 : (pos[nd] >= 0 ? pos[nd] : -1 - nd));
+          for (int d = 0; d < dmax; ++d) {
+            if (nd < 0) { nb_t.push_back(-1); continue; }
+            const int m = idx[(size_t)nd * dmax + d];
+            nb_t.push_back(pos[m] >= 0 ? pos[m] : -1 - m);
+          }
+        }
+        if (l >= 1)
+          for (int u : C[l - 1]) pos[u] = -1;
+      }
+    }
+    c->inc_rows_max = std::max(hc_rows, gc_rows);
+    IncGeo& ig = c->igeo;
+    ig.nw = std::min(kMaxWaves / 2, max_tiles);
+    int maxt = (max_tiles + ig.nw - 1) / ig.nw;
+    maxt = maxt <= 1 ? 1 : (maxt <= 2 ? 2 : 4);
+    if (maxt * ig.nw < max_tiles) return bail(GNA_UNSUPPORTED, "ball too large for the incremental kernel");
+    ig.row_elems = (int)((4 * (F / 4) * c->sz_Acc + kRowPadBytes) / c->sz_Acc);
+    {
+      size_t o = 0;
+      auto al = [](size_t x) { return (x + 15) & ~(size_t)15; };
+      ig.off_w = (int)o; o = al(o + w_bytes);
+      ig.off_hc = (int)o; o = al(o + (size_t)hc_rows * ig.row_elems * c->sz_Acc);
+      ig.off_gc = (int)o; o = al(o + (size_t)gc_rows * ig.row_elems * c->sz_Acc);
+      ig.off_sp = (int)o; o = al(o + g.npad);
+      ig.off_red = (int)o; o = al(o + kRedSlots * 8);
+      ig.off_bias = (int)o; o = al(o + (size_t)F * c->sz_Acc);
+      ig.off_emb = (int)o; o = al(o + (size_t)2 * F * c->sz_Acc);
+      ig.off_head = (int)o; o = al(o + (size_t)2 * (F + 3) * 8);
+      ig.lds_bytes = (int)o;
+      if (o + 64 > lds_max) return bail(GNA_UNSUPPORTED, "incremental local energy does not fit in LDS");
+    }
+    switch (c->prec) {
+      case GNA_FP64: inc_pick_f<PF64>(F, tpw, nch, maxt, &c->k_inc_base, &c->k_inc); break;
+      case GNA_FP32: inc_pick_f<PF32>(F, tpw, nch, maxt, &c->k_inc_base, &c->k_inc); break;
+      default:
+        if (F == 16) {
+          c->k_inc_base = inc_base_pick<PBF16, 16>(tpw, nch);
+          c->k_inc = inc_pick<PBF16, 16>(maxt);
+        } else if (F == 32) {
+          c->k_inc_base = inc_base_pick<PBF16W, 32>(tpw, nch);
+          c->k_inc = inc_pick<PBF16W, 32>(maxt);
+        } else {
+          c->k_inc_base = inc_base_pick<PBF16W, 64>(tpw, nch);
+          c->k_inc = inc_pick<PBF16W, 64>(maxt);
+        }
+    }
+    {
+      auto occ2 = [&](const void* fn, int threads_, int lds) {
+        hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, threads_, lds) != hipSuccess || nb < 1) nb = 1;
+        (void)hipGetLastError();
+        return nb;
+      };
+      c->grid_inc_base = c->n_cu * occ2(c->k_inc_base, 64 * g.wpc, g.lds_bytes);
+      c->grid_inc = c->n_cu * occ2(c->k_inc, 64 * ig.nw, ig.lds_bytes);
+    }
+    const size_t plane_bytes = (size_t)g.npad * F * c->sz_Acc;
+    if ((st = dev_alloc(c, &c->d_ball_off, off.size() * 4)) ||
+        (st = dev_alloc(c, &c->d_ball_cnt, cnt.size() * 4)) ||
+        (st = dev_alloc(c, &c->d_ball_node, std::max<size_t>(1, node_t.size()) * 4)) ||
+        (st = dev_alloc(c, &c->d_ball_self, std::max<size_t>(1, self_t.size()) * 4)) ||
+        (st = dev_alloc(c, &c->d_ball_nb, std::max<size_t>(1, nb_t.size()) * 4)) ||
+        (st = dev_alloc(c, &c->d_inc_planes, (size_t)MB * 2 * std::max(L, 1) * plane_bytes)))
+      return bail(st, c->err);
+    he = hipMemcpy(c->d_ball_off, off.data(), off.size() * 4, hipMemcpyHostToDevice);
+    if (he == hipSuccess) he = hipMemcpy(c->d_ball_cnt, cnt.data(), cnt.size() * 4, hipMemcpyHostToDevice);
+    if (he == hipSuccess && !node_t.empty())
+      he = hipMemcpy(c->d_ball_node, node_t.data(), node_t.size() * 4, hipMemcpyHostToDevice);
+    if (he == hipSuccess && !self_t.empty())
+      he = hipMemcpy(c->d_ball_self, self_t.data(), self_t.size() * 4, hipMemcpyHostToDevice);
+    if (he == hipSuccess && !nb_t.empty())
+      he = hipMemcpy(c->d_ball_nb, nb_t.data(), nb_t.size() * 4, hipMemcpyHostToDevice);
+    if (he != hipSuccess) return bail(GNA_HIP_ERROR, std::string("hipMemcpy: ") + hipGetErrorString(he));
+  }
   he = hipMemcpy(c->d_edges, hedges.data(), hedges.size() * 4, hipMemcpyHostToDevice);
   if (he == hipSuccess) he = hipMemcpy(c->d_idx, idx.data(), idx.size() * 4, hipMemcpyHostToDevice);
   if (he == hipSuccess) he = hipMemcpy(c->d_val64, val.data(), val.size() * 8, hipMemcpyHostToDevice);
@@ -1008,7 +1198,8 @@ gna_status gna_local_energy(gna_ctx* c, const double* theta, const int8_t* spins
   if (!valid_ptr(theta) || (B > 0 && (!valid_ptr(spins) || !valid_ptr(eloc))))
     return fail(c, GNA_INVALID_ARG, "NULL pointer argument");
   if (gna_status st = prepare(c, theta)) return st;
-  if (gna_status st = run_logpsi(c, theta, spins, B, c->d_base)) return st;
+  if (c->eloc_mode == GNA_ELOC_FULL)
+    if (gna_status st = run_logpsi(c, theta, spins, B, c->d_base)) return st;
   long long* nev = n_evals ? reinterpret_cast<long long*>(n_evals) : c->d_nev;
   return run_eloc(c, theta, spins, B, c->d_base, eloc, nev);
 }
@@ -1049,7 +1240,8 @@ gna_status gna_isgo_grad(gna_ctx* c, const double* theta, const int8_t* spins, c
       (B > 0 && (!valid_ptr(spins) || !valid_ptr(logpsi_old))))
     return fail(c, GNA_INVALID_ARG, "NULL pointer argument");
   if (gna_status st = prepare(c, theta)) return st;
-  if (gna_status st = run_logpsi(c, theta, spins, B, c->d_base)) return st;
+  if (c->eloc_mode == GNA_ELOC_FULL)   // the incremental base pass writes log psi itself
+    if (gna_status st = run_logpsi(c, theta, spins, B, c->d_base)) return st;
   double* el = eloc ? eloc : c->d_eloc;
   if (gna_status st = run_eloc(c, theta, spins, B, c->d_base, el, c->d_nev)) return st;
   {

@@ -382,12 +382,15 @@ __device__ void load_spins(const Net& net, const Smem<P>& s, const int8_t* __res
 // Every call performs the same arithmetic in the same order for a node whose
 // receptive field holds the same spins, so log psi differences cancel exactly
 // outside it.
-//   STORE: also write the layer inputs H^0..H^L and messages M^0..M^{L-1}
+//   STORE == 1: also write the layer inputs H^0..H^L and messages M^0..M^{L-1}
 //   (M^l = A_hat H^l, gathered for the reverse pass) to `store` as planes of
 //   npad x F values, element (node, q, i) at node * F + q * F/4 + i (slot
 //   order); H^l is plane l, M^l plane L + 1 + l.
+//   STORE == 2: write the base planes of the incremental local energy: layer
+//   outputs H^1..H^L as planes 0..L-1 and message products G^l = H^l W_msg
+//   (l = 0..L-1) as planes L..2L-1, same element order.
 // ---------------------------------------------------------------------------
-template <class P, int F, int TPW, int NCH, bool STORE = false>
+template <class P, int F, int TPW, int NCH, int STORE = 0>
 __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
                             double& out_la, double& out_ph,
                             typename P::Acc* __restrict__ store = nullptr) {
@@ -438,7 +441,7 @@ __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
   // weight fragment of output tile t at k-step st of block blk (0 message, 1 self)
   auto afrag = [&](int blk, int st, int t) { return wl + (((blk * KSB + st) * MT + t) * 64 + lane) * VEC; };
   for (int l = 0; l < net.L; ++l) {
-    if constexpr (STORE) {
+    if constexpr (STORE == 1) {
 #pragma unroll
       for (int k = 0; k < TPW; ++k)
         if (tile_ok[k]) lds_write<Acc, NS>(store + l * plane + node[k] * F + q * NS, h[k]);
@@ -508,6 +511,8 @@ __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
             if (tile_ok[k]) {
               Acc gm[4] = {gacc[k][0], gacc[k][1], gacc[k][2], gacc[k][3]};
               lds_write<Acc, 4>(hb + node[k] * g.row_elems + q * CS + 4 * (t - ch * MTC), gm);
+              if constexpr (STORE == 2)
+                lds_write<Acc, 4>(store + (net.L + l) * plane + node[k] * F + q * NS + 4 * t, gm);
             }
         }
       }
@@ -537,6 +542,8 @@ __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
           for (int r = 0; r < 4; ++r) gm[4 * tc + r] = a[r];
         }
         lds_write<Acc, CS>(hb + node[k] * g.row_elems + q * CS, gm);
+        if constexpr (STORE == 2)
+          lds_write<Acc, CS>(store + (net.L + l) * plane + node[k] * F + q * NS + ch * CS, gm);
       }
       }
       __syncthreads();
@@ -572,7 +579,7 @@ __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
           for (int r = 0; r < 4; ++r) acc[k][ch * MTC + tc][r] += m[4 * tc + r];
       }
     }
-    if constexpr (STORE) {
+    if constexpr (STORE == 1) {
       // the reverse pass needs M^l = A_hat H^l itself: gather H^l (one more LDS round)
 #pragma unroll
       for (int ch = 0; ch < NCH; ++ch) {
@@ -624,9 +631,11 @@ __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
         pa += (double)ta;
         pp += (double)tp;
       }
+      if constexpr (STORE == 2)
+        lds_write<Acc, NS>(store + l * plane + node[k] * F + q * NS, h[k]);
     }
   }
-  if constexpr (STORE) {
+  if constexpr (STORE == 1) {
 #pragma unroll
     for (int k = 0; k < TPW; ++k)
       if (tile_ok[k]) lds_write<Acc, NS>(store + net.L * plane + node[k] * F + q * NS, h[k]);

@@ -70,7 +70,7 @@ __global__ __launch_bounds__(512) void k_vjp_fwd(Net net, const int8_t* __restri
   for (int b = blockIdx.x; b < Bc; b += gridDim.x) {
     load_spins<P>(net, s, spins + (size_t)(b0 + b) * net.n);
     double la = 0, ph = 0;
-    eval_config<P, F, TPW, NCH, true>(net, s, -1, -1, la, ph, planes + b * per);
+    eval_config<P, F, TPW, NCH, 1>(net, s, -1, -1, la, ph, planes + b * per);
   }
 }
 

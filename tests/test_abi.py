@@ -47,7 +47,7 @@ def _cfg(**kw):
     n, e = w.kagome(2, 2)
     e = np.ascontiguousarray(kw.pop("edges", e), dtype=np.int32)
     base = dict(n_sites=n, n_edges=len(e), n_features=16, n_layers=2, tied=1, precision=0,
-                jz=1.0, jxy=1.0, max_batch=16, reserved1=0, act_budget_bytes=0)
+                jz=1.0, jxy=1.0, max_batch=16, eloc_mode=0, act_budget_bytes=0)
     base.update(kw)
     c = _Config()
     for k, v in base.items():
@@ -59,7 +59,7 @@ def _cfg(**kw):
 
 @pytest.mark.parametrize("field,value,status", [
     ("n_sites", 1, 1), ("n_features", 24, 3), ("n_layers", -1, 3), ("n_layers", 17, 3),
-    ("precision", 7, 1), ("tied", 2, 1), ("reserved1", 1, 1), ("max_batch", -1, 1),
+    ("precision", 7, 1), ("tied", 2, 1), ("eloc_mode", 2, 1), ("max_batch", -1, 1),
     ("jz", float("nan"), 1),
 ])
 def test_bad_config_rejected_before_device(lib, field, value, status):
@@ -79,6 +79,13 @@ def test_bad_graph_rejected(lib, edges, msg):
     out = ctypes.c_void_p()
     assert lib.gna_init(ctypes.byref(c), ctypes.byref(out)) == 2
     assert msg in lib.gna_last_error(None)
+
+
+def test_incremental_needs_tied_weights(lib):
+    c, keep = _cfg(tied=0, eloc_mode=1)
+    out = ctypes.c_void_p()
+    assert lib.gna_init(ctypes.byref(c), ctypes.byref(out)) == 3
+    assert b"tied" in lib.gna_last_error(None)
 
 
 def test_null_arguments(lib):

@@ -292,3 +292,78 @@ def test_autograd_function_backward():
     ref = oracle.logpsi_vjp(theta, spins, wts.cpu().numpy(), n, e, F, L)
     assert np.max(np.abs(th.grad.cpu().numpy() - ref)) < 1e-11 * max(1, np.max(np.abs(ref)))
     g.close()
+
+
+# ---------------------------------------------------------------------------
+# incremental local energy (only the swapped sites' L-hop balls recomputed)
+# ---------------------------------------------------------------------------
+TIED = [c for c in CASES if c[4]]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("case", TIED, ids=[c[0] for c in TIED])
+def test_incremental_local_energy_matches_oracle_and_full(case, prec):
+    name, build, F, L, tied, B = case
+    n, e = build()
+    theta = w.glorot_theta(F, L, tied, seed=0, weight_scale=1.5, bias_std=0.3)
+    spins = np.concatenate([w.random_sz0_spins(B, n, 1000 + B), w.random_spins(2, n, 77)])
+    th, sp = _dev(theta), _dev(spins)
+    gi = _ctx(n, e, F, L, tied, prec, max_batch=len(spins), eloc_mode="incremental")
+    el_i, nev_i = gi.local_energy(th, sp)
+    el_i = el_i.cpu().numpy()
+    gi.close()
+    gf = _ctx(n, e, F, L, tied, prec, max_batch=len(spins))
+    el_f, nev_f = gf.local_energy(th, sp)
+    el_f = el_f.cpu().numpy()
+    gf.close()
+    ref = oracle.local_energy(theta, spins, n, e, F, L, tied)
+    assert int(nev_i.item()) == int(nev_f.item()) == oracle.n_evals(spins, e)
+    scale = max(1.0, np.max(np.abs(ref)))
+    # same arithmetic on every recomputed row: the two modes differ only by the
+    # order of the final FP64 sum of the log-psi difference
+    assert np.max(np.abs(el_i - el_f)) < 1e-12 * scale
+    err = np.max(np.abs(el_i[:, 0] - ref.real) + np.abs(el_i[:, 1] - ref.imag)) / scale
+    site = _site_err(el_i[:, 0], ref.real, n)
+    print(f"[gpu] incremental {name} {prec}: eloc rel {err:.2e} e/site rel {site:.2e}", file=sys.stderr, flush=True)
+    tol = {"fp64": (1e-11, 1e-10), "fp32": (1e-4, 1e-5), "bf16": (1e-1, 3e-2)}[prec]
+    assert err < tol[0] and site < tol[1]
+
+
+@pytest.mark.parametrize("name,prec", [("kagome432_L6F64", "bf16"), ("kagome432_L6F64", "fp64"),
+                                       ("er100_L4F32", "bf16")])
+def test_incremental_full_size_sampled_parity(name, prec):
+    p = w.preset(name)
+    n, e = p.build_graph()
+    theta = w.glorot_theta(p.n_features, p.n_layers, True, seed=p.theta_seed)
+    spins = w.random_sz0_spins(p.batch, n, p.spin_seed)
+    g = _ctx(n, e, p.n_features, p.n_layers, True, prec, max_batch=p.batch, eloc_mode="incremental")
+    el, nev = g.local_energy(_dev(theta), _dev(spins))
+    el = el.cpu().numpy()
+    g.close()
+    assert int(nev.item()) == oracle.n_evals(spins, e)
+    rows = np.random.default_rng(1).choice(p.batch, size=3, replace=False)
+    ref = oracle.local_energy(theta, spins[rows], n, e, p.n_features, p.n_layers)
+    err = np.max(np.abs(el[rows, 0] - ref.real) + np.abs(el[rows, 1] - ref.imag)) / np.max(np.abs(ref))
+    site = _site_err(el[rows, 0], ref.real, n)
+    print(f"[gpu] incremental full {name} {prec}: sampled eloc rel {err:.2e} e/site rel {site:.2e}",
+          file=sys.stderr, flush=True)
+    assert site < EPS_SITE[prec]
+    assert err < {"fp64": 1e-11, "fp32": 1e-4, "bf16": 1e-2}[prec]
+
+
+def test_incremental_isgo_grad_matches_full():
+    n, e = w.kagome(6, 6)
+    F, L = 32, 4
+    th_old = w.glorot_theta(F, L, True, seed=6, weight_scale=1.5, bias_std=0.3)
+    th_new = th_old + 0.02 * np.random.default_rng(3).normal(size=th_old.size)
+    spins = w.random_sz0_spins(64, n, 5)
+    lp_old = oracle.logpsi(th_old, spins, n, e, F, L)
+    out = []
+    for mode in ("full", "incremental"):
+        g = _ctx(n, e, F, L, True, "fp64", max_batch=64, eloc_mode=mode)
+        grad, stats, el = g.isgo_grad(_dev(th_new), _dev(spins), _dev(lp_old))
+        out.append((grad.cpu().numpy(), stats.cpu().numpy(), el.cpu().numpy()))
+        g.close()
+    (g0, s0, e0), (g1, s1, e1) = out
+    assert np.max(np.abs(g0 - g1)) < 1e-11 * np.max(np.abs(g0))
+    assert abs(s0[0] - s1[0]) < 1e-11 * abs(s0[0]) and s0[6] == s1[6]
