@@ -665,6 +665,11 @@ gna_status run_eloc(gna_ctx* c, const double* theta, const int8_t* spins, int B,
   const long long work = (long long)B * std::max(1, c->E);
   long long chunk = work / (16LL * c->grid_eloc);
   chunk = std::max<long long>(16, std::min<long long>(chunk, std::max(1, c->E)));
+  if (c->eloc_mode == GNA_ELOC_INCREMENTAL) {
+    // one sample per XCD at a time: as many chunks per sample as blocks per XCD
+    const int per_x = std::max(1, c->grid_inc / 8);
+    chunk = std::max<long long>(8, (std::max(1, c->E) + per_x - 1) / per_x);
+  }
   int n_chunks = (int)((std::max(1, c->E) + chunk - 1) / chunk);
   if (n_chunks > c->max_chunks) {
     n_chunks = c->max_chunks;
@@ -690,10 +695,12 @@ gna_status run_eloc(gna_ctx* c, const double* theta, const int8_t* spins, int B,
     inc.ball_off = c->d_ball_off; inc.ball_cnt = c->d_ball_cnt; inc.ball_node = c->d_ball_node;
     inc.ball_self = c->d_ball_self; inc.ball_nb = c->d_ball_nb; inc.ell_idx = c->d_idx; inc.ell_val = c->d_val;
     IncGeo ig = c->igeo;
+    int grid_i = std::min(items, c->grid_inc);
+    if (grid_i < ig.xcd || grid_i % ig.xcd) ig.xcd = 1;   // small launches: plain order
     {
       Timed tm(c, "k_eloc_inc");
       void* a2[] = {&net, &inc, &ig, &spins, &B, &planes, &n_chunks, &ichunk, &partial, &cnt};
-      hipError_t e = hipLaunchKernel(c->k_inc, dim3(std::min(items, c->grid_inc)), dim3(64 * ig.nw), a2,
+      hipError_t e = hipLaunchKernel(c->k_inc, dim3(grid_i), dim3(64 * ig.nw), a2,
                                      (size_t)ig.lds_bytes, c->stream);
       if (e != hipSuccess) return hip_fail(c, e, "k_eloc_inc");
     }
@@ -922,7 +929,7 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
   c->grid_logpsi = c->n_cu * occ(c->kern.logpsi);
   c->grid_eloc = c->n_cu * occ(c->kern.eloc);
   c->grid_sweep = c->n_cu * occ(c->kern.sweep);
-  c->max_chunks = std::max(1, (E + 15) / 16);
+  c->max_chunks = std::max(1, (E + 7) / 8);
 
   // ---- host graph tables: ELL (padding points at the node itself with value 0)
   std::vector<int> idx((size_t)g.npad * dmax);
@@ -1073,6 +1080,15 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
     }
     c->inc_rows_max = std::max(hc_rows, gc_rows);
     IncGeo& ig = c->igeo;
+    {
+      int most = 0;   // largest table of one bond, in ints
+      for (int e = 0; e < E; ++e) {
+        const int r0 = off[(size_t)e * (L + 1)], r1 = off[(size_t)e * (L + 1) + L] + cnt[(size_t)e * (L + 1) + L];
+        most = std::max(most, (r1 - r0) * (2 + dmax));
+      }
+      ig.tab_ints = std::max(most, 16);
+    }
+    ig.xcd = 8;   // MI355X: 8 XCDs, workgroups assigned round-robin
     ig.nw = std::min(kMaxWaves / 2, max_tiles);
     int maxt = (max_tiles + ig.nw - 1) / ig.nw;
     maxt = maxt <= 1 ? 1 : (maxt <= 2 ? 2 : 4);
@@ -1089,6 +1105,7 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
       ig.off_bias = (int)o; o = al(o + (size_t)F * c->sz_Acc);
       ig.off_emb = (int)o; o = al(o + (size_t)2 * F * c->sz_Acc);
       ig.off_head = (int)o; o = al(o + (size_t)2 * (F + 3) * 8);
+      ig.off_tab = (int)o; o = al(o + (size_t)ig.tab_ints * 4);
       ig.lds_bytes = (int)o;
       if (o + 64 > lds_max) return bail(GNA_UNSUPPORTED, "incremental local energy does not fit in LDS");
     }

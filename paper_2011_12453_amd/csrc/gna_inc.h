@@ -37,6 +37,9 @@ struct IncGeo {
   int nw;          // waves per workgroup
   int row_elems;   // LDS row stride in Acc elements
   int off_w, off_hc, off_gc, off_sp, off_red, off_bias, off_emb, off_head;
+  int off_tab;     // one bond's ball tables (node, self, neighbour codes)
+  int tab_ints;    // capacity in ints
+  int xcd;         // items are grouped per XCD (blocks b with equal b % xcd share a sample)
   int lds_bytes;
 };
 
@@ -84,9 +87,16 @@ __global__ __launch_bounds__(512) void k_eloc_inc(Net net, IncNet inc, IncGeo ig
   auto afrag = [&](int blk, int st, int t) { return wl + (((blk * KSB + st) * MT + t) * 64 + lane) * VEC; };
   const Acc* bias = sbias + q * NS;
 
-  const int items = B * n_chunks;
-  for (int it = blockIdx.x; it < items; it += gridDim.x) {
-    const int b = it / n_chunks, c = it % n_chunks;
+  int* tab = reinterpret_cast<int*>(smem + ig.off_tab);
+  // XCD-aware order: the blocks of one XCD (equal blockIdx % xcd) walk the chunks of
+  // the same samples together, so a sample's base planes stay in that XCD's L2
+  const int X = ig.xcd;
+  const int per_x = gridDim.x / X;
+  const int xid = blockIdx.x % X, slot = blockIdx.x / X;
+  const long long per_xcd_items = (long long)((B - xid + X - 1) / X) * n_chunks;
+  for (long long j = slot; j < per_xcd_items; j += per_x) {
+    const int b = xid + X * (int)(j / n_chunks), c = (int)(j % n_chunks);
+    const int it = b * n_chunks + c;
     for (int k = threadIdx.x; k < net.n; k += blockDim.x) sp[k] = spins[(size_t)b * net.n + k];
     __syncthreads();
     const Acc* pb = planes + (size_t)b * 2 * Lr * plane;
@@ -96,8 +106,23 @@ __global__ __launch_bounds__(512) void k_eloc_inc(Net net, IncNet inc, IncGeo ig
     for (int e = e0; e < e1; ++e) {
       const int2 ij = net.edges[e];
       if (sp[ij.x] == sp[ij.y]) continue;   // uniform across the workgroup
-      const int* boff = inc.ball_off + e * (Lr + 1);
-      const int* bcnt = inc.ball_cnt + e * (Lr + 1);
+      // this bond's tables -> LDS (rows of all layers: node, self code, neighbour codes)
+      const int* gofs = inc.ball_off + e * (Lr + 1);
+      const int* gcnt = inc.ball_cnt + e * (Lr + 1);
+      const int row0 = gofs[0], nrows = gofs[Lr] + gcnt[Lr] - row0;
+      const int dm = inc.dmax;
+      for (int k = threadIdx.x; k < nrows; k += blockDim.x) {
+        tab[k] = inc.ball_node[row0 + k];
+        tab[nrows + k] = inc.ball_self[row0 + k];
+      }
+      for (int k = threadIdx.x; k < nrows * dm; k += blockDim.x) tab[2 * nrows + k] = inc.ball_nb[(size_t)row0 * dm + k];
+      __syncthreads();
+      int boff[17], bcnt[17];
+#pragma unroll 1
+      for (int l = 0; l <= Lr; ++l) {
+        boff[l] = gofs[l] - row0;
+        bcnt[l] = gcnt[l];
+      }
       // spin of node nd in the exchanged configuration
       auto xnew = [&](int nd) {
         const int8_t v = (nd == ij.x) ? sp[ij.y] : ((nd == ij.y) ? sp[ij.x] : sp[nd]);
@@ -105,11 +130,11 @@ __global__ __launch_bounds__(512) void k_eloc_inc(Net net, IncNet inc, IncGeo ig
       };
       double pa = 0.0, pp = 0.0;
       for (int l = 1; l <= Lr; ++l) {
-        const int* rows_prev = inc.ball_node + boff[l - 1];
+        const int* rows_prev = tab + boff[l - 1];
         const int tprev = bcnt[l - 1] / 16;
-        const int* rows_cur = inc.ball_node + boff[l];
-        const int* self_cur = inc.ball_self + boff[l];
-        const int* nb_cur = inc.ball_nb + (size_t)boff[l] * inc.dmax;
+        const int* rows_cur = tab + boff[l];
+        const int* self_cur = tab + nrows + boff[l];
+        const int* nb_cur = tab + 2 * nrows + (size_t)boff[l] * dm;
         const int tcur = bcnt[l] / 16;
         const Acc* Hbase = pb + (size_t)(l - 2) * plane;           // H^{l-1} (l >= 2)
         const Acc* Gbase = pb + (size_t)(Lr + l - 1) * plane;      // G^{l-1}
