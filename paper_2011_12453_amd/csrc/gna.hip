@@ -417,6 +417,7 @@ template <class P, int F>
 const void* inc_pick(int maxt) {
   if (maxt == 1) return reinterpret_cast<const void*>(&k_eloc_inc<P, F, 1>);
   if (maxt == 2) return reinterpret_cast<const void*>(&k_eloc_inc<P, F, 2>);
+  if (maxt == 3) return reinterpret_cast<const void*>(&k_eloc_inc<P, F, 3>);
   return reinterpret_cast<const void*>(&k_eloc_inc<P, F, 4>);
 }
 template <class P>
@@ -512,12 +513,10 @@ struct gna_ctx {
   IncGeo igeo{};
   const void* k_inc_base = nullptr;
   const void* k_inc = nullptr;
-  int grid_inc_base = 1, grid_inc = 1, inc_rows_max = 16;
+  int grid_inc_base = 1, grid_inc = 1, inc_r4 = 4, inc_chunk_cap = 64;
   int* d_ball_off = nullptr;
   int* d_ball_cnt = nullptr;
-  int* d_ball_node = nullptr;
-  int* d_ball_self = nullptr;
-  int* d_ball_nb = nullptr;
+  int* d_ball_tab = nullptr;
   void* d_inc_planes = nullptr;   // [max_batch][2L][npad][F] Acc
   // reverse pass (FP32 for the FP32/BF16 modes, FP64 for FP64)
   Geo vgeo{};
@@ -666,9 +665,12 @@ gna_status run_eloc(gna_ctx* c, const double* theta, const int8_t* spins, int B,
   long long chunk = work / (16LL * c->grid_eloc);
   chunk = std::max<long long>(16, std::min<long long>(chunk, std::max(1, c->E)));
   if (c->eloc_mode == GNA_ELOC_INCREMENTAL) {
-    // one sample per XCD at a time: as many chunks per sample as blocks per XCD
+    // two samples per XCD at a time: half as many chunks per sample as blocks per XCD;
+    // a chunk holds at most one bond per thread of the workgroup
     const int per_x = std::max(1, c->grid_inc / 8);
-    chunk = std::max<long long>(8, (std::max(1, c->E) + per_x - 1) / per_x);
+    const int per_sample = std::max(1, per_x / 2);
+    chunk = std::max<long long>(8, (std::max(1, c->E) + per_sample - 1) / per_sample);
+    chunk = std::min<long long>(chunk, c->inc_chunk_cap);
   }
   int n_chunks = (int)((std::max(1, c->E) + chunk - 1) / chunk);
   if (n_chunks > c->max_chunks) {
@@ -691,9 +693,9 @@ gna_status run_eloc(gna_ctx* c, const double* theta, const int8_t* spins, int B,
       if (e != hipSuccess) return hip_fail(c, e, "k_inc_base");
     }
     IncNet inc{};
-    inc.n = c->N; inc.F = c->F; inc.L = c->L; inc.dmax = c->dmax; inc.rows_max = c->inc_rows_max;
-    inc.ball_off = c->d_ball_off; inc.ball_cnt = c->d_ball_cnt; inc.ball_node = c->d_ball_node;
-    inc.ball_self = c->d_ball_self; inc.ball_nb = c->d_ball_nb; inc.ell_idx = c->d_idx; inc.ell_val = c->d_val;
+    inc.n = c->N; inc.F = c->F; inc.L = c->L; inc.dmax = c->dmax; inc.r4 = c->inc_r4;
+    inc.ball_off = c->d_ball_off; inc.ball_cnt = c->d_ball_cnt; inc.ball_tab = c->d_ball_tab;
+    inc.ell_val = c->d_val;
     IncGeo ig = c->igeo;
     int grid_i = std::min(items, c->grid_inc);
     if (grid_i < ig.xcd || grid_i % ig.xcd) ig.xcd = 1;   // small launches: plain order
@@ -817,6 +819,8 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
     return init_fail(GNA_INVALID_ARG, "unknown eloc_mode");
   if (cfg->eloc_mode == GNA_ELOC_INCREMENTAL && !cfg->tied)
     return init_fail(GNA_UNSUPPORTED, "incremental local energy needs tied weights");
+  if (cfg->eloc_mode == GNA_ELOC_INCREMENTAL && L < 1)
+    return init_fail(GNA_UNSUPPORTED, "incremental local energy needs n_layers >= 1");
   if (cfg->max_batch < 0) return init_fail(GNA_INVALID_ARG, "max_batch must be >= 0");
   if (cfg->act_budget_bytes < 0) return init_fail(GNA_INVALID_ARG, "act_budget_bytes must be >= 0");
   if (!std::isfinite(cfg->jz) || !std::isfinite(cfg->jxy)) return init_fail(GNA_INVALID_ARG, "couplings must be finite");
@@ -1025,7 +1029,7 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
         (st = dev_alloc(c, &c->d_vjp_part, (size_t)c->vjp_rows * c->P * 8)))
       return bail(st, c->err);
   }
-  // incremental local energy: per-bond balls, base planes, kernels
+  // incremental local energy: per-bond nested balls, base planes, kernels
   c->eloc_mode = cfg->eloc_mode;
   if (c->eloc_mode == GNA_ELOC_INCREMENTAL) {
     std::vector<std::vector<int>> adj(N);
@@ -1033,82 +1037,95 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
       adj[cfg->edges[2 * e]].push_back(cfg->edges[2 * e + 1]);
       adj[cfg->edges[2 * e + 1]].push_back(cfg->edges[2 * e]);
     }
-    std::vector<int> off((size_t)std::max(E, 1) * (L + 1), 0), cnt((size_t)std::max(E, 1) * (L + 1), 0);
-    std::vector<int> node_t, self_t, nb_t;
-    int hc_rows = 16, gc_rows = 16, max_tiles = 1;
-    std::vector<int> pos(N, -1), mark(N, 0);
-    for (int e = 0; e < E; ++e) {
-      std::vector<std::vector<int>> C(L + 1);
-      C[0] = {std::min(cfg->edges[2 * e], cfg->edges[2 * e + 1]), std::max(cfg->edges[2 * e], cfg->edges[2 * e + 1])};
-      for (int l = 1; l <= L; ++l) {
-        std::vector<int> nx = C[l - 1];
-        for (int u : C[l - 1]) mark[u] = l;
-        for (int u : C[l - 1])
-          for (int v : adj[u])
-            if (mark[v] != l) { mark[v] = l; nx.push_back(v); }
-        std::sort(nx.begin(), nx.end());
-        C[l] = nx;
-      }
-      for (int u = 0; u < N; ++u) mark[u] = 0;
-      for (int l = 0; l <= L; ++l) {
-        const int padded = ((int)C[l].size() + 15) / 16 * 16;
-        off[(size_t)e * (L + 1) + l] = (int)node_t.size();
-        cnt[(size_t)e * (L + 1) + l] = padded;
-        max_tiles = std::max(max_tiles, padded / 16);
-        if (l < L) gc_rows = std::max(gc_rows, padded);
-        if (l >= 1 && l < L) hc_rows = std::max(hc_rows, padded);
-        if (l >= 1)
-          for (size_t r = 0; r < C[l - 1].size(); ++r) pos[C[l - 1][r]] = (int)r;
-        for (int r = 0; r < padded; ++r) {
-          const int nd = r < (int)C[l].size() ? C[l][r] : -1;
-          node_t.push_back(nd);
-          if (l == 0) {
-            self_t.push_back(-1);
-            for (int d = 0; d < dmax; ++d) nb_t.push_back(-1);
-            continue;
-          }
-          self_t.push_back(nd < 0 ? -1 : (pos[nd] >= 0 ? pos[nd] : -1 - nd));
-          for (int d = 0; d < dmax; ++d) {
-            if (nd < 0) { nb_t.push_back(-1); continue; }
-            const int m = idx[(size_t)nd * dmax + d];
-            nb_t.push_back(pos[m] >= 0 ? pos[m] : -1 - m);
-          }
-        }
-        if (l >= 1)
-          for (int u : C[l - 1]) pos[u] = -1;
-      }
-    }
-    c->inc_rows_max = std::max(hc_rows, gc_rows);
-    IncGeo& ig = c->igeo;
+    // node list of bond e: C_0 = {i, j}, then the nodes at distance 1, 2, ..., L+1
+    // (each ring sorted), so that C_l is a prefix
+    std::vector<std::vector<int>> lists(std::max(E, 1));
+    std::vector<int> cnt((size_t)std::max(E, 1) * (L + 2), 0);
+    int max_rows = 2, max_ball = 2;
     {
-      int most = 0;   // largest table of one bond, in ints
+      std::vector<int> mark(N, 0);
       for (int e = 0; e < E; ++e) {
-        const int r0 = off[(size_t)e * (L + 1)], r1 = off[(size_t)e * (L + 1) + L] + cnt[(size_t)e * (L + 1) + L];
-        most = std::max(most, (r1 - r0) * (2 + dmax));
+        std::vector<int>& lst = lists[e];
+        const int a = cfg->edges[2 * e], bb = cfg->edges[2 * e + 1];
+        lst = {std::min(a, bb), std::max(a, bb)};
+        for (int u : lst) mark[u] = 1;
+        cnt[(size_t)e * (L + 2)] = 2;
+        size_t r0 = 0;
+        for (int l = 1; l <= L + 1; ++l) {
+          const size_t r1 = lst.size();
+          std::vector<int> ring;
+          for (size_t r = r0; r < r1; ++r)
+            for (int v : adj[lst[r]])
+              if (!mark[v]) { mark[v] = 1; ring.push_back(v); }
+          std::sort(ring.begin(), ring.end());
+          lst.insert(lst.end(), ring.begin(), ring.end());
+          cnt[(size_t)e * (L + 2) + l] = (int)lst.size();
+          r0 = r1;
+        }
+        for (int u : lst) mark[u] = 0;
+        max_rows = std::max(max_rows, (int)lst.size());
+        max_ball = std::max(max_ball, cnt[(size_t)e * (L + 2) + L]);
       }
-      ig.tab_ints = std::max(most, 16);
     }
-    ig.xcd = 8;   // MI355X: 8 XCDs, workgroups assigned round-robin
-    ig.nw = std::min(kMaxWaves / 2, max_tiles);
-    int maxt = (max_tiles + ig.nw - 1) / ig.nw;
-    maxt = maxt <= 1 ? 1 : (maxt <= 2 ? 2 : 4);
-    if (maxt * ig.nw < max_tiles) return bail(GNA_UNSUPPORTED, "ball too large for the incremental kernel");
-    ig.row_elems = (int)((4 * (F / 4) * c->sz_Acc + kRowPadBytes) / c->sz_Acc);
+    const int r4 = (max_rows + 3) / 4 * 4;
+    const int max_tiles = (max_ball + 15) / 16;
+    // per bond: r4 node slots, then |C_L| x dmax neighbour list positions
+    std::vector<int> off(std::max(E, 1), 0), tabv;
     {
+      std::vector<int> pos(N, -1);
+      for (int e = 0; e < E; ++e) {
+        const std::vector<int>& lst = lists[e];
+        off[e] = (int)tabv.size();
+        for (int r = 0; r < r4; ++r) tabv.push_back(r < (int)lst.size() ? lst[r] : -1);
+        for (size_t r = 0; r < lst.size(); ++r) pos[lst[r]] = (int)r;
+        const int nball = cnt[(size_t)e * (L + 2) + L];
+        for (int r = 0; r < nball; ++r)
+          for (int d = 0; d < dmax; ++d) {
+            const int m = idx[(size_t)lst[r] * dmax + d];   // a neighbour of C_L lies in C_{L+1}
+            if (pos[m] < 0) return bail(GNA_UNSUPPORTED, "ball table: neighbour outside C_{L+1}");
+            tabv.push_back(pos[m]);
+          }
+        for (int nd : lst) pos[nd] = -1;
+      }
+    }
+    IncGeo& ig = c->igeo;
+    ig.xcd = 8;   // MI355X: 8 XCDs, workgroups assigned round-robin
+    ig.rows = max_rows;
+    ig.tabw = r4 + max_ball * dmax;
+    ig.row_elems = (int)((4 * (F / 4) * c->sz_Acc + kRowPadBytes) / c->sz_Acc);
+    const int chunk_cap = 64 * kMaxWaves / 2;   // bonds per work item: at most one per thread
+    // largest number of exchanges in flight that fits in LDS and in four tiles per wave
+    int maxt = 0;
+    int s_cap = kIncMaxSwaps;
+    if (const char* ev = std::getenv("GNA_INC_MAX_SWAPS")) s_cap = std::max(1, std::min(kIncMaxSwaps, std::atoi(ev)));
+    for (int S = s_cap; S >= 1; --S) {
+      const int tiles = S * max_tiles;
+      const int nw = std::min(kMaxWaves / 2, tiles);
+      const int mt = (tiles + nw - 1) / nw;   // tiles per wave: 1 .. 4
+      if (mt > 4) continue;
       size_t o = 0;
       auto al = [](size_t x) { return (x + 15) & ~(size_t)15; };
-      ig.off_w = (int)o; o = al(o + w_bytes);
-      ig.off_hc = (int)o; o = al(o + (size_t)hc_rows * ig.row_elems * c->sz_Acc);
-      ig.off_gc = (int)o; o = al(o + (size_t)gc_rows * ig.row_elems * c->sz_Acc);
-      ig.off_sp = (int)o; o = al(o + g.npad);
-      ig.off_red = (int)o; o = al(o + kRedSlots * 8);
-      ig.off_bias = (int)o; o = al(o + (size_t)F * c->sz_Acc);
-      ig.off_emb = (int)o; o = al(o + (size_t)2 * F * c->sz_Acc);
-      ig.off_head = (int)o; o = al(o + (size_t)2 * (F + 3) * 8);
-      ig.off_tab = (int)o; o = al(o + (size_t)ig.tab_ints * 4);
-      ig.lds_bytes = (int)o;
-      if (o + 64 > lds_max) return bail(GNA_UNSUPPORTED, "incremental local energy does not fit in LDS");
+      IncGeo t = ig;
+      t.S = S;
+      t.nw = nw;
+      t.off_w = (int)o; o = al(o + w_bytes);
+      t.off_buf = (int)o; o = al(o + (size_t)S * max_rows * ig.row_elems * c->sz_Acc);
+      t.off_tab = (int)o; o = al(o + (size_t)S * ig.tabw * 4);
+      t.off_sp = (int)o; o = al(o + g.npad);
+      t.off_red = (int)o; o = al(o + (size_t)kIncMaxSwaps * 2 * kMaxWaves * 8);
+      t.off_bias = (int)o; o = al(o + (size_t)F * c->sz_Acc);
+      t.off_emb = (int)o; o = al(o + (size_t)2 * F * c->sz_Acc);
+      t.off_head = (int)o; o = al(o + (size_t)2 * (F + 3) * 8);
+      t.off_ev = (int)o; o = al(o + (size_t)N * dmax * c->sz_Acc);
+      t.off_list = (int)o; o = al(o + (size_t)chunk_cap * 4);
+      t.lds_bytes = (int)o;
+      if (o + 1024 > lds_max) continue;   // static LDS of the kernel
+      ig = t;
+      maxt = mt;
+      break;
     }
+    if (maxt == 0) return bail(GNA_UNSUPPORTED, "incremental local energy does not fit in LDS");
+    c->inc_chunk_cap = std::min(chunk_cap, 64 * ig.nw);
     switch (c->prec) {
       case GNA_FP64: inc_pick_f<PF64>(F, tpw, nch, maxt, &c->k_inc_base, &c->k_inc); break;
       case GNA_FP32: inc_pick_f<PF32>(F, tpw, nch, maxt, &c->k_inc_base, &c->k_inc); break;
@@ -1135,22 +1152,17 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
       c->grid_inc_base = c->n_cu * occ2(c->k_inc_base, 64 * g.wpc, g.lds_bytes);
       c->grid_inc = c->n_cu * occ2(c->k_inc, 64 * ig.nw, ig.lds_bytes);
     }
+    c->inc_r4 = r4;
     const size_t plane_bytes = (size_t)g.npad * F * c->sz_Acc;
     if ((st = dev_alloc(c, &c->d_ball_off, off.size() * 4)) ||
         (st = dev_alloc(c, &c->d_ball_cnt, cnt.size() * 4)) ||
-        (st = dev_alloc(c, &c->d_ball_node, std::max<size_t>(1, node_t.size()) * 4)) ||
-        (st = dev_alloc(c, &c->d_ball_self, std::max<size_t>(1, self_t.size()) * 4)) ||
-        (st = dev_alloc(c, &c->d_ball_nb, std::max<size_t>(1, nb_t.size()) * 4)) ||
+        (st = dev_alloc(c, &c->d_ball_tab, std::max<size_t>(4, tabv.size()) * 4)) ||
         (st = dev_alloc(c, &c->d_inc_planes, (size_t)MB * 2 * std::max(L, 1) * plane_bytes)))
       return bail(st, c->err);
     he = hipMemcpy(c->d_ball_off, off.data(), off.size() * 4, hipMemcpyHostToDevice);
     if (he == hipSuccess) he = hipMemcpy(c->d_ball_cnt, cnt.data(), cnt.size() * 4, hipMemcpyHostToDevice);
-    if (he == hipSuccess && !node_t.empty())
-      he = hipMemcpy(c->d_ball_node, node_t.data(), node_t.size() * 4, hipMemcpyHostToDevice);
-    if (he == hipSuccess && !self_t.empty())
-      he = hipMemcpy(c->d_ball_self, self_t.data(), self_t.size() * 4, hipMemcpyHostToDevice);
-    if (he == hipSuccess && !nb_t.empty())
-      he = hipMemcpy(c->d_ball_nb, nb_t.data(), nb_t.size() * 4, hipMemcpyHostToDevice);
+    if (he == hipSuccess && !tabv.empty())
+      he = hipMemcpy(c->d_ball_tab, tabv.data(), tabv.size() * 4, hipMemcpyHostToDevice);
     if (he != hipSuccess) return bail(GNA_HIP_ERROR, std::string("hipMemcpy: ") + hipGetErrorString(he));
   }
   he = hipMemcpy(c->d_edges, hedges.data(), hedges.size() * 4, hipMemcpyHostToDevice);

@@ -278,6 +278,20 @@ __device__ __forceinline__ void lds_write(T* __restrict__ dst, const T* src) {
   }
 }
 
+// copy of N elements of T from global memory (16-byte aligned rows), issued as
+// global loads, so that a branch between an LDS row and a global row is never
+// merged into one flat access
+template <class T, int N>
+__device__ __forceinline__ void gmem_read(const T* src, T (&dst)[N]) {
+  constexpr int B = N * (int)sizeof(T);
+  static_assert(B % 16 == 0, "rows are whole 16-byte vectors");
+  using V = unsigned int __attribute__((ext_vector_type(4)));
+  using G = const __attribute__((address_space(1))) V*;
+  G s = (G)(src);
+#pragma unroll
+  for (int k = 0; k < B / 16; ++k) reinterpret_cast<V*>(dst)[k] = s[k];
+}
+
 // ---------------------------------------------------------------------------
 // Per-workgroup view of LDS.
 // ---------------------------------------------------------------------------
