@@ -413,18 +413,31 @@ const void* inc_base_pick(int tpw, int nch) {
   if (tpw == 2) return inc_base_kernel<P, F, 2, 1>();
   return inc_base_kernel<P, F, 4, 1>();
 }
+struct IncKern {
+  const void* base = nullptr;    // k_inc_base
+  const void* eloc = nullptr;    // k_eloc_inc
+  const void* sweep = nullptr;   // k_sweep_inc
+};
+template <class P, int F, int MAXT>
+void inc_fill(IncKern& k) {
+  k.eloc = reinterpret_cast<const void*>(&k_eloc_inc<P, F, MAXT>);
+  k.sweep = reinterpret_cast<const void*>(&k_sweep_inc<P, F, MAXT>);
+}
 template <class P, int F>
-const void* inc_pick(int maxt) {
-  if (maxt == 1) return reinterpret_cast<const void*>(&k_eloc_inc<P, F, 1>);
-  if (maxt == 2) return reinterpret_cast<const void*>(&k_eloc_inc<P, F, 2>);
-  if (maxt == 3) return reinterpret_cast<const void*>(&k_eloc_inc<P, F, 3>);
-  return reinterpret_cast<const void*>(&k_eloc_inc<P, F, 4>);
+IncKern inc_pick(int tpw, int nch, int maxt) {
+  IncKern k;
+  k.base = inc_base_pick<P, F>(tpw, nch);
+  if (maxt == 1) inc_fill<P, F, 1>(k);
+  else if (maxt == 2) inc_fill<P, F, 2>(k);
+  else if (maxt == 3) inc_fill<P, F, 3>(k);
+  else inc_fill<P, F, 4>(k);
+  return k;
 }
 template <class P>
-void inc_pick_f(int F, int tpw, int nch, int maxt, const void** base, const void** ker) {
-  if (F == 16) { *base = inc_base_pick<P, 16>(tpw, nch); *ker = inc_pick<P, 16>(maxt); }
-  else if (F == 32) { *base = inc_base_pick<P, 32>(tpw, nch); *ker = inc_pick<P, 32>(maxt); }
-  else { *base = inc_base_pick<P, 64>(tpw, nch); *ker = inc_pick<P, 64>(maxt); }
+IncKern inc_pick_f(int F, int tpw, int nch, int maxt) {
+  if (F == 16) return inc_pick<P, 16>(tpw, nch, maxt);
+  if (F == 32) return inc_pick<P, 32>(tpw, nch, maxt);
+  return inc_pick<P, 64>(tpw, nch, maxt);
 }
 
 // reverse-pass kernels of one (precision, F, TPW, NCH) instantiation (FP32 or FP64)
@@ -511,9 +524,8 @@ struct gna_ctx {
   // incremental local energy
   int eloc_mode = 0;
   IncGeo igeo{};
-  const void* k_inc_base = nullptr;
-  const void* k_inc = nullptr;
-  int grid_inc_base = 1, grid_inc = 1, inc_r4 = 4, inc_chunk_cap = 64;
+  IncKern ik{};
+  int grid_inc_base = 1, grid_inc = 1, grid_sweep_inc = 1, inc_r4 = 4, inc_chunk_cap = 64;
   int* d_ball_off = nullptr;
   int* d_ball_cnt = nullptr;
   int* d_ball_tab = nullptr;
@@ -652,6 +664,14 @@ gna_status run_logpsi(gna_ctx* c, const double* theta, const int8_t* spins, int 
   return launch(c, c->kern.logpsi, grid, args, "k_logpsi");
 }
 
+IncNet make_inc(const gna_ctx* c) {
+  IncNet inc{};
+  inc.n = c->N; inc.F = c->F; inc.L = c->L; inc.dmax = c->dmax; inc.r4 = c->inc_r4;
+  inc.ball_off = c->d_ball_off; inc.ball_cnt = c->d_ball_cnt; inc.ball_tab = c->d_ball_tab;
+  inc.ell_val = c->d_val;
+  return inc;
+}
+
 gna_status run_eloc(gna_ctx* c, const double* theta, const int8_t* spins, int B, const double* base,
                     double* eloc, long long* nev) {
   {
@@ -688,21 +708,18 @@ gna_status run_eloc(gna_ctx* c, const double* theta, const int8_t* spins, int B,
     {
       Timed tm(c, "k_inc_base");
       void* a1[] = {&net, &spins, &B, &planes, &lp_out};
-      hipError_t e = hipLaunchKernel(c->k_inc_base, dim3(std::min(B, c->grid_inc_base)), dim3(64 * c->geo.wpc), a1,
+      hipError_t e = hipLaunchKernel(c->ik.base, dim3(std::min(B, c->grid_inc_base)), dim3(64 * c->geo.wpc), a1,
                                      (size_t)c->geo.lds_bytes, c->stream);
       if (e != hipSuccess) return hip_fail(c, e, "k_inc_base");
     }
-    IncNet inc{};
-    inc.n = c->N; inc.F = c->F; inc.L = c->L; inc.dmax = c->dmax; inc.r4 = c->inc_r4;
-    inc.ball_off = c->d_ball_off; inc.ball_cnt = c->d_ball_cnt; inc.ball_tab = c->d_ball_tab;
-    inc.ell_val = c->d_val;
+    IncNet inc = make_inc(c);
     IncGeo ig = c->igeo;
     int grid_i = std::min(items, c->grid_inc);
     if (grid_i < ig.xcd || grid_i % ig.xcd) ig.xcd = 1;   // small launches: plain order
     {
       Timed tm(c, "k_eloc_inc");
       void* a2[] = {&net, &inc, &ig, &spins, &B, &planes, &n_chunks, &ichunk, &partial, &cnt};
-      hipError_t e = hipLaunchKernel(c->k_inc, dim3(grid_i), dim3(64 * ig.nw), a2,
+      hipError_t e = hipLaunchKernel(c->ik.eloc, dim3(grid_i), dim3(64 * ig.nw), a2,
                                      (size_t)ig.lds_bytes, c->stream);
       if (e != hipSuccess) return hip_fail(c, e, "k_eloc_inc");
     }
@@ -1111,7 +1128,8 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
       t.off_w = (int)o; o = al(o + w_bytes);
       t.off_buf = (int)o; o = al(o + (size_t)S * max_rows * ig.row_elems * c->sz_Acc);
       t.off_tab = (int)o; o = al(o + (size_t)S * ig.tabw * 4);
-      t.off_sp = (int)o; o = al(o + g.npad);
+      t.spw = (int)al(g.npad);
+      t.off_sp = (int)o; o = al(o + (size_t)S * t.spw);
       t.off_red = (int)o; o = al(o + (size_t)kIncMaxSwaps * 2 * kMaxWaves * 8);
       t.off_bias = (int)o; o = al(o + (size_t)F * c->sz_Acc);
       t.off_emb = (int)o; o = al(o + (size_t)2 * F * c->sz_Acc);
@@ -1119,7 +1137,7 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
       t.off_ev = (int)o; o = al(o + (size_t)N * dmax * c->sz_Acc);
       t.off_list = (int)o; o = al(o + (size_t)chunk_cap * 4);
       t.lds_bytes = (int)o;
-      if (o + 1024 > lds_max) continue;   // static LDS of the kernel
+      if (o + 2048 > lds_max) continue;   // static LDS of the kernels
       ig = t;
       maxt = mt;
       break;
@@ -1127,19 +1145,12 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
     if (maxt == 0) return bail(GNA_UNSUPPORTED, "incremental local energy does not fit in LDS");
     c->inc_chunk_cap = std::min(chunk_cap, 64 * ig.nw);
     switch (c->prec) {
-      case GNA_FP64: inc_pick_f<PF64>(F, tpw, nch, maxt, &c->k_inc_base, &c->k_inc); break;
-      case GNA_FP32: inc_pick_f<PF32>(F, tpw, nch, maxt, &c->k_inc_base, &c->k_inc); break;
+      case GNA_FP64: c->ik = inc_pick_f<PF64>(F, tpw, nch, maxt); break;
+      case GNA_FP32: c->ik = inc_pick_f<PF32>(F, tpw, nch, maxt); break;
       default:
-        if (F == 16) {
-          c->k_inc_base = inc_base_pick<PBF16, 16>(tpw, nch);
-          c->k_inc = inc_pick<PBF16, 16>(maxt);
-        } else if (F == 32) {
-          c->k_inc_base = inc_base_pick<PBF16W, 32>(tpw, nch);
-          c->k_inc = inc_pick<PBF16W, 32>(maxt);
-        } else {
-          c->k_inc_base = inc_base_pick<PBF16W, 64>(tpw, nch);
-          c->k_inc = inc_pick<PBF16W, 64>(maxt);
-        }
+        if (F == 16) c->ik = inc_pick<PBF16, 16>(tpw, nch, maxt);
+        else if (F == 32) c->ik = inc_pick<PBF16W, 32>(tpw, nch, maxt);
+        else c->ik = inc_pick<PBF16W, 64>(tpw, nch, maxt);
     }
     {
       auto occ2 = [&](const void* fn, int threads_, int lds) {
@@ -1149,8 +1160,9 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
         (void)hipGetLastError();
         return nb;
       };
-      c->grid_inc_base = c->n_cu * occ2(c->k_inc_base, 64 * g.wpc, g.lds_bytes);
-      c->grid_inc = c->n_cu * occ2(c->k_inc, 64 * ig.nw, ig.lds_bytes);
+      c->grid_inc_base = c->n_cu * occ2(c->ik.base, 64 * g.wpc, g.lds_bytes);
+      c->grid_inc = c->n_cu * occ2(c->ik.eloc, 64 * ig.nw, ig.lds_bytes);
+      c->grid_sweep_inc = c->n_cu * occ2(c->ik.sweep, 64 * ig.nw, ig.lds_bytes);
     }
     c->inc_r4 = r4;
     const size_t plane_bytes = (size_t)g.npad * F * c->sz_Acc;
@@ -1244,6 +1256,34 @@ gna_status gna_metropolis_sweep(gna_ctx* c, const double* theta, int8_t* spins, 
   if (B == 0) return GNA_OK;
   if (gna_status st = prepare(c, theta)) return st;
   Net net = make_net(c, theta);
+  if (c->eloc_mode == GNA_ELOC_INCREMENTAL) {
+    // planes of the current configurations, incremental sweeps, then log psi of the
+    // final configurations by the full evaluation
+    void* planes = c->d_inc_planes;
+    double* none = nullptr;
+    {
+      Timed tm(c, "k_inc_base");
+      void* a1[] = {&net, &spins, &B, &planes, &none};
+      hipError_t e = hipLaunchKernel(c->ik.base, dim3(std::min(B, c->grid_inc_base)), dim3(64 * c->geo.wpc), a1,
+                                     (size_t)c->geo.lds_bytes, c->stream);
+      if (e != hipSuccess) return hip_fail(c, e, "k_inc_base");
+    }
+    if (gna_status st = check_launch(c, "k_inc_base")) return st;
+    IncNet inc = make_inc(c);
+    IncGeo ig = c->igeo;
+    const int grid_s = std::max(1, std::min(c->grid_sweep_inc, (B + ig.S - 1) / ig.S));
+    int Bv = B, ns = n_sweeps;
+    unsigned long long sd = seed, cb = counter_base;
+    int* acc = n_accept;
+    {
+      Timed tm(c, "k_sweep_inc");
+      void* a2[] = {&net, &inc, &ig, &spins, &planes, &Bv, &ns, &sd, &cb, &acc};
+      hipError_t e = hipLaunchKernel(c->ik.sweep, dim3(grid_s), dim3(64 * ig.nw), a2, (size_t)ig.lds_bytes, c->stream);
+      if (e != hipSuccess) return hip_fail(c, e, "k_sweep_inc");
+    }
+    if (gna_status st = check_launch(c, "k_sweep_inc")) return st;
+    return run_logpsi(c, theta, spins, B, logpsi);
+  }
   int grid = std::min(B, c->grid_sweep);
   int Bv = B, ns = n_sweeps;
   unsigned long long sd = seed, cb = counter_base;

@@ -23,8 +23,16 @@
 //     [0, |C_l|) with G^{l-1} in place; rows [|C_l|, |C_{l+1}|) receive base
 //     G^{l-1} rows, so that the gather reads only LDS (the list runs to C_{L+1});
 //   - after the gather, rows [0, |C_l|) receive H'^l.
-// Tile (swap w, tile t) is owned by wave (t * nswap + w) % waves at every layer,
+// Tile (job w, tile t) is owned by wave (t * njobs + w) % waves at every layer,
 // so a wave reads back only rows it wrote itself and a layer needs two barriers.
+//
+// The same ball evaluation serves the Metropolis sampler (Section 3.2): there each
+// job belongs to its own chain, and the recomputed rows H'^l (C_l) and G'^{l-1}
+// (C_{l-1}) are written into that chain's planes as they are produced.  Rows read
+// later in the same evaluation are never among the rows written before them
+// (layer l reads H^{l-1} outside C_{l-1} and G^{l-1} outside C_l).  A rejected
+// proposal is followed by a restore job: the same ball for the unexchanged
+// configuration, which rewrites the old rows bit for bit.
 #pragma once
 
 #include "gna_kernels.h"
@@ -41,13 +49,14 @@ struct IncNet {
   const void* ell_val;     // [npad][dmax] A_hat in Acc precision
 };
 
-// LDS layout of k_eloc_inc (byte offsets) and launch shape
+// LDS layout of the incremental kernels (byte offsets) and launch shape
 struct IncGeo {
   int nw;           // waves per workgroup
-  int S;            // exchanges in flight per workgroup (<= kIncMaxSwaps)
+  int S;            // jobs (exchanges) in flight per workgroup (<= kIncMaxSwaps)
   int row_elems;    // LDS row stride in Acc elements
-  int rows;         // buffer rows per exchange (max |C_{L+1}|)
-  int tabw;         // ints per exchange table in LDS (r4 + rows * dmax, multiple of 4)
+  int rows;         // buffer rows per job (max |C_{L+1}|)
+  int tabw;         // ints per job table in LDS (r4 + max|C_L| * dmax, multiple of 4)
+  int spw;          // bytes per spin configuration in LDS
   int off_w, off_buf, off_tab, off_sp, off_red, off_bias, off_emb, off_head, off_ev, off_list;
   int xcd;          // items are grouped per XCD (blocks b with equal b % xcd share a sample)
   int lds_bytes;
@@ -56,57 +65,312 @@ struct IncGeo {
 constexpr int kIncMaxSwaps = 8;
 constexpr int kIncCopy = 4;   // 16-byte base-row copies held in registers per thread
 
+// job flags
+constexpr int kJobSwap = 1;      // evaluate the exchanged configuration (else the current one)
+constexpr int kJobReadout = 2;   // accumulate the readout difference
+
+// The jobs of one group (LDS, written before the group's first barrier)
+struct IncJobs {
+  int cnt[kIncMaxSwaps][18];   // |C_l| of the job's bond
+  int2 ij[kIncMaxSwaps];       // bond endpoints
+  int e[kIncMaxSwaps];         // bond index
+  int flags[kIncMaxSwaps];
+  int spoff[kIncMaxSwaps];     // byte offset of the job's spins in the spin area
+  long long pboff[kIncMaxSwaps];   // element offset of the job's planes
+};
+
+// LDS views of the incremental kernels
+template <class P>
+struct IncLds {
+  typename P::WT* wl;
+  typename P::Acc* buf;
+  int* tab;
+  int8_t* sp;
+  double* red;                 // [kIncMaxSwaps][2][kMaxWaves]
+  typename P::Acc* sbias;
+  typename P::Acc* semb;
+  double* shead;
+  typename P::Acc* sev;
+  int* slist;
+  __device__ IncLds(const IncGeo& ig, unsigned char* smem) {
+    using Acc = typename P::Acc;
+    wl = reinterpret_cast<typename P::WT*>(smem + ig.off_w);
+    buf = reinterpret_cast<Acc*>(smem + ig.off_buf);
+    tab = reinterpret_cast<int*>(smem + ig.off_tab);
+    sp = reinterpret_cast<int8_t*>(smem + ig.off_sp);
+    red = reinterpret_cast<double*>(smem + ig.off_red);
+    sbias = reinterpret_cast<Acc*>(smem + ig.off_bias);
+    semb = reinterpret_cast<Acc*>(smem + ig.off_emb);
+    shead = reinterpret_cast<double*>(smem + ig.off_head);
+    sev = reinterpret_cast<Acc*>(smem + ig.off_ev);
+    slist = reinterpret_cast<int*>(smem + ig.off_list);
+  }
+};
+
+// weights (tied: one layer) and the small tables -> LDS
+template <class P, int F>
+__device__ void inc_stage(const Net& net, const IncNet& inc, const IncLds<P>& x) {
+  using Acc = typename P::Acc;
+  using WT = typename P::WT;
+  constexpr int NS = F / 4;
+  const int bd = blockDim.x;
+  const WT* src = reinterpret_cast<const WT*>(net.wfrag);
+  for (int k = threadIdx.x; k < 2 * F * F; k += bd) x.wl[k] = src[k];
+  for (int k = threadIdx.x; k < F; k += bd)
+    x.sbias[k] = reinterpret_cast<const Acc*>(net.bias)[P::lc(k / NS, k % NS)];   // slot order
+  for (int k = threadIdx.x; k < 2 * F; k += bd) x.semb[k] = reinterpret_cast<const Acc*>(net.emb)[k];
+  for (int k = threadIdx.x; k < F + 3; k += bd) {
+    x.shead[k] = net.head_a[k];
+    x.shead[F + 3 + k] = net.head_p[k];
+  }
+  const Acc* ev = reinterpret_cast<const Acc*>(inc.ell_val);
+  for (int k = threadIdx.x; k < net.n * inc.dmax; k += bd) x.sev[k] = ev[k];
+}
+
+// One group of nsw jobs: tables -> LDS, then layers 1..L over the jobs' balls.
+// Entry: jobs.{ij, e, flags, spoff, pboff} written and visible (after a barrier).
+// Exit: readout partials of job j in red[(2j + {0,1}) * kMaxWaves + wave] for jobs
+// with kJobReadout (the caller synchronises before reading them).  With WRITE the
+// recomputed rows are stored into the jobs' planes.
+template <class P, int F, int MAXT, bool WRITE>
+__device__ void inc_group(const Net& net, const IncNet& inc, const IncGeo& ig, const IncLds<P>& x, IncJobs& jobs,
+                          int nsw, typename P::Acc* planes, unsigned char* smem) {
+  using Acc = typename P::Acc;
+  using CF = typename P::CF;
+  constexpr int NS = F / 4, MT = F / 16, KSB = F / P::KS, VEC = P::VEC;
+  constexpr int SM = kIncMaxSwaps;
+  constexpr int VPR = F * (int)sizeof(Acc) / 16;   // 16-byte vectors per row
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int q = lane >> 4, col = lane & 15;
+  const int nw = ig.nw, Lr = net.L, dm = inc.dmax, bd = blockDim.x;
+  const size_t plane = (size_t)net.g.npad * F;
+  auto afrag = [&](int blk, int st, int t) { return x.wl + (((blk * KSB + st) * MT + t) * 64 + lane) * VEC; };
+  const Acc* bias = x.sbias + q * NS;
+
+  // tables of the group -> LDS (16-byte vectors)
+  for (int k = threadIdx.x; k < nsw * (Lr + 2); k += bd) {
+    const int w = k / (Lr + 2), l = k % (Lr + 2);
+    jobs.cnt[w][l] = inc.ball_cnt[jobs.e[w] * (Lr + 2) + l];
+  }
+  {
+    const int tv = ig.tabw / 4;
+    for (int k = threadIdx.x; k < nsw * tv; k += bd) {
+      const int w = k / tv, v = k % tv;
+      const int eg = jobs.e[w];
+      const int nr = inc.ball_cnt[eg * (Lr + 2) + Lr];
+      const int nv = (inc.r4 + nr * dm) / 4;   // this bond's table, in vectors
+      if (v < nv)
+        reinterpret_cast<int4*>(x.tab + w * ig.tabw)[v] = reinterpret_cast<const int4*>(inc.ball_tab + inc.ball_off[eg])[v];
+    }
+  }
+  __syncthreads();
+  // spin of node nd in the configuration job w evaluates
+  auto xspin = [&](int w, int nd) {
+    const int8_t* spw = x.sp + jobs.spoff[w];
+    const int2 ij = jobs.ij[w];
+    int8_t v = spw[nd];
+    if (jobs.flags[w] & kJobSwap) v = (nd == ij.x) ? spw[ij.y] : ((nd == ij.y) ? spw[ij.x] : v);
+    return v > 0 ? 1 : 0;
+  };
+  for (int l = 1; l <= Lr; ++l) {
+    // ---- base G^{l-1} rows of the nodes at distance l+1 -> buffer (issued first)
+    using V4 = unsigned int __attribute__((ext_vector_type(4)));
+    V4 cvv[kIncCopy];
+    int cdst[kIncCopy];
+    {
+      int cst[SM + 1];
+      cst[0] = 0;
+#pragma unroll
+      for (int w = 0; w < SM; ++w) cst[w + 1] = cst[w] + (w < nsw ? (jobs.cnt[w][l + 1] - jobs.cnt[w][l]) * VPR : 0);
+      const int ctot = cst[SM];
+      // copy item idx -> (source vector, byte offset of the destination in LDS)
+      auto locate = [&](int idx, const V4*& src) {
+        int w = 0, start = 0;
+#pragma unroll
+        for (int u = 1; u < SM; ++u)
+          if (idx >= cst[u]) { w = u; start = cst[u]; }
+        const int rel = idx - start;
+        const int rr = jobs.cnt[w][l] + rel / VPR, v = rel % VPR;
+        const int nd = x.tab[w * ig.tabw + rr];
+        const Acc* Gb = planes + jobs.pboff[w] + (size_t)(Lr + l - 1) * plane;
+        src = reinterpret_cast<const V4*>(Gb + (size_t)nd * F) + v;
+        return ig.off_buf + ((w * ig.rows + rr) * ig.row_elems) * (int)sizeof(Acc) + 16 * v;
+      };
+      const V4* ph = reinterpret_cast<const V4*>(planes + jobs.pboff[0]);   // in-bounds placeholder
+#pragma unroll
+      for (int u = 0; u < kIncCopy; ++u) {
+        const int idx = threadIdx.x + u * bd;
+        const V4* src = ph;
+        cdst[u] = -1;
+        if (idx < ctot) cdst[u] = locate(idx, src);
+        cvv[u] = *src;   // unconditional, so the value stays in registers
+      }
+      for (int idx = threadIdx.x + kIncCopy * bd; idx < ctot; idx += bd) {   // rare: large rings
+        const V4* src;
+        const int o = locate(idx, src);
+        *reinterpret_cast<V4*>(smem + o) = *src;
+      }
+    }
+    // ---- this wave's tiles
+    int trow[MAXT], tsw[MAXT];
+    bool tok[MAXT];
+#pragma unroll
+    for (int k = 0; k < MAXT; ++k) {
+      const int g = wv + k * nw;
+      const int w = g % nsw, tt = g / nsw;
+      tsw[k] = w;
+      tok[k] = tt * 16 < jobs.cnt[w][l];
+      trow[k] = tt * 16 + col;
+    }
+    // ---- products: self -> registers, message -> buffer rows [0, |C_l|) in place
+    CF acc[MAXT][MT];
+#pragma unroll
+    for (int k = 0; k < MAXT; ++k) {
+      if (!tok[k]) continue;
+      const int w = tsw[k], r = trow[k];
+      const int cl = jobs.cnt[w][l], cp = jobs.cnt[w][l - 1];
+      const int nd = r < cl ? x.tab[w * ig.tabw + r] : -1;
+      Acc* pw = planes + jobs.pboff[w];
+      Acc h[NS];
+      if (l == 1) {
+        const int xs = nd >= 0 ? xspin(w, nd) : 0;
+#pragma unroll
+        for (int i = 0; i < NS; ++i) h[i] = nd >= 0 ? x.semb[xs * F + P::lc(q, i)] : (Acc)0;
+      } else if (r < cp) {
+        lds_read<Acc, NS>(x.buf + ((size_t)w * ig.rows + r) * ig.row_elems + q * NS, h);       // H'^{l-1}
+      } else if (nd >= 0) {
+        gmem_read<Acc, NS>(pw + (size_t)(l - 2) * plane + (size_t)nd * F + q * NS, h);     // base H^{l-1}
+      } else {
+#pragma unroll
+        for (int i = 0; i < NS; ++i) h[i] = (Acc)0;
+      }
+      Acc* row = x.buf + ((size_t)w * ig.rows + r) * ig.row_elems + q * NS;
+#pragma unroll
+      for (int t = 0; t < MT; ++t) {
+        CF a, gs = CF{0, 0, 0, 0};
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) a[rr] = bias[4 * t + rr];
+#pragma unroll
+        for (int st = 0; st < KSB; ++st) {
+          const auto bop = P::make_b(&h[st * VEC]);
+          gs = P::mma(P::load_a(afrag(0, st, t)), bop, gs);
+          a = P::mma(P::load_a(afrag(1, st, t)), bop, a);
+        }
+        acc[k][t] = a;
+        Acc gm[4] = {gs[0], gs[1], gs[2], gs[3]};
+        if (r < cl) lds_write<Acc, 4>(row + 4 * t, gm);
+        if (WRITE && r < cp)   // G^{l-1} changed on C_{l-1}
+          lds_write<Acc, 4>(pw + (size_t)(Lr + l - 1) * plane + (size_t)nd * F + q * NS + 4 * t, gm);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kIncCopy; ++u)
+      if (cdst[u] >= 0) *reinterpret_cast<V4*>(smem + cdst[u]) = cvv[u];
+    __syncthreads();   // every G^{l-1} row of every job is in its buffer
+    // ---- gather, activation; readout difference at the last layer
+    if (l == Lr && lane == 0)
+      for (int w = 0; w < nsw; ++w) x.red[(2 * w) * kMaxWaves + wv] = x.red[(2 * w + 1) * kMaxWaves + wv] = 0.0;
+    Acc hn[MAXT][NS];
+#pragma unroll
+    for (int k = 0; k < MAXT; ++k) {
+      if (!tok[k]) continue;
+      const int w = tsw[k], r = trow[k];
+      const int cl = jobs.cnt[w][l];
+      const int* tw = x.tab + w * ig.tabw;
+      const int nd = r < cl ? tw[r] : -1;
+      const Acc* bw = x.buf + (size_t)w * ig.rows * ig.row_elems;
+      Acc* pw = planes + jobs.pboff[w];
+      const bool rd = l == Lr && (jobs.flags[w] & kJobReadout);
+      Acc hb[NS];
+      if (rd && nd >= 0) gmem_read<Acc, NS>(pw + (size_t)(Lr - 1) * plane + (size_t)nd * F + q * NS, hb);
+      Acc m[NS];
+#pragma unroll
+      for (int i = 0; i < NS; ++i) m[i] = (Acc)0;
+      if (nd >= 0) {
+        const int* nbp = tw + inc.r4 + r * dm;
+        for (int d = 0; d < dm; d += 4) {
+          const int4 pv = *reinterpret_cast<const int4*>(nbp + d);
+          const int pc[4] = {pv.x, pv.y, pv.z, pv.w};
+          const Acc* wp = x.sev + nd * dm + d;
+          const Acc wt[4] = {wp[0], wp[1], wp[2], wp[3]};
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            Acc rowv[NS];
+            lds_read<Acc, NS>(bw + pc[u] * ig.row_elems + q * NS, rowv);
+#pragma unroll
+            for (int i = 0; i < NS; ++i) m[i] += wt[u] * rowv[i];
+          }
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < MT; ++t)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) hn[k][4 * t + rr] = P::act(acc[k][t][rr] + m[4 * t + rr]);
+      if (rd) {   // wave-uniform
+        double pa = 0.0, pp = 0.0;
+        if (nd >= 0) {
+          // readout difference of this node, each side formed as in the full evaluation
+          Acc ta1 = 0, tp1 = 0, ta0 = 0, tp0 = 0;
+#pragma unroll
+          for (int i = 0; i < NS; ++i) {
+            const int f = P::lc(q, i);
+            ta1 += (Acc)x.shead[f] * hn[k][i];
+            tp1 += (Acc)x.shead[F + 3 + f] * hn[k][i];
+            ta0 += (Acc)x.shead[f] * hb[i];
+            tp0 += (Acc)x.shead[F + 3 + f] * hb[i];
+          }
+          pa = (double)ta1 - (double)ta0;
+          pp = (double)tp1 - (double)tp0;
+        }
+        pa = wave_sum(pa);
+        pp = wave_sum(pp);
+        if (lane == 0) {
+          x.red[(2 * w) * kMaxWaves + wv] += pa;
+          x.red[(2 * w + 1) * kMaxWaves + wv] += pp;
+        }
+      }
+      if (WRITE && nd >= 0)   // H^l changed on C_l (after the readout read the old row)
+        lds_write<Acc, NS>(pw + (size_t)(l - 1) * plane + (size_t)nd * F + q * NS, hn[k]);
+    }
+    if (l < Lr) {
+      __syncthreads();   // every gather read of the buffers is done
+#pragma unroll
+      for (int k = 0; k < MAXT; ++k) {
+        if (!tok[k]) continue;
+        const int w = tsw[k], r = trow[k];
+        if (r < jobs.cnt[w][l]) lds_write<Acc, NS>(x.buf + ((size_t)w * ig.rows + r) * ig.row_elems + q * NS, hn[k]);
+      }
+    }
+  }
+}
+
+// compensated sum step (Neumaier)
+__device__ __forceinline__ void inc_neumaier(double& s, double& c, double x) {
+  const double t = s + x;
+  c += (fabs(s) >= fabs(x)) ? ((s - t) + x) : ((x - t) + s);
+  s = t;
+}
+
+// Local energy: the exchanges of the anti-aligned bonds of every sample.
 template <class P, int F, int MAXT>
 __global__ __launch_bounds__(512) void k_eloc_inc(Net net, IncNet inc, IncGeo ig, const int8_t* __restrict__ spins,
                                                   int B, const typename P::Acc* __restrict__ planes, int n_chunks,
                                                   int chunk, double* __restrict__ partial, int* __restrict__ cnt) {
   using Acc = typename P::Acc;
-  using WT = typename P::WT;
-  using CF = typename P::CF;
-  constexpr int NS = F / 4, MT = F / 16, KSB = F / P::KS, VEC = P::VEC;
   constexpr int SM = kIncMaxSwaps;
-  constexpr int VPR = F * (int)sizeof(Acc) / 16;   // 16-byte vectors per row
   extern __shared__ __align__(16) unsigned char smem[];
-  WT* wl = reinterpret_cast<WT*>(smem + ig.off_w);
-  Acc* buf = reinterpret_cast<Acc*>(smem + ig.off_buf);
-  int* tab = reinterpret_cast<int*>(smem + ig.off_tab);
-  int8_t* sp = reinterpret_cast<int8_t*>(smem + ig.off_sp);
-  double* red = reinterpret_cast<double*>(smem + ig.off_red);   // [SM][2][kMaxWaves]
-  Acc* sbias = reinterpret_cast<Acc*>(smem + ig.off_bias);
-  Acc* semb = reinterpret_cast<Acc*>(smem + ig.off_emb);
-  double* shead = reinterpret_cast<double*>(smem + ig.off_head);
-  Acc* sev = reinterpret_cast<Acc*>(smem + ig.off_ev);
-  int* slist = reinterpret_cast<int*>(smem + ig.off_list);       // anti-aligned bonds of the item
-  __shared__ int s_cnt[SM][18];
-  __shared__ int2 s_ij[SM];
+  IncLds<P> x(ig, smem);
+  __shared__ IncJobs jobs;
   __shared__ int s_wc[kMaxWaves];
   __shared__ double s_acc[SM][4];
-
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int q = lane >> 4, col = lane & 15;
-  const int nw = ig.nw, Lr = net.L, dm = inc.dmax, S = ig.S;
-  const int bd = blockDim.x;
+  const int nw = ig.nw, Lr = net.L, S = ig.S, bd = blockDim.x;
   const size_t plane = (size_t)net.g.npad * F;
-
-  // stage weights (tied: one layer) and the small tables
-  {
-    const int nwt = 2 * F * F;
-    const WT* src = reinterpret_cast<const WT*>(net.wfrag);
-    for (int k = threadIdx.x; k < nwt; k += bd) wl[k] = src[k];
-    for (int k = threadIdx.x; k < F; k += bd)
-      sbias[k] = reinterpret_cast<const Acc*>(net.bias)[P::lc(k / NS, k % NS)];   // slot order
-    for (int k = threadIdx.x; k < 2 * F; k += bd) semb[k] = reinterpret_cast<const Acc*>(net.emb)[k];
-    for (int k = threadIdx.x; k < F + 3; k += bd) {
-      shead[k] = net.head_a[k];
-      shead[F + 3 + k] = net.head_p[k];
-    }
-    const Acc* ev = reinterpret_cast<const Acc*>(inc.ell_val);
-    for (int k = threadIdx.x; k < net.n * dm; k += bd) sev[k] = ev[k];
-  }
+  Acc* pl = const_cast<Acc*>(planes);   // read only: inc_group without WRITE
+  inc_stage<P, F>(net, inc, x);
   __syncthreads();
-  auto afrag = [&](int blk, int st, int t) { return wl + (((blk * KSB + st) * MT + t) * 64 + lane) * VEC; };
-  const Acc* bias = sbias + q * NS;
 
   // XCD-aware order: the blocks of one XCD (equal blockIdx % xcd) walk the chunks of
   // the same samples together, so a sample's base planes stay in that XCD's L2
@@ -117,9 +381,8 @@ __global__ __launch_bounds__(512) void k_eloc_inc(Net net, IncNet inc, IncGeo ig
   for (long long jj = slot; jj < per_xcd_items; jj += per_x) {
     const int b = xid + X * (int)(jj / n_chunks), c = (int)(jj % n_chunks);
     const int it = b * n_chunks + c;
-    for (int k = threadIdx.x; k < net.n; k += bd) sp[k] = spins[(size_t)b * net.n + k];
+    for (int k = threadIdx.x; k < net.n; k += bd) x.sp[k] = spins[(size_t)b * net.n + k];
     __syncthreads();
-    const Acc* pb = planes + (size_t)b * 2 * Lr * plane;
     // anti-aligned bonds of the chunk, in bond order (ballot compaction)
     const int e0 = c * chunk, clen = max(0, min(net.ne, e0 + chunk) - e0);
     int nanti = 0;
@@ -127,7 +390,7 @@ __global__ __launch_bounds__(512) void k_eloc_inc(Net net, IncNet inc, IncGeo ig
       int flag = 0;
       if ((int)threadIdx.x < clen) {
         const int2 ij = net.edges[e0 + threadIdx.x];
-        flag = sp[ij.x] != sp[ij.y];
+        flag = x.sp[ij.x] != x.sp[ij.y];
       }
       const unsigned long long m = __ballot(flag);
       if (lane == 0) s_wc[wv] = __popcll(m);
@@ -138,227 +401,36 @@ __global__ __launch_bounds__(512) void k_eloc_inc(Net net, IncNet inc, IncGeo ig
         if (v < wv) before += cv;
         nanti += cv;
       }
-      if (flag) slist[before + __popcll(m & ((1ull << lane) - 1ull))] = e0 + threadIdx.x;
+      if (flag) x.slist[before + __popcll(m & ((1ull << lane) - 1ull))] = e0 + threadIdx.x;
     }
-    // per-swap-slot compensated sums (thread w accumulates slot w)
+    // per-job-slot compensated sums (thread w accumulates slot w)
     double sr = 0, cr = 0, si = 0, ci = 0;
     for (int g0 = 0; g0 < nanti; g0 += S) {
       const int nsw = min(S, nanti - g0);
-      __syncthreads();   // slist visible; the previous group is done with tab / red
-      // tables of the group -> LDS (16-byte vectors)
-      {
-        for (int k = threadIdx.x; k < nsw * (Lr + 2); k += bd) {
-          const int w = k / (Lr + 2), l = k % (Lr + 2);
-          s_cnt[w][l] = inc.ball_cnt[slist[g0 + w] * (Lr + 2) + l];
-        }
-        if ((int)threadIdx.x < nsw) s_ij[threadIdx.x] = net.edges[slist[g0 + threadIdx.x]];
-        const int tv = ig.tabw / 4;
-        for (int k = threadIdx.x; k < nsw * tv; k += bd) {
-          const int w = k / tv, v = k % tv;
-          const int eg = slist[g0 + w];
-          const int nr = inc.ball_cnt[eg * (Lr + 2) + Lr];
-          const int nv = (inc.r4 + nr * dm) / 4;   // this bond's table, in vectors
-          if (v < nv)
-            reinterpret_cast<int4*>(tab + w * ig.tabw)[v] =
-                reinterpret_cast<const int4*>(inc.ball_tab + inc.ball_off[eg])[v];
-        }
+      __syncthreads();   // slist visible; the previous group is done with the job tables
+      if ((int)threadIdx.x < nsw) {
+        const int w = threadIdx.x, eg = x.slist[g0 + w];
+        jobs.e[w] = eg;
+        jobs.ij[w] = net.edges[eg];
+        jobs.flags[w] = kJobSwap | kJobReadout;
+        jobs.spoff[w] = 0;
+        jobs.pboff[w] = (long long)b * 2 * Lr * plane;
       }
       __syncthreads();
-      // the exchanged configuration of swap w: spin of node nd
-      auto xnew = [&](int w, int nd) {
-        const int2 ij = s_ij[w];
-        const int8_t v = (nd == ij.x) ? sp[ij.y] : ((nd == ij.y) ? sp[ij.x] : sp[nd]);
-        return v > 0 ? 1 : 0;
-      };
-      for (int l = 1; l <= Lr; ++l) {
-        const Acc* Hbase = pb + (size_t)(l - 2) * plane;           // H^{l-1} (l >= 2)
-        const Acc* Gbase = pb + (size_t)(Lr + l - 1) * plane;      // G^{l-1}
-        // ---- base G^{l-1} rows of the nodes at distance l+1 -> buffer (issued first)
-        uint4 cvv[kIncCopy];
-        int cdst[kIncCopy];
-        int ctot = 0;
-        {
-          int cst[SM + 1];
-          cst[0] = 0;
-#pragma unroll
-          for (int w = 0; w < SM; ++w)
-            cst[w + 1] = cst[w] + (w < nsw ? (s_cnt[w][l + 1] - s_cnt[w][l]) * VPR : 0);
-          ctot = cst[SM];
-          // copy item idx -> (source vector, byte offset of the destination in LDS)
-          auto locate = [&](int idx, const uint4*& src) {
-            int w = 0, start = 0;
-#pragma unroll
-            for (int u = 1; u < SM; ++u)
-              if (idx >= cst[u]) { w = u; start = cst[u]; }
-            const int rel = idx - start;
-            const int rr = s_cnt[w][l] + rel / VPR, v = rel % VPR;
-            const int nd = tab[w * ig.tabw + rr];
-            src = reinterpret_cast<const uint4*>(Gbase + (size_t)nd * F) + v;
-            return ig.off_buf + ((w * ig.rows + rr) * ig.row_elems) * (int)sizeof(Acc) + 16 * v;
-          };
-#pragma unroll
-          for (int u = 0; u < kIncCopy; ++u) {
-            const int idx = threadIdx.x + u * bd;
-            const uint4* src = reinterpret_cast<const uint4*>(Gbase);   // in-bounds placeholder
-            cdst[u] = -1;
-            if (idx < ctot) cdst[u] = locate(idx, src);
-            cvv[u] = *src;   // unconditional, so the value stays in registers
-          }
-          for (int idx = threadIdx.x + kIncCopy * bd; idx < ctot; idx += bd) {   // rare: large rings
-            const uint4* src;
-            const int o = locate(idx, src);
-            *reinterpret_cast<uint4*>(smem + o) = *src;
-          }
-        }
-        // ---- this wave's tiles: inputs
-        Acc h[MAXT][NS];
-        int trow[MAXT], tsw[MAXT];
-        bool tok[MAXT];
-#pragma unroll
-        for (int k = 0; k < MAXT; ++k) {
-          const int g = wv + k * nw;
-          const int w = g % nsw, tt = g / nsw;
-          tsw[k] = w;
-          tok[k] = tt * 16 < s_cnt[w][l];
-          trow[k] = tt * 16 + col;
-        }
-        auto load_h = [&](int k) {
-          const int w = tsw[k], r = trow[k];
-          const int cl = s_cnt[w][l], cp = s_cnt[w][l - 1];
-          const int nd = r < cl ? tab[w * ig.tabw + r] : -1;
-          if (l == 1) {
-            const int x = nd >= 0 ? xnew(w, nd) : 0;
-#pragma unroll
-            for (int i = 0; i < NS; ++i) h[k][i] = nd >= 0 ? semb[x * F + P::lc(q, i)] : (Acc)0;
-          } else if (r < cp) {
-            lds_read<Acc, NS>(buf + ((size_t)w * ig.rows + r) * ig.row_elems + q * NS, h[k]);   // H'^{l-1}
-          } else if (nd >= 0) {
-            gmem_read<Acc, NS>(Hbase + (size_t)nd * F + q * NS, h[k]);                       // base H^{l-1}
-          } else {
-#pragma unroll
-            for (int i = 0; i < NS; ++i) h[k][i] = (Acc)0;
-          }
-        };
-        // ---- products: self -> registers, message -> buffer rows [0, |C_l|) in place
-        CF acc[MAXT][MT];
-#pragma unroll
-        for (int k = 0; k < MAXT; ++k) {
-          if (!tok[k]) continue;
-          load_h(k);
-          const int w = tsw[k], r = trow[k];
-          const bool wr = r < s_cnt[w][l];
-          Acc* row = buf + ((size_t)w * ig.rows + r) * ig.row_elems + q * NS;
-#pragma unroll
-          for (int t = 0; t < MT; ++t) {
-            CF a, gs = CF{0, 0, 0, 0};
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr) a[rr] = bias[4 * t + rr];
-#pragma unroll
-            for (int st = 0; st < KSB; ++st) {
-              const auto bop = P::make_b(&h[k][st * VEC]);
-              gs = P::mma(P::load_a(afrag(0, st, t)), bop, gs);
-              a = P::mma(P::load_a(afrag(1, st, t)), bop, a);
-            }
-            acc[k][t] = a;
-            if (wr) {
-              Acc gm[4] = {gs[0], gs[1], gs[2], gs[3]};
-              lds_write<Acc, 4>(row + 4 * t, gm);
-            }
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < kIncCopy; ++u)
-          if (cdst[u] >= 0) *reinterpret_cast<uint4*>(smem + cdst[u]) = cvv[u];
-        __syncthreads();   // every G^{l-1} row of every swap is in its buffer
-        // ---- gather, activation; readout difference at the last layer
-        if (l == Lr && lane == 0)
-          for (int w = 0; w < nsw; ++w) red[(2 * w) * kMaxWaves + wv] = red[(2 * w + 1) * kMaxWaves + wv] = 0.0;
-        Acc hn[MAXT][NS];
-#pragma unroll
-        for (int k = 0; k < MAXT; ++k) {
-          if (!tok[k]) continue;
-          const int w = tsw[k], r = trow[k];
-          const int cl = s_cnt[w][l];
-          const int* tw = tab + w * ig.tabw;
-          const int nd = r < cl ? tw[r] : -1;
-          const Acc* bw = buf + (size_t)w * ig.rows * ig.row_elems;
-          Acc hb[NS];
-          if (l == Lr && nd >= 0) gmem_read<Acc, NS>(pb + (size_t)(Lr - 1) * plane + (size_t)nd * F + q * NS, hb);
-          Acc m[NS];
-#pragma unroll
-          for (int i = 0; i < NS; ++i) m[i] = (Acc)0;
-          if (nd >= 0) {
-            const int* nbp = tw + inc.r4 + r * dm;
-            for (int d = 0; d < dm; d += 4) {
-              const int4 pv = *reinterpret_cast<const int4*>(nbp + d);
-              const int pc[4] = {pv.x, pv.y, pv.z, pv.w};
-              const Acc* wp = sev + nd * dm + d;
-              const Acc wt[4] = {wp[0], wp[1], wp[2], wp[3]};
-#pragma unroll
-              for (int u = 0; u < 4; ++u) {
-                Acc rowv[NS];
-                lds_read<Acc, NS>(bw + pc[u] * ig.row_elems + q * NS, rowv);
-#pragma unroll
-                for (int i = 0; i < NS; ++i) m[i] += wt[u] * rowv[i];
-              }
-            }
-          }
-#pragma unroll
-          for (int t = 0; t < MT; ++t)
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr) hn[k][4 * t + rr] = P::act(acc[k][t][rr] + m[4 * t + rr]);
-          if (l == Lr) {
-            double pa = 0.0, pp = 0.0;
-            if (nd >= 0) {
-              // readout difference of this node, each side formed as in the full evaluation
-              Acc ta1 = 0, tp1 = 0, ta0 = 0, tp0 = 0;
-#pragma unroll
-              for (int i = 0; i < NS; ++i) {
-                const int f = P::lc(q, i);
-                ta1 += (Acc)shead[f] * hn[k][i];
-                tp1 += (Acc)shead[F + 3 + f] * hn[k][i];
-                ta0 += (Acc)shead[f] * hb[i];
-                tp0 += (Acc)shead[F + 3 + f] * hb[i];
-              }
-              pa = (double)ta1 - (double)ta0;
-              pp = (double)tp1 - (double)tp0;
-            }
-            pa = wave_sum(pa);
-            pp = wave_sum(pp);
-            if (lane == 0) {
-              red[(2 * w) * kMaxWaves + wv] += pa;
-              red[(2 * w + 1) * kMaxWaves + wv] += pp;
-            }
-          }
-        }
-        if (l < Lr) {
-          __syncthreads();   // every gather read of the buffers is done
-#pragma unroll
-          for (int k = 0; k < MAXT; ++k) {
-            if (!tok[k]) continue;
-            const int w = tsw[k], r = trow[k];
-            if (r < s_cnt[w][l]) lds_write<Acc, NS>(buf + ((size_t)w * ig.rows + r) * ig.row_elems + q * NS, hn[k]);
-          }
-        }
-      }
+      inc_group<P, F, MAXT, false>(net, inc, ig, x, jobs, nsw, pl, smem);
       __syncthreads();   // readout partials of every wave
       if ((int)threadIdx.x < nsw) {
         const int w = threadIdx.x;
         double da = 0.0, dp = 0.0;
         for (int v = 0; v < nw; ++v) {
-          da += red[(2 * w) * kMaxWaves + v];
-          dp += red[(2 * w + 1) * kMaxWaves + v];
+          da += x.red[(2 * w) * kMaxWaves + v];
+          dp += x.red[(2 * w + 1) * kMaxWaves + v];
         }
         const double mm = exp(da);
         double sn, cs;
         sincos(dp, &sn, &cs);
-        const double xr = mm * cs, xi = mm * sn;
-        double t = sr + xr;
-        cr += (fabs(sr) >= fabs(xr)) ? ((sr - t) + xr) : ((xr - t) + sr);
-        sr = t;
-        t = si + xi;
-        ci += (fabs(si) >= fabs(xi)) ? ((si - t) + xi) : ((xi - t) + si);
-        si = t;
+        inc_neumaier(sr, cr, mm * cs);
+        inc_neumaier(si, ci, mm * sn);
       }
     }
     // combine the slots in slot order
@@ -370,15 +442,9 @@ __global__ __launch_bounds__(512) void k_eloc_inc(Net net, IncNet inc, IncGeo ig
     if (threadIdx.x == 0) {
       double tr = 0, tcr = 0, ti = 0, tci = 0;
       for (int w = 0; w < min(S, SM); ++w) {
-        double x = s_acc[w][0];
-        double t = tr + x;
-        tcr += (fabs(tr) >= fabs(x)) ? ((tr - t) + x) : ((x - t) + tr);
-        tr = t;
+        inc_neumaier(tr, tcr, s_acc[w][0]);
         tcr += s_acc[w][1];
-        x = s_acc[w][2];
-        t = ti + x;
-        tci += (fabs(ti) >= fabs(x)) ? ((ti - t) + x) : ((x - t) + ti);
-        ti = t;
+        inc_neumaier(ti, tci, s_acc[w][2]);
         tci += s_acc[w][3];
       }
       double* o = partial + 4 * (size_t)it;
@@ -386,6 +452,145 @@ __global__ __launch_bounds__(512) void k_eloc_inc(Net net, IncNet inc, IncGeo ig
       cnt[it] = nanti;
     }
     __syncthreads();
+  }
+}
+
+// Metropolis spin-swap sweeps (Section 3.2) with incremental proposals.  Slot w of
+// block x runs chains x + (w + S k) * gridDim.x one after the other; the draws are
+// the ones of the full-recompute sampler (Philox4x32-10, counter (step, chain, 0),
+// key = seed), and a proposal is accepted when u < exp(2 Re Delta).  The chains'
+// planes must hold their current configurations (base pass) and are kept current.
+// log psi is not tracked here: the caller evaluates the final configurations.
+template <class P, int F, int MAXT>
+__global__ __launch_bounds__(512) void k_sweep_inc(Net net, IncNet inc, IncGeo ig, int8_t* __restrict__ spins,
+                                                   typename P::Acc* planes, int B, int n_sweeps,
+                                                   unsigned long long seed, unsigned long long counter_base,
+                                                   int* __restrict__ n_accept) {
+  constexpr int SM = kIncMaxSwaps;
+  extern __shared__ __align__(16) unsigned char smem[];
+  IncLds<P> x(ig, smem);
+  __shared__ IncJobs jobs;
+  __shared__ int s_chain[SM], s_acc[SM], s_prop[SM], s_pend[SM], s_job[SM], s_done[SM], s_jslot[SM];
+  __shared__ long long s_t[SM];
+  __shared__ double s_u[SM];
+  __shared__ int s_nsw, s_switch;
+  const int nw = ig.nw, S = ig.S, bd = blockDim.x;
+  const size_t per_chain = (size_t)2 * net.L * net.g.npad * F;
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  const long long total = (long long)n_sweeps * net.n;
+  inc_stage<P, F>(net, inc, x);
+  if ((int)threadIdx.x < S) {
+    const int w = threadIdx.x;
+    const int b = blockIdx.x + w * gridDim.x;
+    s_chain[w] = b < B ? b : -1;
+    s_t[w] = 0;
+    s_acc[w] = 0;
+    s_pend[w] = -1;
+  }
+  __syncthreads();
+  for (int w = 0; w < S; ++w)
+    if (s_chain[w] >= 0)
+      for (int k = threadIdx.x; k < net.n; k += bd) x.sp[w * ig.spw + k] = spins[(size_t)s_chain[w] * net.n + k];
+  while (true) {
+    __syncthreads();
+    // each slot's next job: a pending restore, else its next anti-aligned proposal
+    if ((int)threadIdx.x < S) {
+      const int w = threadIdx.x, b = s_chain[w];
+      int job = 0;   // 0 none, 1 proposal, 2 restore
+      s_done[w] = 0;
+      if (b >= 0) {
+        if (s_pend[w] >= 0) {
+          job = 2;
+        } else {
+          const int8_t* spw = x.sp + w * ig.spw;
+          long long t = s_t[w];
+          while (t < total) {
+            const unsigned long long step = counter_base + (unsigned long long)t;
+            uint32_t c[4] = {(uint32_t)step, (uint32_t)(step >> 32), (uint32_t)b, 0u};
+            philox4x32_10(c, k0, k1);
+            const int e = (int)(((unsigned long long)c[0] * (unsigned long long)net.ne) >> 32);
+            const int2 ij = net.edges[e];
+            if (spw[ij.x] != spw[ij.y]) {
+              s_prop[w] = e;   // the proposal's bond
+              s_u[w] = ((double)c[1] + 0.5) * 2.3283064365386963e-10;   // 2^-32
+              job = 1;
+              break;
+            }
+            ++t;   // identity step
+          }
+          s_t[w] = t;
+          if (!job) s_done[w] = 1;
+        }
+      }
+      s_job[w] = job;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int sw = 0, k = 0;
+      for (int w = 0; w < S; ++w) {
+        sw |= s_done[w];
+        if (s_job[w]) s_jslot[k++] = w;
+      }
+      s_switch = sw;
+      s_nsw = k;
+    }
+    __syncthreads();
+    if (s_switch) {
+      // finished chains: spins and acceptance count out, the slot's next chain in
+      for (int w = 0; w < S; ++w) {
+        if (!s_done[w]) continue;
+        const int b = s_chain[w];
+        for (int k = threadIdx.x; k < net.n; k += bd) spins[(size_t)b * net.n + k] = x.sp[w * ig.spw + k];
+        const int nb = b + S * gridDim.x;
+        if (nb < B)
+          for (int k = threadIdx.x; k < net.n; k += bd) x.sp[w * ig.spw + k] = spins[(size_t)nb * net.n + k];
+      }
+      __syncthreads();
+      if ((int)threadIdx.x < S && s_done[threadIdx.x]) {
+        const int w = threadIdx.x, b = s_chain[w];
+        if (n_accept) n_accept[b] = s_acc[w];
+        const int nb = b + S * gridDim.x;
+        s_chain[w] = nb < B ? nb : -1;
+        s_t[w] = 0;
+        s_acc[w] = 0;
+        s_pend[w] = -1;
+      }
+      continue;   // select again (a slot's proposal is drawn again: its t is unchanged)
+    }
+    const int nsw = s_nsw;
+    if (nsw == 0) break;
+    if ((int)threadIdx.x < nsw) {
+      const int j = threadIdx.x, w = s_jslot[j];
+      const int e = s_job[w] == 1 ? s_prop[w] : s_pend[w];
+      jobs.e[j] = e;
+      jobs.ij[j] = net.edges[e];
+      jobs.flags[j] = s_job[w] == 1 ? (kJobSwap | kJobReadout) : 0;
+      jobs.spoff[j] = w * ig.spw;
+      jobs.pboff[j] = (long long)s_chain[w] * (long long)per_chain;
+    }
+    __syncthreads();
+    inc_group<P, F, MAXT, true>(net, inc, ig, x, jobs, nsw, planes, smem);
+    __syncthreads();   // readout partials of every wave
+    if ((int)threadIdx.x < nsw) {
+      const int j = threadIdx.x, w = s_jslot[j];
+      if (s_job[w] == 1) {
+        double da = 0.0;
+        for (int v = 0; v < nw; ++v) da += x.red[(2 * j) * kMaxWaves + v];
+        if (s_u[w] < exp(2.0 * da)) {   // accept: the planes already hold the new rows
+          int8_t* spw = x.sp + w * ig.spw;
+          const int2 ij = jobs.ij[j];
+          const int8_t tmp = spw[ij.x];
+          spw[ij.x] = spw[ij.y];
+          spw[ij.y] = tmp;
+          ++s_acc[w];
+        } else {
+          s_pend[w] = s_prop[w];   // reject: the restore job of this bond comes next
+        }
+        ++s_t[w];
+      } else {
+        s_pend[w] = -1;   // restored
+      }
+    }
   }
 }
 

@@ -178,13 +178,14 @@ def test_anisotropic_couplings():
     g.close()
 
 
-def test_sampler_fp64_trajectory_matches_oracle():
+@pytest.mark.parametrize("mode", ["full", "incremental"])
+def test_sampler_fp64_trajectory_matches_oracle(mode):
     # both sides draw the same Philox4x32-10 stream and decide in FP64
     n, e = w.kagome(2, 2)
     F, L = 16, 2
     theta = w.glorot_theta(F, L, True, seed=3, weight_scale=2.0, bias_std=0.3)
     s0 = w.random_sz0_spins(64, n, 11)
-    g = _ctx(n, e, F, L, True, "fp64", max_batch=64)
+    g = _ctx(n, e, F, L, True, "fp64", max_batch=64, eloc_mode=mode)
     th = _dev(theta)
     sp = _dev(s0)
     lp = g.logpsi(th, sp)
@@ -197,13 +198,14 @@ def test_sampler_fp64_trajectory_matches_oracle():
     g.close()
 
 
+@pytest.mark.parametrize("mode", ["full", "incremental"])
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
-def test_sampler_reduced_precision_invariants(prec):
+def test_sampler_reduced_precision_invariants(prec, mode):
     n, e = w.kagome(6, 6)
     F, L = 32, 4
     theta = w.glorot_theta(F, L, True, seed=3, weight_scale=2.0, bias_std=0.3)
     s0 = w.random_sz0_spins(32, n, 12)
-    g = _ctx(n, e, F, L, True, prec, max_batch=32)
+    g = _ctx(n, e, F, L, True, prec, max_batch=32, eloc_mode=mode)
     th, sp = _dev(theta), _dev(s0)
     lp = g.logpsi(th, sp)
     acc = g.metropolis_sweep(th, sp, lp, n_sweeps=1, seed=99)
@@ -367,3 +369,80 @@ def test_incremental_isgo_grad_matches_full():
     (g0, s0, e0), (g1, s1, e1) = out
     assert np.max(np.abs(g0 - g1)) < 1e-11 * np.max(np.abs(g0))
     assert abs(s0[0] - s1[0]) < 1e-11 * abs(s0[0]) and s0[6] == s1[6]
+
+
+# ---------------------------------------------------------------------------
+# incremental Metropolis proposals (ball recomputed, planes updated in place)
+# ---------------------------------------------------------------------------
+def _sweep(g, theta, s0, n_sweeps, seed, counter_base=0):
+    th, sp = _dev(theta), _dev(s0)
+    lp = g.logpsi(th, sp)
+    acc = g.metropolis_sweep(th, sp, lp, n_sweeps=n_sweeps, seed=seed, counter_base=counter_base)
+    return sp.cpu().numpy(), lp.cpu().numpy(), acc.cpu().numpy()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("case", TIED, ids=[c[0] for c in TIED])
+def test_incremental_sampler_matches_full_sampler(case, prec):
+    # the proposals' log-psi differences agree to FP64 rounding, so both samplers
+    # take the same decisions on the same Philox draws
+    name, build, F, L, tied, B = case
+    n, e = build()
+    theta = w.glorot_theta(F, L, tied, seed=5, weight_scale=1.5, bias_std=0.3)
+    s0 = w.random_sz0_spins(max(B, 8), n, 2000 + B)
+    out = {}
+    for mode in ("full", "incremental"):
+        g = _ctx(n, e, F, L, tied, prec, max_batch=len(s0), eloc_mode=mode)
+        out[mode] = _sweep(g, theta, s0, 2, seed=4242, counter_base=9)
+        g.close()
+    (sf, lf, af), (si, li, ai) = out["full"], out["incremental"]
+    print(f"[gpu] incremental sampler {name} {prec}: accepted {ai.sum()} of {len(s0) * 2 * n} draws",
+          file=sys.stderr, flush=True)
+    assert np.array_equal(si, sf) and np.array_equal(ai, af)
+    assert np.array_equal(li, lf)   # both evaluate the final configurations fully
+    assert np.all(si.sum(1) == s0.sum(1))
+
+
+def test_incremental_sampler_then_local_energy():
+    # after the sweep the planes hold the final configurations; a following local
+    # energy (which rebuilds them) must agree with the full mode on those spins
+    n, e = w.kagome(6, 6)
+    F, L = 32, 4
+    theta = w.glorot_theta(F, L, True, seed=8, weight_scale=1.5, bias_std=0.3)
+    s0 = w.random_sz0_spins(24, n, 31)
+    g = _ctx(n, e, F, L, True, "fp64", max_batch=24, eloc_mode="incremental")
+    th, sp = _dev(theta), _dev(s0)
+    lp = g.logpsi(th, sp)
+    g.metropolis_sweep(th, sp, lp, n_sweeps=1, seed=5)
+    el, _ = g.local_energy(th, sp)
+    g.close()
+    ref = oracle.local_energy(theta, sp.cpu().numpy(), n, e, F, L)
+    assert np.max(np.abs(el.cpu().numpy()[:, 0] - ref.real)) < 1e-11 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_incremental_sampler_full_size_matches_full_sampler():
+    # 432-site Kagome, L=6, F=64, BF16: a few chains, one sweep, both samplers
+    p = w.preset("kagome432_L6F64")
+    n, e = p.build_graph()
+    theta = w.glorot_theta(p.n_features, p.n_layers, True, seed=p.theta_seed)
+    s0 = w.random_sz0_spins(16, n, p.spin_seed)
+    out = {}
+    for mode in ("full", "incremental"):
+        g = _ctx(n, e, p.n_features, p.n_layers, True, "bf16", max_batch=16, eloc_mode=mode)
+        out[mode] = _sweep(g, theta, s0, 1, seed=77)
+        g.close()
+    (sf, lf, af), (si, li, ai) = out["full"], out["incremental"]
+    print(f"[gpu] incremental sampler kagome432 bf16: accepted {ai.sum()} of {16 * n}", file=sys.stderr, flush=True)
+    assert np.array_equal(si, sf) and np.array_equal(ai, af) and np.array_equal(li, lf)
+
+
+def test_incremental_sampler_zero_sweeps_and_small_batch():
+    n, e = w.kagome(2, 2)
+    theta = w.glorot_theta(16, 2, True, seed=2, weight_scale=1.5, bias_std=0.3)
+    s0 = w.random_sz0_spins(5, n, 3)
+    g = _ctx(n, e, 16, 2, True, "fp32", max_batch=8, eloc_mode="incremental")
+    s1, _, acc = _sweep(g, theta, s0, 0, seed=1)
+    assert np.array_equal(s1, s0) and np.all(acc == 0)
+    s2, lp2, acc2 = _sweep(g, theta, s0[:1], 3, seed=1)
+    assert s2.shape == (1, n) and s2.sum() == 0
+    g.close()
