@@ -70,14 +70,17 @@ enum {
  *             sum is taken in FP64 from the FP32 last-layer output.          */
 enum { GNA_FP64 = 0, GNA_FP32 = 1, GNA_BF16 = 2 };
 
-/* How gna_local_energy evaluates log psi(s^ij):
+/* How gna_local_energy and gna_metropolis_sweep evaluate log psi(s^ij):
  *   GNA_ELOC_FULL: every exchanged configuration through all L layers.
  *   GNA_ELOC_INCREMENTAL: only the nodes within graph distance l of the two
  *     exchanged sites are recomputed at layer l (the rest of the configuration
  *     is unchanged there), from per-sample planes of the base configuration kept
  *     in device memory (2 L x N x F values per sample).  The recomputed rows use
  *     the same arithmetic as the full evaluation, so both modes give the same
- *     log psi differences up to the order of the final FP64 sum.            */
+ *     log psi differences up to the order of the final FP64 sum.  The sampler
+ *     keeps each chain's planes current: an accepted proposal's rows stay, a
+ *     rejected one is recomputed for the unexchanged configuration.
+ *     Needs tied weights and n_layers >= 1.                                   */
 enum { GNA_ELOC_FULL = 0, GNA_ELOC_INCREMENTAL = 1 };
 
 typedef struct {
@@ -142,6 +145,9 @@ gna_status gna_local_energy(gna_ctx *ctx, const double *theta, const int8_t *spi
  * the swap is accepted iff u < exp(2 Re[log psi(s^ij) - log psi(s)]).
  * spins [B][N] and logpsi [B][2] are read and updated in place; logpsi must
  * hold the chains' current values (e.g. from gna_logpsi on this context).
+ * In GNA_ELOC_INCREMENTAL mode the difference is taken from the recomputed
+ * receptive field, and logpsi is overwritten at the end by the full evaluation
+ * of the final configurations (bitwise what gna_logpsi returns for them).
  * n_accept: [B] int32 output (accepted swaps), may be NULL.                */
 gna_status gna_metropolis_sweep(gna_ctx *ctx, const double *theta, int8_t *spins,
                                 double *logpsi, int32_t B, int32_t n_sweeps,
