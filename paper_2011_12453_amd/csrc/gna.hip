@@ -525,10 +525,10 @@ struct gna_ctx {
   int eloc_mode = 0;
   IncGeo igeo{};
   IncKern ik{};
-  int grid_inc_base = 1, grid_inc = 1, grid_sweep_inc = 1, inc_r4 = 4, inc_chunk_cap = 64;
-  int* d_ball_off = nullptr;
+  int grid_inc_base = 1, grid_inc = 1, grid_sweep_inc = 1, inc_r8 = 8, inc_chunk_cap = 64;
+  int2* d_ball_meta = nullptr;
   int* d_ball_cnt = nullptr;
-  int* d_ball_tab = nullptr;
+  uint16_t* d_ball_tab = nullptr;
   void* d_inc_planes = nullptr;   // [max_batch][2L][npad][F] Acc
   // reverse pass (FP32 for the FP32/BF16 modes, FP64 for FP64)
   Geo vgeo{};
@@ -666,8 +666,8 @@ gna_status run_logpsi(gna_ctx* c, const double* theta, const int8_t* spins, int 
 
 IncNet make_inc(const gna_ctx* c) {
   IncNet inc{};
-  inc.n = c->N; inc.F = c->F; inc.L = c->L; inc.dmax = c->dmax; inc.r4 = c->inc_r4;
-  inc.ball_off = c->d_ball_off; inc.ball_cnt = c->d_ball_cnt; inc.ball_tab = c->d_ball_tab;
+  inc.n = c->N; inc.F = c->F; inc.L = c->L; inc.dmax = c->dmax; inc.r8 = c->inc_r8;
+  inc.ball_meta = c->d_ball_meta; inc.ball_cnt = c->d_ball_cnt; inc.ball_tab = c->d_ball_tab;
   inc.ell_val = c->d_val;
   return inc;
 }
@@ -1084,31 +1084,35 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
         max_ball = std::max(max_ball, cnt[(size_t)e * (L + 2) + L]);
       }
     }
-    const int r4 = (max_rows + 3) / 4 * 4;
+    const int r8 = (max_rows + 7) / 8 * 8;
     const int max_tiles = (max_ball + 15) / 16;
-    // per bond: r4 node slots, then |C_L| x dmax neighbour list positions
-    std::vector<int> off(std::max(E, 1), 0), tabv;
+    // per bond: r8 node slots, then |C_L| x dmax neighbour list positions (16-bit
+    // entries: N <= 4096), padded to whole 16-byte vectors
+    std::vector<int2> meta(std::max(E, 1), int2{0, 0});
+    std::vector<uint16_t> tabv;
     {
       std::vector<int> pos(N, -1);
       for (int e = 0; e < E; ++e) {
         const std::vector<int>& lst = lists[e];
-        off[e] = (int)tabv.size();
-        for (int r = 0; r < r4; ++r) tabv.push_back(r < (int)lst.size() ? lst[r] : -1);
+        meta[e].x = (int)tabv.size();
+        for (int r = 0; r < r8; ++r) tabv.push_back(r < (int)lst.size() ? (uint16_t)lst[r] : (uint16_t)0xffff);
         for (size_t r = 0; r < lst.size(); ++r) pos[lst[r]] = (int)r;
         const int nball = cnt[(size_t)e * (L + 2) + L];
         for (int r = 0; r < nball; ++r)
           for (int d = 0; d < dmax; ++d) {
             const int m = idx[(size_t)lst[r] * dmax + d];   // a neighbour of C_L lies in C_{L+1}
             if (pos[m] < 0) return bail(GNA_UNSUPPORTED, "ball table: neighbour outside C_{L+1}");
-            tabv.push_back(pos[m]);
+            tabv.push_back((uint16_t)pos[m]);
           }
+        while (tabv.size() % 8) tabv.push_back(0);
+        meta[e].y = (int)(tabv.size() - meta[e].x) / 8;
         for (int nd : lst) pos[nd] = -1;
       }
     }
     IncGeo& ig = c->igeo;
     ig.xcd = 8;   // MI355X: 8 XCDs, workgroups assigned round-robin
     ig.rows = max_rows;
-    ig.tabw = r4 + max_ball * dmax;
+    ig.tabw = (r8 + max_ball * dmax + 7) / 8 * 8;
     ig.row_elems = (int)((4 * (F / 4) * c->sz_Acc + kRowPadBytes) / c->sz_Acc);
     const int chunk_cap = 64 * kMaxWaves / 2;   // bonds per work item: at most one per thread
     // largest number of exchanges in flight that fits in LDS and in four tiles per wave
@@ -1127,7 +1131,7 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
       t.nw = nw;
       t.off_w = (int)o; o = al(o + w_bytes);
       t.off_buf = (int)o; o = al(o + (size_t)S * max_rows * ig.row_elems * c->sz_Acc);
-      t.off_tab = (int)o; o = al(o + (size_t)S * ig.tabw * 4);
+      t.off_tab = (int)o; o = al(o + (size_t)S * ig.tabw * 2);
       t.spw = (int)al(g.npad);
       t.off_sp = (int)o; o = al(o + (size_t)S * t.spw);
       t.off_red = (int)o; o = al(o + (size_t)kIncMaxSwaps * 2 * kMaxWaves * 8);
@@ -1164,17 +1168,17 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
       c->grid_inc = c->n_cu * occ2(c->ik.eloc, 64 * ig.nw, ig.lds_bytes);
       c->grid_sweep_inc = c->n_cu * occ2(c->ik.sweep, 64 * ig.nw, ig.lds_bytes);
     }
-    c->inc_r4 = r4;
+    c->inc_r8 = r8;
     const size_t plane_bytes = (size_t)g.npad * F * c->sz_Acc;
-    if ((st = dev_alloc(c, &c->d_ball_off, off.size() * 4)) ||
+    if ((st = dev_alloc(c, &c->d_ball_meta, meta.size() * 8)) ||
         (st = dev_alloc(c, &c->d_ball_cnt, cnt.size() * 4)) ||
-        (st = dev_alloc(c, &c->d_ball_tab, std::max<size_t>(4, tabv.size()) * 4)) ||
+        (st = dev_alloc(c, &c->d_ball_tab, std::max<size_t>(8, tabv.size()) * 2)) ||
         (st = dev_alloc(c, &c->d_inc_planes, (size_t)MB * 2 * std::max(L, 1) * plane_bytes)))
       return bail(st, c->err);
-    he = hipMemcpy(c->d_ball_off, off.data(), off.size() * 4, hipMemcpyHostToDevice);
+    he = hipMemcpy(c->d_ball_meta, meta.data(), meta.size() * 8, hipMemcpyHostToDevice);
     if (he == hipSuccess) he = hipMemcpy(c->d_ball_cnt, cnt.data(), cnt.size() * 4, hipMemcpyHostToDevice);
     if (he == hipSuccess && !tabv.empty())
-      he = hipMemcpy(c->d_ball_tab, tabv.data(), tabv.size() * 4, hipMemcpyHostToDevice);
+      he = hipMemcpy(c->d_ball_tab, tabv.data(), tabv.size() * 2, hipMemcpyHostToDevice);
     if (he != hipSuccess) return bail(GNA_HIP_ERROR, std::string("hipMemcpy: ") + hipGetErrorString(he));
   }
   he = hipMemcpy(c->d_edges, hedges.data(), hedges.size() * 4, hipMemcpyHostToDevice);

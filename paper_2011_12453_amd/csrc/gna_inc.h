@@ -41,11 +41,11 @@ namespace gna {
 
 struct IncNet {
   int n, F, L, dmax;
-  int r4;                  // node-list slots per bond (max |C_{L+1}| rounded up to 4)
-  const int* ball_off;     // [ne] first int of bond e's table (multiple of 4)
+  int r8;                  // node-list slots per bond (max |C_{L+1}| rounded up to 8)
+  const int2* ball_meta;   // [ne] (first entry of bond e's table (multiple of 8), its length in 16-byte vectors)
   const int* ball_cnt;     // [ne][L+2] |C_l|, l = 0 .. L+1
-  const int* ball_tab;     // per bond: r4 node ids of C_{L+1} (-1 padded), then |C_L| x dmax
-                           // neighbour list positions; 4-int aligned
+  const uint16_t* ball_tab;   // per bond: r8 node ids of C_{L+1}, then |C_L| x dmax neighbour
+                              // list positions, padded to a multiple of 8 entries
   const void* ell_val;     // [npad][dmax] A_hat in Acc precision
 };
 
@@ -55,7 +55,7 @@ struct IncGeo {
   int S;            // jobs (exchanges) in flight per workgroup (<= kIncMaxSwaps)
   int row_elems;    // LDS row stride in Acc elements
   int rows;         // buffer rows per job (max |C_{L+1}|)
-  int tabw;         // ints per job table in LDS (r4 + max|C_L| * dmax, multiple of 4)
+  int tabw;         // entries per job table in LDS (r8 + max|C_L| * dmax, multiple of 8)
   int spw;          // bytes per spin configuration in LDS
   int off_w, off_buf, off_tab, off_sp, off_red, off_bias, off_emb, off_head, off_ev, off_list;
   int xcd;          // items are grouped per XCD (blocks b with equal b % xcd share a sample)
@@ -77,6 +77,7 @@ struct IncJobs {
   int flags[kIncMaxSwaps];
   int spoff[kIncMaxSwaps];     // byte offset of the job's spins in the spin area
   long long pboff[kIncMaxSwaps];   // element offset of the job's planes
+  int2 meta[kIncMaxSwaps];         // ball_meta of the job's bond
 };
 
 // LDS views of the incremental kernels
@@ -84,24 +85,24 @@ template <class P>
 struct IncLds {
   typename P::WT* wl;
   typename P::Acc* buf;
-  int* tab;
+  uint16_t* tab;
   int8_t* sp;
   double* red;                 // [kIncMaxSwaps][2][kMaxWaves]
   typename P::Acc* sbias;
   typename P::Acc* semb;
-  double* shead;
+  typename P::Acc* shead;      // [2][F] readout weights v_a, v_p in Acc, slot order
   typename P::Acc* sev;
   int* slist;
   __device__ IncLds(const IncGeo& ig, unsigned char* smem) {
     using Acc = typename P::Acc;
     wl = reinterpret_cast<typename P::WT*>(smem + ig.off_w);
     buf = reinterpret_cast<Acc*>(smem + ig.off_buf);
-    tab = reinterpret_cast<int*>(smem + ig.off_tab);
+    tab = reinterpret_cast<uint16_t*>(smem + ig.off_tab);
     sp = reinterpret_cast<int8_t*>(smem + ig.off_sp);
     red = reinterpret_cast<double*>(smem + ig.off_red);
     sbias = reinterpret_cast<Acc*>(smem + ig.off_bias);
     semb = reinterpret_cast<Acc*>(smem + ig.off_emb);
-    shead = reinterpret_cast<double*>(smem + ig.off_head);
+    shead = reinterpret_cast<Acc*>(smem + ig.off_head);
     sev = reinterpret_cast<Acc*>(smem + ig.off_ev);
     slist = reinterpret_cast<int*>(smem + ig.off_list);
   }
@@ -119,16 +120,17 @@ __device__ void inc_stage(const Net& net, const IncNet& inc, const IncLds<P>& x)
   for (int k = threadIdx.x; k < F; k += bd)
     x.sbias[k] = reinterpret_cast<const Acc*>(net.bias)[P::lc(k / NS, k % NS)];   // slot order
   for (int k = threadIdx.x; k < 2 * F; k += bd) x.semb[k] = reinterpret_cast<const Acc*>(net.emb)[k];
-  for (int k = threadIdx.x; k < F + 3; k += bd) {
-    x.shead[k] = net.head_a[k];
-    x.shead[F + 3 + k] = net.head_p[k];
+  for (int k = threadIdx.x; k < F; k += bd) {
+    const int f = P::lc(k / NS, k % NS);
+    x.shead[k] = (Acc)net.head_a[f];
+    x.shead[F + k] = (Acc)net.head_p[f];
   }
   const Acc* ev = reinterpret_cast<const Acc*>(inc.ell_val);
   for (int k = threadIdx.x; k < net.n * inc.dmax; k += bd) x.sev[k] = ev[k];
 }
 
 // One group of nsw jobs: tables -> LDS, then layers 1..L over the jobs' balls.
-// Entry: jobs.{ij, e, flags, spoff, pboff} written and visible (after a barrier).
+// Entry: jobs.{ij, e, flags, spoff, pboff, meta} written and visible (after a barrier).
 // Exit: readout partials of job j in red[(2j + {0,1}) * kMaxWaves + wave] for jobs
 // with kJobReadout (the caller synchronises before reading them).  With WRITE the
 // recomputed rows are stored into the jobs' planes.
@@ -145,7 +147,6 @@ __device__ void inc_group(const Net& net, const IncNet& inc, const IncGeo& ig, c
   const int q = lane >> 4, col = lane & 15;
   const int nw = ig.nw, Lr = net.L, dm = inc.dmax, bd = blockDim.x;
   const size_t plane = (size_t)net.g.npad * F;
-  auto afrag = [&](int blk, int st, int t) { return x.wl + (((blk * KSB + st) * MT + t) * 64 + lane) * VEC; };
   const Acc* bias = x.sbias + q * NS;
 
   // tables of the group -> LDS (16-byte vectors)
@@ -154,14 +155,11 @@ __device__ void inc_group(const Net& net, const IncNet& inc, const IncGeo& ig, c
     jobs.cnt[w][l] = inc.ball_cnt[jobs.e[w] * (Lr + 2) + l];
   }
   {
-    const int tv = ig.tabw / 4;
+    const int tv = ig.tabw / 8;
     for (int k = threadIdx.x; k < nsw * tv; k += bd) {
       const int w = k / tv, v = k % tv;
-      const int eg = jobs.e[w];
-      const int nr = inc.ball_cnt[eg * (Lr + 2) + Lr];
-      const int nv = (inc.r4 + nr * dm) / 4;   // this bond's table, in vectors
-      if (v < nv)
-        reinterpret_cast<int4*>(x.tab + w * ig.tabw)[v] = reinterpret_cast<const int4*>(inc.ball_tab + inc.ball_off[eg])[v];
+      const int2 mt = jobs.meta[w];
+      if (v < mt.y) reinterpret_cast<int4*>(x.tab + w * ig.tabw)[v] = reinterpret_cast<const int4*>(inc.ball_tab + mt.x)[v];
     }
   }
   __syncthreads();
@@ -174,7 +172,8 @@ __device__ void inc_group(const Net& net, const IncNet& inc, const IncGeo& ig, c
     return v > 0 ? 1 : 0;
   };
   for (int l = 1; l <= Lr; ++l) {
-    // ---- base G^{l-1} rows of the nodes at distance l+1 -> buffer (issued first)
+    // ---- base G^{l-1} rows of the nodes at distance l+1 -> buffer (requested first,
+    // stored after this wave's products)
     using V4 = unsigned int __attribute__((ext_vector_type(4)));
     V4 cvv[kIncCopy];
     int cdst[kIncCopy];
@@ -224,6 +223,24 @@ __device__ void inc_group(const Net& net, const IncNet& inc, const IncGeo& ig, c
       trow[k] = tt * 16 + col;
     }
     // ---- products: self -> registers, message -> buffer rows [0, |C_l|) in place
+    // layer input of tile k: embedding (l = 1), H'^{l-1} from the buffer, or base H^{l-1}
+    auto load_in = [&](int k, Acc (&h)[NS]) {
+      const int w = tsw[k], r = trow[k];
+      const int cl = jobs.cnt[w][l], cp = jobs.cnt[w][l - 1];
+      const int nd = r < cl ? x.tab[w * ig.tabw + r] : -1;
+      if (l == 1) {
+        const int xs = nd >= 0 ? xspin(w, nd) : 0;
+#pragma unroll
+        for (int i = 0; i < NS; ++i) h[i] = nd >= 0 ? x.semb[xs * F + P::lc(q, i)] : (Acc)0;
+      } else if (r < cp) {
+        lds_read<Acc, NS>(x.buf + ((size_t)w * ig.rows + r) * ig.row_elems + q * NS, h);
+      } else if (nd >= 0) {
+        gmem_read<Acc, NS>(planes + jobs.pboff[w] + (size_t)(l - 2) * plane + (size_t)nd * F + q * NS, h);
+      } else {
+#pragma unroll
+        for (int i = 0; i < NS; ++i) h[i] = (Acc)0;
+      }
+    };
     CF acc[MAXT][MT];
 #pragma unroll
     for (int k = 0; k < MAXT; ++k) {
@@ -233,19 +250,9 @@ __device__ void inc_group(const Net& net, const IncNet& inc, const IncGeo& ig, c
       const int nd = r < cl ? x.tab[w * ig.tabw + r] : -1;
       Acc* pw = planes + jobs.pboff[w];
       Acc h[NS];
-      if (l == 1) {
-        const int xs = nd >= 0 ? xspin(w, nd) : 0;
-#pragma unroll
-        for (int i = 0; i < NS; ++i) h[i] = nd >= 0 ? x.semb[xs * F + P::lc(q, i)] : (Acc)0;
-      } else if (r < cp) {
-        lds_read<Acc, NS>(x.buf + ((size_t)w * ig.rows + r) * ig.row_elems + q * NS, h);       // H'^{l-1}
-      } else if (nd >= 0) {
-        gmem_read<Acc, NS>(pw + (size_t)(l - 2) * plane + (size_t)nd * F + q * NS, h);     // base H^{l-1}
-      } else {
-#pragma unroll
-        for (int i = 0; i < NS; ++i) h[i] = (Acc)0;
-      }
+      load_in(k, h);
       Acc* row = x.buf + ((size_t)w * ig.rows + r) * ig.row_elems + q * NS;
+      auto afr = [&](int blk, int st, int t) { return x.wl + (((blk * KSB + st) * MT + t) * 64 + lane) * VEC; };
 #pragma unroll
       for (int t = 0; t < MT; ++t) {
         CF a, gs = CF{0, 0, 0, 0};
@@ -254,8 +261,8 @@ __device__ void inc_group(const Net& net, const IncNet& inc, const IncGeo& ig, c
 #pragma unroll
         for (int st = 0; st < KSB; ++st) {
           const auto bop = P::make_b(&h[st * VEC]);
-          gs = P::mma(P::load_a(afrag(0, st, t)), bop, gs);
-          a = P::mma(P::load_a(afrag(1, st, t)), bop, a);
+          gs = P::mma(P::load_a(afr(0, st, t)), bop, gs);
+          a = P::mma(P::load_a(afr(1, st, t)), bop, a);
         }
         acc[k][t] = a;
         Acc gm[4] = {gs[0], gs[1], gs[2], gs[3]};
@@ -277,21 +284,26 @@ __device__ void inc_group(const Net& net, const IncNet& inc, const IncGeo& ig, c
       if (!tok[k]) continue;
       const int w = tsw[k], r = trow[k];
       const int cl = jobs.cnt[w][l];
-      const int* tw = x.tab + w * ig.tabw;
+      const uint16_t* tw = x.tab + w * ig.tabw;
       const int nd = r < cl ? tw[r] : -1;
       const Acc* bw = x.buf + (size_t)w * ig.rows * ig.row_elems;
       Acc* pw = planes + jobs.pboff[w];
-      const bool rd = l == Lr && (jobs.flags[w] & kJobReadout);
-      Acc hb[NS];
-      if (rd && nd >= 0) gmem_read<Acc, NS>(pw + (size_t)(Lr - 1) * plane + (size_t)nd * F + q * NS, hb);
+      const bool last = l == Lr;
+      const bool rd = last && (jobs.flags[w] & kJobReadout);
+      Acc r0[2] = {(Acc)0, (Acc)0};   // base readout partials of the node
+      if (rd && nd >= 0) {
+        const Acc* rp = pw + (size_t)(Lr - 1) * plane + (size_t)nd * 8 + q * 2;
+        r0[0] = rp[0];
+        r0[1] = rp[1];
+      }
       Acc m[NS];
 #pragma unroll
       for (int i = 0; i < NS; ++i) m[i] = (Acc)0;
       if (nd >= 0) {
-        const int* nbp = tw + inc.r4 + r * dm;
+        const uint16_t* nbp = tw + inc.r8 + r * dm;
         for (int d = 0; d < dm; d += 4) {
-          const int4 pv = *reinterpret_cast<const int4*>(nbp + d);
-          const int pc[4] = {pv.x, pv.y, pv.z, pv.w};
+          const uint2 pv = *reinterpret_cast<const uint2*>(nbp + d);
+          const int pc[4] = {(int)(pv.x & 0xffffu), (int)(pv.x >> 16), (int)(pv.y & 0xffffu), (int)(pv.y >> 16)};
           const Acc* wp = x.sev + nd * dm + d;
           const Acc wt[4] = {wp[0], wp[1], wp[2], wp[3]};
 #pragma unroll
@@ -307,31 +319,34 @@ __device__ void inc_group(const Net& net, const IncNet& inc, const IncGeo& ig, c
       for (int t = 0; t < MT; ++t)
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) hn[k][4 * t + rr] = P::act(acc[k][t][rr] + m[4 * t + rr]);
-      if (rd) {   // wave-uniform
-        double pa = 0.0, pp = 0.0;
-        if (nd >= 0) {
-          // readout difference of this node, each side formed as in the full evaluation
-          Acc ta1 = 0, tp1 = 0, ta0 = 0, tp0 = 0;
+      if (last && (rd || WRITE)) {   // wave-uniform
+        // readout partials of this node, formed as in the full evaluation
+        Acc va[NS], vp[NS];
+        lds_read<Acc, NS>(x.shead + q * NS, va);
+        lds_read<Acc, NS>(x.shead + F + q * NS, vp);
+        Acc ta1 = 0, tp1 = 0;
 #pragma unroll
-          for (int i = 0; i < NS; ++i) {
-            const int f = P::lc(q, i);
-            ta1 += (Acc)x.shead[f] * hn[k][i];
-            tp1 += (Acc)x.shead[F + 3 + f] * hn[k][i];
-            ta0 += (Acc)x.shead[f] * hb[i];
-            tp0 += (Acc)x.shead[F + 3 + f] * hb[i];
+        for (int i = 0; i < NS; ++i) {
+          ta1 += va[i] * hn[k][i];
+          tp1 += vp[i] * hn[k][i];
+        }
+        if (rd) {
+          double pa = nd >= 0 ? (double)ta1 - (double)r0[0] : 0.0;
+          double pp = nd >= 0 ? (double)tp1 - (double)r0[1] : 0.0;
+          pa = wave_sum(pa);
+          pp = wave_sum(pp);
+          if (lane == 0) {
+            x.red[(2 * w) * kMaxWaves + wv] += pa;
+            x.red[(2 * w + 1) * kMaxWaves + wv] += pp;
           }
-          pa = (double)ta1 - (double)ta0;
-          pp = (double)tp1 - (double)tp0;
         }
-        pa = wave_sum(pa);
-        pp = wave_sum(pp);
-        if (lane == 0) {
-          x.red[(2 * w) * kMaxWaves + wv] += pa;
-          x.red[(2 * w + 1) * kMaxWaves + wv] += pp;
+        if (WRITE && nd >= 0) {   // after the base partials were read
+          const Acc rv[2] = {ta1, tp1};
+          lds_write<Acc, 2>(pw + (size_t)(Lr - 1) * plane + (size_t)nd * 8 + q * 2, rv);
         }
-      }
-      if (WRITE && nd >= 0)   // H^l changed on C_l (after the readout read the old row)
+      } else if (WRITE && !last && nd >= 0) {   // H^l changed on C_l
         lds_write<Acc, NS>(pw + (size_t)(l - 1) * plane + (size_t)nd * F + q * NS, hn[k]);
+      }
     }
     if (l < Lr) {
       __syncthreads();   // every gather read of the buffers is done
@@ -403,8 +418,9 @@ __global__ __launch_bounds__(512) void k_eloc_inc(Net net, IncNet inc, IncGeo ig
       }
       if (flag) x.slist[before + __popcll(m & ((1ull << lane) - 1ull))] = e0 + threadIdx.x;
     }
-    // per-job-slot compensated sums (thread w accumulates slot w)
-    double sr = 0, cr = 0, si = 0, ci = 0;
+    // per-job-slot compensated sums in LDS (thread w accumulates slot w)
+    if ((int)threadIdx.x < SM)
+      s_acc[threadIdx.x][0] = s_acc[threadIdx.x][1] = s_acc[threadIdx.x][2] = s_acc[threadIdx.x][3] = 0.0;
     for (int g0 = 0; g0 < nanti; g0 += S) {
       const int nsw = min(S, nanti - g0);
       __syncthreads();   // slist visible; the previous group is done with the job tables
@@ -412,6 +428,7 @@ __global__ __launch_bounds__(512) void k_eloc_inc(Net net, IncNet inc, IncGeo ig
         const int w = threadIdx.x, eg = x.slist[g0 + w];
         jobs.e[w] = eg;
         jobs.ij[w] = net.edges[eg];
+        jobs.meta[w] = inc.ball_meta[eg];
         jobs.flags[w] = kJobSwap | kJobReadout;
         jobs.spoff[w] = 0;
         jobs.pboff[w] = (long long)b * 2 * Lr * plane;
@@ -429,15 +446,11 @@ __global__ __launch_bounds__(512) void k_eloc_inc(Net net, IncNet inc, IncGeo ig
         const double mm = exp(da);
         double sn, cs;
         sincos(dp, &sn, &cs);
-        inc_neumaier(sr, cr, mm * cs);
-        inc_neumaier(si, ci, mm * sn);
+        inc_neumaier(s_acc[w][0], s_acc[w][1], mm * cs);
+        inc_neumaier(s_acc[w][2], s_acc[w][3], mm * sn);
       }
     }
     // combine the slots in slot order
-    if ((int)threadIdx.x < SM) {
-      s_acc[threadIdx.x][0] = sr; s_acc[threadIdx.x][1] = cr;
-      s_acc[threadIdx.x][2] = si; s_acc[threadIdx.x][3] = ci;
-    }
     __syncthreads();
     if (threadIdx.x == 0) {
       double tr = 0, tcr = 0, ti = 0, tci = 0;
@@ -564,6 +577,7 @@ __global__ __launch_bounds__(512) void k_sweep_inc(Net net, IncNet inc, IncGeo i
       const int e = s_job[w] == 1 ? s_prop[w] : s_pend[w];
       jobs.e[j] = e;
       jobs.ij[j] = net.edges[e];
+      jobs.meta[j] = inc.ball_meta[e];
       jobs.flags[j] = s_job[w] == 1 ? (kJobSwap | kJobReadout) : 0;
       jobs.spoff[j] = w * ig.spw;
       jobs.pboff[j] = (long long)s_chain[w] * (long long)per_chain;

@@ -401,8 +401,10 @@ __device__ void load_spins(const Net& net, const Smem<P>& s, const int8_t* __res
 //   npad x F values, element (node, q, i) at node * F + q * F/4 + i (slot
 //   order); H^l is plane l, M^l plane L + 1 + l.
 //   STORE == 2: write the base planes of the incremental local energy: layer
-//   outputs H^1..H^L as planes 0..L-1 and message products G^l = H^l W_msg
-//   (l = 0..L-1) as planes L..2L-1, same element order.
+//   outputs H^1..H^{L-1} as planes 0..L-2, the layer-L readout partials (per
+//   node and lane quad q, the pair (t_a, t_p) of Acc sums v . H^L over the
+//   quad's slots) in plane L-1 at node * 8 + q * 2, and message products
+//   G^l = H^l W_msg (l = 0..L-1) as planes L..2L-1, same element order.
 // ---------------------------------------------------------------------------
 template <class P, int F, int TPW, int NCH, int STORE = 0>
 __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
@@ -645,8 +647,14 @@ __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
         pa += (double)ta;
         pp += (double)tp;
       }
-      if constexpr (STORE == 2)
-        lds_write<Acc, NS>(store + l * plane + node[k] * F + q * NS, h[k]);
+      if constexpr (STORE == 2) {
+        if (!last) {
+          lds_write<Acc, NS>(store + l * plane + node[k] * F + q * NS, h[k]);
+        } else if (tile_ok[k]) {   // layer L: the node's readout partials, not its row
+          const Acc rv[2] = {ta, tp};
+          lds_write<Acc, 2>(store + l * plane + node[k] * 8 + q * 2, rv);
+        }
+      }
     }
   }
   if constexpr (STORE == 1) {
