@@ -153,6 +153,21 @@ gna_status gna_metropolis_sweep(gna_ctx *ctx, const double *theta, int8_t *spins
                                 double *logpsi, int32_t B, int32_t n_sweeps,
                                 uint64_t seed, uint64_t counter_base, int32_t *n_accept);
 
+/* One variational step on device-resident state, everything enqueued on the
+ * context's stream with no host synchronisation, so that a caller can capture it
+ * in a HIP graph and replay it (Section 3's loop of sampling, energy and update):
+ *   1. logpsi <- log psi(spins)                               (gna_logpsi)
+ *   2. n_sweeps Metropolis sweeps with counter base *counter  (gna_metropolis_sweep)
+ *   3. *counter += n_sweeps * N                               (device side)
+ *   4. ISGO gradient with logpsi as the sampling distribution (gna_isgo_grad;
+ *      grad [P], stats [8], eloc [B][2] or NULL)
+ *   5. theta -= lr * grad                                     (gna_sgd_update)
+ * counter: device uint64, read and advanced on the device, so every replay of a
+ * captured step draws new proposals.  All pointers are device pointers.      */
+gna_status gna_step(gna_ctx *ctx, double *theta, int8_t *spins, double *logpsi, int32_t B,
+                    int32_t n_sweeps, uint64_t seed, uint64_t *counter, double lr, double *grad,
+                    double *stats, double *eloc, int32_t *n_accept);
+
 /* Reverse pass: grad[P] = sum_x cot[x][0] d log|psi(s_x)|/dtheta
  *                         + cot[x][1] d phase(s_x)/dtheta   (overwritten).
  * Computed in FP64 for every precision mode; per-layer activations are

@@ -59,6 +59,10 @@ _EXPORTS = {
                                        ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p]),
     "gna_sgd_update": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double]),
+    "gna_step": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_void_p,
+                                  ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_void_p]),
     "gna_profile_enable": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "gna_profile_read": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_char_p,
                                           ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
@@ -216,6 +220,29 @@ class GNA:
         theta, grad = self._theta(theta), self._theta(grad)
         self._check(self._lib.gna_sgd_update(self._ctx, _ptr(theta), _ptr(grad), float(alpha)))
         return theta
+
+    def step(self, theta, spins, logpsi, n_sweeps: int, seed: int, counter, lr: float,
+             grad=None, stats=None, eloc=None, n_accept=None):
+        """One device-resident step (``gna_step``): log psi, sweeps, counter advance, ISGO
+        gradient, SGD.  ``counter`` is a device uint64 tensor of one element (int64 dtype).
+        Returns ``(grad[P], stats[8], eloc[B, 2], n_accept[B])``."""
+        theta, spins = self._theta(theta), self._spins(spins)
+        B = spins.shape[0]
+        logpsi = self._t(logpsi, torch.float64, (B, 2), "logpsi")
+        counter = self._t(counter, torch.int64, (1,), "counter")
+        grad = self._empty((self.num_params,)) if grad is None else self._theta(grad)
+        stats = self._empty((8,)) if stats is None else self._t(stats, torch.float64, (8,), "stats")
+        eloc = self._empty((B, 2)) if eloc is None else self._t(eloc, torch.float64, (B, 2), "eloc")
+        acc = self._empty((B,), torch.int32) if n_accept is None else self._t(n_accept, torch.int32, (B,), "n_accept")
+        self._check(self._lib.gna_step(self._ctx, _ptr(theta), _ptr(spins), _ptr(logpsi), B, int(n_sweeps),
+                                       ctypes.c_uint64(seed), _ptr(counter), float(lr), _ptr(grad),
+                                       _ptr(stats), _ptr(eloc), _ptr(acc)))
+        return grad, stats, eloc, acc
+
+    def set_stream(self, stream):
+        """Enqueue later calls on ``stream`` (a torch.cuda.Stream), e.g. a graph-capture stream."""
+        self._check(self._lib.gna_set_stream(self._ctx, ctypes.c_void_p(stream.cuda_stream)))
+        self._stream = stream
 
     def profile_enable(self, on: bool = True):
         """Bracket every launch with HIP events on the context's stream."""

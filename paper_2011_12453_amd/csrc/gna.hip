@@ -145,6 +145,11 @@ __global__ void k_zero_i64(long long* p, int n) {
   if (i < n) p[i] = 0;
 }
 
+// device-resident Philox counter base of the sampler: advanced by each step
+__global__ void k_add_u64(unsigned long long* p, unsigned long long d) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p += d;
+}
+
 __global__ void k_eloc_finalize(const int8_t* __restrict__ spins, int N, const int2* __restrict__ edges,
                                 int E, double jz, double jxy, int B, int n_chunks,
                                 const double* __restrict__ partial, const int* __restrict__ cnt,
@@ -172,9 +177,12 @@ __global__ void k_eloc_finalize(const int8_t* __restrict__ spins, int N, const i
 template <class P, int F, int TPW, int NCH>
 __global__ __launch_bounds__(512) void k_sweep(Net net, int8_t* __restrict__ spins, double* __restrict__ logpsi,
                                                 int B, int n_sweeps, unsigned long long seed,
-                                                unsigned long long counter_base, int* __restrict__ n_accept) {
+                                                unsigned long long counter_base,
+                                                const unsigned long long* __restrict__ counter_dev,
+                                                int* __restrict__ n_accept) {
   extern __shared__ __align__(16) unsigned char smem[];
   Smem<P> s(net.g, smem);
+  if (counter_dev) counter_base += *counter_dev;   // graph replays read the current base
   stage_graph<P>(net, s);
   if (net.tied) stage_weights<P, F>(net, s, 0);
   __syncthreads();
@@ -418,26 +426,27 @@ struct IncKern {
   const void* eloc = nullptr;    // k_eloc_inc
   const void* sweep = nullptr;   // k_sweep_inc
 };
-template <class P, int F, int MAXT>
+template <class P, int F, int MAXT, int NT = 512>
 void inc_fill(IncKern& k) {
-  k.eloc = reinterpret_cast<const void*>(&k_eloc_inc<P, F, MAXT>);
-  k.sweep = reinterpret_cast<const void*>(&k_sweep_inc<P, F, MAXT>);
+  k.eloc = reinterpret_cast<const void*>(&k_eloc_inc<P, F, MAXT, NT>);
+  k.sweep = reinterpret_cast<const void*>(&k_sweep_inc<P, F, MAXT, NT>);
 }
 template <class P, int F>
-IncKern inc_pick(int tpw, int nch, int maxt) {
+IncKern inc_pick(int tpw, int nch, int maxt, bool wide) {
   IncKern k;
   k.base = inc_base_pick<P, F>(tpw, nch);
-  if (maxt == 1) inc_fill<P, F, 1>(k);
+  if (wide) inc_fill<P, F, 1, 1024>(k);   // 16 waves, one tile each
+  else if (maxt == 1) inc_fill<P, F, 1>(k);
   else if (maxt == 2) inc_fill<P, F, 2>(k);
   else if (maxt == 3) inc_fill<P, F, 3>(k);
   else inc_fill<P, F, 4>(k);
   return k;
 }
 template <class P>
-IncKern inc_pick_f(int F, int tpw, int nch, int maxt) {
-  if (F == 16) return inc_pick<P, 16>(tpw, nch, maxt);
-  if (F == 32) return inc_pick<P, 32>(tpw, nch, maxt);
-  return inc_pick<P, 64>(tpw, nch, maxt);
+IncKern inc_pick_f(int F, int tpw, int nch, int maxt, bool wide) {
+  if (F == 16) return inc_pick<P, 16>(tpw, nch, maxt, wide);
+  if (F == 32) return inc_pick<P, 32>(tpw, nch, maxt, wide);
+  return inc_pick<P, 64>(tpw, nch, maxt, wide);
 }
 
 // reverse-pass kernels of one (precision, F, TPW, NCH) instantiation (FP32 or FP64)
@@ -526,6 +535,7 @@ struct gna_ctx {
   IncGeo igeo{};
   IncKern ik{};
   int grid_inc_base = 1, grid_inc = 1, grid_sweep_inc = 1, inc_r8 = 8, inc_chunk_cap = 64;
+  bool inc_wide = false;   // 16-wave incremental kernels
   int2* d_ball_meta = nullptr;
   int* d_ball_cnt = nullptr;
   uint16_t* d_ball_tab = nullptr;
@@ -1119,11 +1129,14 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
     int maxt = 0;
     int s_cap = kIncMaxSwaps;
     if (const char* ev = std::getenv("GNA_INC_MAX_SWAPS")) s_cap = std::max(1, std::min(kIncMaxSwaps, std::atoi(ev)));
+    // 8 waves with up to 4 tiles each; the 16-wave shape (one tile per wave, 128
+    // VGPRs) is kept for the tuner
+    const bool wide = c->inc_wide;
     for (int S = s_cap; S >= 1; --S) {
       const int tiles = S * max_tiles;
-      const int nw = std::min(kMaxWaves / 2, tiles);
+      const int nw = std::min(wide ? kMaxWaves : kMaxWaves / 2, tiles);
       const int mt = (tiles + nw - 1) / nw;   // tiles per wave: 1 .. 4
-      if (mt > 4) continue;
+      if (mt > (wide ? 1 : 4)) continue;
       size_t o = 0;
       auto al = [](size_t x) { return (x + 15) & ~(size_t)15; };
       IncGeo t = ig;
@@ -1140,6 +1153,7 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
       t.off_head = (int)o; o = al(o + (size_t)2 * (F + 3) * 8);
       t.off_ev = (int)o; o = al(o + (size_t)N * dmax * c->sz_Acc);
       t.off_list = (int)o; o = al(o + (size_t)chunk_cap * 4);
+      t.off_cpy = (int)o; o = al(o + (size_t)S * max_rows * 16);
       t.lds_bytes = (int)o;
       if (o + 2048 > lds_max) continue;   // static LDS of the kernels
       ig = t;
@@ -1149,12 +1163,12 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
     if (maxt == 0) return bail(GNA_UNSUPPORTED, "incremental local energy does not fit in LDS");
     c->inc_chunk_cap = std::min(chunk_cap, 64 * ig.nw);
     switch (c->prec) {
-      case GNA_FP64: c->ik = inc_pick_f<PF64>(F, tpw, nch, maxt); break;
-      case GNA_FP32: c->ik = inc_pick_f<PF32>(F, tpw, nch, maxt); break;
+      case GNA_FP64: c->ik = inc_pick_f<PF64>(F, tpw, nch, maxt, wide); break;
+      case GNA_FP32: c->ik = inc_pick_f<PF32>(F, tpw, nch, maxt, wide); break;
       default:
-        if (F == 16) c->ik = inc_pick<PBF16, 16>(tpw, nch, maxt);
-        else if (F == 32) c->ik = inc_pick<PBF16W, 32>(tpw, nch, maxt);
-        else c->ik = inc_pick<PBF16W, 64>(tpw, nch, maxt);
+        if (F == 16) c->ik = inc_pick<PBF16, 16>(tpw, nch, maxt, wide);
+        else if (F == 32) c->ik = inc_pick<PBF16W, 32>(tpw, nch, maxt, wide);
+        else c->ik = inc_pick<PBF16W, 64>(tpw, nch, maxt, wide);
     }
     {
       auto occ2 = [&](const void* fn, int threads_, int lds) {
@@ -1249,14 +1263,9 @@ gna_status gna_local_energy(gna_ctx* c, const double* theta, const int8_t* spins
   return run_eloc(c, theta, spins, B, c->d_base, eloc, nev);
 }
 
-gna_status gna_metropolis_sweep(gna_ctx* c, const double* theta, int8_t* spins, double* logpsi, int32_t B,
-                                int32_t n_sweeps, uint64_t seed, uint64_t counter_base, int32_t* n_accept) {
-  if (!c) return GNA_INVALID_ARG;
-  if (gna_status st = check_batch(c, B)) return st;
-  if (n_sweeps < 0) return fail(c, GNA_INVALID_ARG, "n_sweeps must be >= 0");
-  if (!valid_ptr(theta) || (B > 0 && (!valid_ptr(spins) || !valid_ptr(logpsi))))
-    return fail(c, GNA_INVALID_ARG, "NULL pointer argument");
-  if (c->E == 0 && n_sweeps > 0) return fail(c, GNA_INVALID_ARG, "graph has no bonds to propose");
+static gna_status run_sweep(gna_ctx* c, const double* theta, int8_t* spins, double* logpsi, int32_t B,
+                            int32_t n_sweeps, uint64_t seed, uint64_t counter_base,
+                            const unsigned long long* counter_dev, int32_t* n_accept) {
   if (B == 0) return GNA_OK;
   if (gna_status st = prepare(c, theta)) return st;
   Net net = make_net(c, theta);
@@ -1281,7 +1290,7 @@ gna_status gna_metropolis_sweep(gna_ctx* c, const double* theta, int8_t* spins, 
     int* acc = n_accept;
     {
       Timed tm(c, "k_sweep_inc");
-      void* a2[] = {&net, &inc, &ig, &spins, &planes, &Bv, &ns, &sd, &cb, &acc};
+      void* a2[] = {&net, &inc, &ig, &spins, &planes, &Bv, &ns, &sd, &cb, &counter_dev, &acc};
       hipError_t e = hipLaunchKernel(c->ik.sweep, dim3(grid_s), dim3(64 * ig.nw), a2, (size_t)ig.lds_bytes, c->stream);
       if (e != hipSuccess) return hip_fail(c, e, "k_sweep_inc");
     }
@@ -1292,8 +1301,19 @@ gna_status gna_metropolis_sweep(gna_ctx* c, const double* theta, int8_t* spins, 
   int Bv = B, ns = n_sweeps;
   unsigned long long sd = seed, cb = counter_base;
   int* acc = n_accept;
-  void* args[] = {&net, &spins, &logpsi, &Bv, &ns, &sd, &cb, &acc};
+  void* args[] = {&net, &spins, &logpsi, &Bv, &ns, &sd, &cb, &counter_dev, &acc};
   return launch(c, c->kern.sweep, grid, args, "k_sweep");
+}
+
+gna_status gna_metropolis_sweep(gna_ctx* c, const double* theta, int8_t* spins, double* logpsi, int32_t B,
+                                int32_t n_sweeps, uint64_t seed, uint64_t counter_base, int32_t* n_accept) {
+  if (!c) return GNA_INVALID_ARG;
+  if (gna_status st = check_batch(c, B)) return st;
+  if (n_sweeps < 0) return fail(c, GNA_INVALID_ARG, "n_sweeps must be >= 0");
+  if (!valid_ptr(theta) || (B > 0 && (!valid_ptr(spins) || !valid_ptr(logpsi))))
+    return fail(c, GNA_INVALID_ARG, "NULL pointer argument");
+  if (c->E == 0 && n_sweeps > 0) return fail(c, GNA_INVALID_ARG, "graph has no bonds to propose");
+  return run_sweep(c, theta, spins, logpsi, B, n_sweeps, seed, counter_base, nullptr, n_accept);
 }
 
 gna_status gna_logpsi_vjp(gna_ctx* c, const double* theta, const int8_t* spins, int32_t B, const double* cot,
@@ -1334,6 +1354,31 @@ gna_status gna_sgd_update(gna_ctx* c, double* theta, const double* grad, double 
   Timed tm(c, "k_sgd");
   hipLaunchKernelGGL(k_sgd, dim3((n + 255) / 256), dim3(256), 0, c->stream, theta, grad, alpha, n);
   return check_launch(c, "k_sgd");
+}
+
+gna_status gna_step(gna_ctx* c, double* theta, int8_t* spins, double* logpsi, int32_t B, int32_t n_sweeps,
+                    uint64_t seed, uint64_t* counter, double lr, double* grad, double* stats, double* eloc,
+                    int32_t* n_accept) {
+  if (!c) return GNA_INVALID_ARG;
+  if (gna_status st = check_batch(c, B)) return st;
+  if (n_sweeps < 0) return fail(c, GNA_INVALID_ARG, "n_sweeps must be >= 0");
+  if (!std::isfinite(lr)) return fail(c, GNA_INVALID_ARG, "lr must be finite");
+  if (!valid_ptr(theta) || !valid_ptr(counter) || !valid_ptr(grad) || !valid_ptr(stats) ||
+      (B > 0 && (!valid_ptr(spins) || !valid_ptr(logpsi))))
+    return fail(c, GNA_INVALID_ARG, "NULL pointer argument");
+  if (c->E == 0 && n_sweeps > 0) return fail(c, GNA_INVALID_ARG, "graph has no bonds to propose");
+  if (gna_status st = prepare(c, theta)) return st;
+  if (gna_status st = run_logpsi(c, theta, spins, B, logpsi)) return st;
+  unsigned long long* cd = reinterpret_cast<unsigned long long*>(counter);
+  if (gna_status st = run_sweep(c, theta, spins, logpsi, B, n_sweeps, seed, 0, cd, n_accept)) return st;
+  {
+    Timed tm(c, "k_add_u64");
+    hipLaunchKernelGGL(k_add_u64, dim3(1), dim3(64), 0, c->stream, cd,
+                       (unsigned long long)n_sweeps * (unsigned long long)c->N);
+  }
+  if (gna_status st = check_launch(c, "k_add_u64")) return st;
+  if (gna_status st = gna_isgo_grad(c, theta, spins, logpsi, nullptr, B, grad, stats, eloc)) return st;
+  return gna_sgd_update(c, theta, grad, lr);
 }
 
 gna_status gna_profile_enable(gna_ctx* c, int32_t on) {

@@ -57,7 +57,7 @@ struct IncGeo {
   int rows;         // buffer rows per job (max |C_{L+1}|)
   int tabw;         // entries per job table in LDS (r8 + max|C_L| * dmax, multiple of 8)
   int spw;          // bytes per spin configuration in LDS
-  int off_w, off_buf, off_tab, off_sp, off_red, off_bias, off_emb, off_head, off_ev, off_list;
+  int off_w, off_buf, off_tab, off_sp, off_red, off_bias, off_emb, off_head, off_ev, off_list, off_cpy;
   int xcd;          // items are grouped per XCD (blocks b with equal b % xcd share a sample)
   int lds_bytes;
 };
@@ -78,6 +78,7 @@ struct IncJobs {
   int spoff[kIncMaxSwaps];     // byte offset of the job's spins in the spin area
   long long pboff[kIncMaxSwaps];   // element offset of the job's planes
   int2 meta[kIncMaxSwaps];         // ball_meta of the job's bond
+  int2 lay[17];                    // layer l: (first copy-list entry, copy rows) of the group
 };
 
 // LDS views of the incremental kernels
@@ -93,6 +94,7 @@ struct IncLds {
   typename P::Acc* shead;      // [2][F] readout weights v_a, v_p in Acc, slot order
   typename P::Acc* sev;
   int* slist;
+  int4* cpy;                   // ring-row copy list of the group: (source offset lo, hi, LDS destination, 0)
   __device__ IncLds(const IncGeo& ig, unsigned char* smem) {
     using Acc = typename P::Acc;
     wl = reinterpret_cast<typename P::WT*>(smem + ig.off_w);
@@ -105,6 +107,7 @@ struct IncLds {
     shead = reinterpret_cast<Acc*>(smem + ig.off_head);
     sev = reinterpret_cast<Acc*>(smem + ig.off_ev);
     slist = reinterpret_cast<int*>(smem + ig.off_list);
+    cpy = reinterpret_cast<int4*>(smem + ig.off_cpy);
   }
 };
 
@@ -130,11 +133,11 @@ __device__ void inc_stage(const Net& net, const IncNet& inc, const IncLds<P>& x)
 }
 
 // One group of nsw jobs: tables -> LDS, then layers 1..L over the jobs' balls.
-// Entry: jobs.{ij, e, flags, spoff, pboff, meta} written and visible (after a barrier).
+// Entry: jobs.{ij, e, flags, spoff, pboff, meta, cnt} written and visible (after a barrier).
 // Exit: readout partials of job j in red[(2j + {0,1}) * kMaxWaves + wave] for jobs
 // with kJobReadout (the caller synchronises before reading them).  With WRITE the
 // recomputed rows are stored into the jobs' planes.
-template <class P, int F, int MAXT, bool WRITE>
+template <class P, int F, int MAXT, bool WRITE, int NCOPY = kIncCopy, int GU = 4>
 __device__ void inc_group(const Net& net, const IncNet& inc, const IncGeo& ig, const IncLds<P>& x, IncJobs& jobs,
                           int nsw, typename P::Acc* planes, unsigned char* smem) {
   using Acc = typename P::Acc;
@@ -150,16 +153,48 @@ __device__ void inc_group(const Net& net, const IncNet& inc, const IncGeo& ig, c
   const Acc* bias = x.sbias + q * NS;
 
   // tables of the group -> LDS (16-byte vectors)
-  for (int k = threadIdx.x; k < nsw * (Lr + 2); k += bd) {
-    const int w = k / (Lr + 2), l = k % (Lr + 2);
-    jobs.cnt[w][l] = inc.ball_cnt[jobs.e[w] * (Lr + 2) + l];
-  }
   {
     const int tv = ig.tabw / 8;
     for (int k = threadIdx.x; k < nsw * tv; k += bd) {
       const int w = k / tv, v = k % tv;
       const int2 mt = jobs.meta[w];
       if (v < mt.y) reinterpret_cast<int4*>(x.tab + w * ig.tabw)[v] = reinterpret_cast<const int4*>(inc.ball_tab + mt.x)[v];
+    }
+  }
+  // copy list: the rows of ring l+1 (list positions [|C_l|, |C_{l+1}|)) of every job, for
+  // layers l = 1..L in turn, with their source offset (node row of the job's planes) and
+  // LDS destination; entry of (job w, position rr) at layer l:
+  //   sum_w' (|C_l|_w' - |C_1|_w') + sum_{w' < w} (|C_{l+1}|_w' - |C_l|_w') + rr - |C_l|_w
+  {
+    int tot = 0;
+    for (int w = 0; w < nsw; ++w) tot += jobs.cnt[w][Lr + 1] - jobs.cnt[w][1];
+    for (int k = threadIdx.x; k < tot; k += bd) {
+      int w = 0, start = 0;
+      while (k - start >= jobs.cnt[w][Lr + 1] - jobs.cnt[w][1]) {
+        start += jobs.cnt[w][Lr + 1] - jobs.cnt[w][1];
+        ++w;
+      }
+      const int rr = jobs.cnt[w][1] + (k - start);
+      int l = 1;
+      while (rr >= jobs.cnt[w][l + 1]) ++l;
+      int idx = rr - jobs.cnt[w][l];
+      for (int u = 0; u < nsw; ++u) {
+        idx += jobs.cnt[u][l] - jobs.cnt[u][1];
+        if (u < w) idx += jobs.cnt[u][l + 1] - jobs.cnt[u][l];
+      }
+      const int nd = inc.ball_tab[jobs.meta[w].x + rr];
+      const long long so = jobs.pboff[w] + (long long)nd * F;
+      x.cpy[idx] = make_int4((int)(unsigned)so, (int)(so >> 32),
+                             ig.off_buf + (w * ig.rows + rr) * ig.row_elems * (int)sizeof(Acc), 0);
+    }
+    if ((int)threadIdx.x <= Lr) {
+      const int l = threadIdx.x;
+      int base = 0, rows = 0;
+      for (int u = 0; u < nsw; ++u) {
+        base += jobs.cnt[u][max(l, 1)] - jobs.cnt[u][1];
+        rows += l >= 1 ? jobs.cnt[u][l + 1] - jobs.cnt[u][l] : 0;
+      }
+      jobs.lay[l] = make_int2(base, rows);
     }
   }
   __syncthreads();
@@ -175,64 +210,59 @@ __device__ void inc_group(const Net& net, const IncNet& inc, const IncGeo& ig, c
     // ---- base G^{l-1} rows of the nodes at distance l+1 -> buffer (requested first,
     // stored after this wave's products)
     using V4 = unsigned int __attribute__((ext_vector_type(4)));
-    V4 cvv[kIncCopy];
-    int cdst[kIncCopy];
+    V4 cvv[NCOPY];
+    int cdst[NCOPY];
     {
-      int cst[SM + 1];
-      cst[0] = 0;
-#pragma unroll
-      for (int w = 0; w < SM; ++w) cst[w + 1] = cst[w] + (w < nsw ? (jobs.cnt[w][l + 1] - jobs.cnt[w][l]) * VPR : 0);
-      const int ctot = cst[SM];
+      const int2 lay = jobs.lay[l];
+      const int ctot = lay.y * VPR;
+      const Acc* Gl = planes + (size_t)(Lr + l - 1) * plane;
       // copy item idx -> (source vector, byte offset of the destination in LDS)
       auto locate = [&](int idx, const V4*& src) {
-        int w = 0, start = 0;
-#pragma unroll
-        for (int u = 1; u < SM; ++u)
-          if (idx >= cst[u]) { w = u; start = cst[u]; }
-        const int rel = idx - start;
-        const int rr = jobs.cnt[w][l] + rel / VPR, v = rel % VPR;
-        const int nd = x.tab[w * ig.tabw + rr];
-        const Acc* Gb = planes + jobs.pboff[w] + (size_t)(Lr + l - 1) * plane;
-        src = reinterpret_cast<const V4*>(Gb + (size_t)nd * F) + v;
-        return ig.off_buf + ((w * ig.rows + rr) * ig.row_elems) * (int)sizeof(Acc) + 16 * v;
+        const int4 c = x.cpy[lay.x + idx / VPR];
+        const int v = idx % VPR;
+        const long long so = (long long)(((unsigned long long)(unsigned)c.y << 32) | (unsigned)c.x);
+        src = reinterpret_cast<const V4*>(Gl + so) + v;
+        return c.z + 16 * v;
       };
       const V4* ph = reinterpret_cast<const V4*>(planes + jobs.pboff[0]);   // in-bounds placeholder
 #pragma unroll
-      for (int u = 0; u < kIncCopy; ++u) {
+      for (int u = 0; u < NCOPY; ++u) {   // no branches: the lookups overlap
         const int idx = threadIdx.x + u * bd;
         const V4* src = ph;
-        cdst[u] = -1;
-        if (idx < ctot) cdst[u] = locate(idx, src);
+        const int o = locate(min(idx, max(ctot - 1, 0)), src);
+        cdst[u] = idx < ctot ? o : -1;
+        if (ctot == 0) src = ph;
         cvv[u] = *src;   // unconditional, so the value stays in registers
       }
-      for (int idx = threadIdx.x + kIncCopy * bd; idx < ctot; idx += bd) {   // rare: large rings
+      for (int idx = threadIdx.x + NCOPY * bd; idx < ctot; idx += bd) {   // rare: large rings
         const V4* src;
         const int o = locate(idx, src);
         *reinterpret_cast<V4*>(smem + o) = *src;
       }
     }
-    // ---- this wave's tiles
-    int trow[MAXT], tsw[MAXT];
+    // ---- this wave's tiles: job, row, |C_l|, |C_{l-1}| and node of each (looked up once)
+    int trow[MAXT], tsw[MAXT], tcl[MAXT], tcp[MAXT], tnd[MAXT];
     bool tok[MAXT];
 #pragma unroll
     for (int k = 0; k < MAXT; ++k) {
       const int g = wv + k * nw;
       const int w = g % nsw, tt = g / nsw;
       tsw[k] = w;
-      tok[k] = tt * 16 < jobs.cnt[w][l];
+      tcl[k] = jobs.cnt[w][l];
+      tcp[k] = jobs.cnt[w][l - 1];
+      tok[k] = tt * 16 < tcl[k];
       trow[k] = tt * 16 + col;
+      tnd[k] = trow[k] < tcl[k] ? (int)x.tab[w * ig.tabw + trow[k]] : -1;
     }
     // ---- products: self -> registers, message -> buffer rows [0, |C_l|) in place
     // layer input of tile k: embedding (l = 1), H'^{l-1} from the buffer, or base H^{l-1}
     auto load_in = [&](int k, Acc (&h)[NS]) {
-      const int w = tsw[k], r = trow[k];
-      const int cl = jobs.cnt[w][l], cp = jobs.cnt[w][l - 1];
-      const int nd = r < cl ? x.tab[w * ig.tabw + r] : -1;
+      const int w = tsw[k], r = trow[k], nd = tnd[k];
       if (l == 1) {
         const int xs = nd >= 0 ? xspin(w, nd) : 0;
 #pragma unroll
         for (int i = 0; i < NS; ++i) h[i] = nd >= 0 ? x.semb[xs * F + P::lc(q, i)] : (Acc)0;
-      } else if (r < cp) {
+      } else if (r < tcp[k]) {
         lds_read<Acc, NS>(x.buf + ((size_t)w * ig.rows + r) * ig.row_elems + q * NS, h);
       } else if (nd >= 0) {
         gmem_read<Acc, NS>(planes + jobs.pboff[w] + (size_t)(l - 2) * plane + (size_t)nd * F + q * NS, h);
@@ -246,8 +276,8 @@ __device__ void inc_group(const Net& net, const IncNet& inc, const IncGeo& ig, c
     for (int k = 0; k < MAXT; ++k) {
       if (!tok[k]) continue;
       const int w = tsw[k], r = trow[k];
-      const int cl = jobs.cnt[w][l], cp = jobs.cnt[w][l - 1];
-      const int nd = r < cl ? x.tab[w * ig.tabw + r] : -1;
+      const int cl = tcl[k], cp = tcp[k];
+      const int nd = tnd[k];
       Acc* pw = planes + jobs.pboff[w];
       Acc h[NS];
       load_in(k, h);
@@ -269,10 +299,11 @@ __device__ void inc_group(const Net& net, const IncNet& inc, const IncGeo& ig, c
         if (r < cl) lds_write<Acc, 4>(row + 4 * t, gm);
         if (WRITE && r < cp)   // G^{l-1} changed on C_{l-1}
           lds_write<Acc, 4>(pw + (size_t)(Lr + l - 1) * plane + (size_t)nd * F + q * NS + 4 * t, gm);
+        if (GU < 4) __builtin_amdgcn_sched_barrier(0);   // low-register shape: one output tile at a time
       }
     }
 #pragma unroll
-    for (int u = 0; u < kIncCopy; ++u)
+    for (int u = 0; u < NCOPY; ++u)
       if (cdst[u] >= 0) *reinterpret_cast<V4*>(smem + cdst[u]) = cvv[u];
     __syncthreads();   // every G^{l-1} row of every job is in its buffer
     // ---- gather, activation; readout difference at the last layer
@@ -283,9 +314,8 @@ __device__ void inc_group(const Net& net, const IncNet& inc, const IncGeo& ig, c
     for (int k = 0; k < MAXT; ++k) {
       if (!tok[k]) continue;
       const int w = tsw[k], r = trow[k];
-      const int cl = jobs.cnt[w][l];
       const uint16_t* tw = x.tab + w * ig.tabw;
-      const int nd = r < cl ? tw[r] : -1;
+      const int nd = tnd[k];
       const Acc* bw = x.buf + (size_t)w * ig.rows * ig.row_elems;
       Acc* pw = planes + jobs.pboff[w];
       const bool last = l == Lr;
@@ -307,11 +337,15 @@ __device__ void inc_group(const Net& net, const IncNet& inc, const IncGeo& ig, c
           const Acc* wp = x.sev + nd * dm + d;
           const Acc wt[4] = {wp[0], wp[1], wp[2], wp[3]};
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            Acc rowv[NS];
-            lds_read<Acc, NS>(bw + pc[u] * ig.row_elems + q * NS, rowv);
+          for (int u = 0; u < 4; u += GU) {
 #pragma unroll
-            for (int i = 0; i < NS; ++i) m[i] += wt[u] * rowv[i];
+           for (int uu = u; uu < u + GU; ++uu) {
+            Acc rowv[NS];
+            lds_read<Acc, NS>(bw + pc[uu] * ig.row_elems + q * NS, rowv);
+#pragma unroll
+            for (int i = 0; i < NS; ++i) m[i] += wt[uu] * rowv[i];
+           }
+           if (GU < 4) __builtin_amdgcn_sched_barrier(0);   // keep GU rows in flight at most
           }
         }
       }
@@ -333,8 +367,8 @@ __device__ void inc_group(const Net& net, const IncNet& inc, const IncGeo& ig, c
         if (rd) {
           double pa = nd >= 0 ? (double)ta1 - (double)r0[0] : 0.0;
           double pp = nd >= 0 ? (double)tp1 - (double)r0[1] : 0.0;
-          pa = wave_sum(pa);
-          pp = wave_sum(pp);
+          pa = wave_sum_dpp(pa);
+          pp = wave_sum_dpp(pp);
           if (lane == 0) {
             x.red[(2 * w) * kMaxWaves + wv] += pa;
             x.red[(2 * w + 1) * kMaxWaves + wv] += pp;
@@ -354,7 +388,7 @@ __device__ void inc_group(const Net& net, const IncNet& inc, const IncGeo& ig, c
       for (int k = 0; k < MAXT; ++k) {
         if (!tok[k]) continue;
         const int w = tsw[k], r = trow[k];
-        if (r < jobs.cnt[w][l]) lds_write<Acc, NS>(x.buf + ((size_t)w * ig.rows + r) * ig.row_elems + q * NS, hn[k]);
+        if (r < tcl[k]) lds_write<Acc, NS>(x.buf + ((size_t)w * ig.rows + r) * ig.row_elems + q * NS, hn[k]);
       }
     }
   }
@@ -368,8 +402,8 @@ __device__ __forceinline__ void inc_neumaier(double& s, double& c, double x) {
 }
 
 // Local energy: the exchanges of the anti-aligned bonds of every sample.
-template <class P, int F, int MAXT>
-__global__ __launch_bounds__(512) void k_eloc_inc(Net net, IncNet inc, IncGeo ig, const int8_t* __restrict__ spins,
+template <class P, int F, int MAXT, int NT>
+__global__ __launch_bounds__(NT) void k_eloc_inc(Net net, IncNet inc, IncGeo ig, const int8_t* __restrict__ spins,
                                                   int B, const typename P::Acc* __restrict__ planes, int n_chunks,
                                                   int chunk, double* __restrict__ partial, int* __restrict__ cnt) {
   using Acc = typename P::Acc;
@@ -429,12 +463,13 @@ __global__ __launch_bounds__(512) void k_eloc_inc(Net net, IncNet inc, IncGeo ig
         jobs.e[w] = eg;
         jobs.ij[w] = net.edges[eg];
         jobs.meta[w] = inc.ball_meta[eg];
+        for (int l = 0; l < Lr + 2; ++l) jobs.cnt[w][l] = inc.ball_cnt[eg * (Lr + 2) + l];
         jobs.flags[w] = kJobSwap | kJobReadout;
         jobs.spoff[w] = 0;
         jobs.pboff[w] = (long long)b * 2 * Lr * plane;
       }
       __syncthreads();
-      inc_group<P, F, MAXT, false>(net, inc, ig, x, jobs, nsw, pl, smem);
+      inc_group<P, F, MAXT, false, NT == 1024 ? 1 : kIncCopy, NT == 1024 ? 1 : 4>(net, inc, ig, x, jobs, nsw, pl, smem);
       __syncthreads();   // readout partials of every wave
       if ((int)threadIdx.x < nsw) {
         const int w = threadIdx.x;
@@ -474,10 +509,11 @@ __global__ __launch_bounds__(512) void k_eloc_inc(Net net, IncNet inc, IncGeo ig
 // key = seed), and a proposal is accepted when u < exp(2 Re Delta).  The chains'
 // planes must hold their current configurations (base pass) and are kept current.
 // log psi is not tracked here: the caller evaluates the final configurations.
-template <class P, int F, int MAXT>
-__global__ __launch_bounds__(512) void k_sweep_inc(Net net, IncNet inc, IncGeo ig, int8_t* __restrict__ spins,
+template <class P, int F, int MAXT, int NT>
+__global__ __launch_bounds__(NT) void k_sweep_inc(Net net, IncNet inc, IncGeo ig, int8_t* __restrict__ spins,
                                                    typename P::Acc* planes, int B, int n_sweeps,
                                                    unsigned long long seed, unsigned long long counter_base,
+                                                   const unsigned long long* __restrict__ counter_dev,
                                                    int* __restrict__ n_accept) {
   constexpr int SM = kIncMaxSwaps;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -491,6 +527,7 @@ __global__ __launch_bounds__(512) void k_sweep_inc(Net net, IncNet inc, IncGeo i
   const size_t per_chain = (size_t)2 * net.L * net.g.npad * F;
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   const long long total = (long long)n_sweeps * net.n;
+  if (counter_dev) counter_base += *counter_dev;   // graph replays read the current base
   inc_stage<P, F>(net, inc, x);
   if ((int)threadIdx.x < S) {
     const int w = threadIdx.x;
@@ -578,12 +615,13 @@ __global__ __launch_bounds__(512) void k_sweep_inc(Net net, IncNet inc, IncGeo i
       jobs.e[j] = e;
       jobs.ij[j] = net.edges[e];
       jobs.meta[j] = inc.ball_meta[e];
+      for (int l = 0; l < net.L + 2; ++l) jobs.cnt[j][l] = inc.ball_cnt[e * (net.L + 2) + l];
       jobs.flags[j] = s_job[w] == 1 ? (kJobSwap | kJobReadout) : 0;
       jobs.spoff[j] = w * ig.spw;
       jobs.pboff[j] = (long long)s_chain[w] * (long long)per_chain;
     }
     __syncthreads();
-    inc_group<P, F, MAXT, true>(net, inc, ig, x, jobs, nsw, planes, smem);
+    inc_group<P, F, MAXT, true, NT == 1024 ? 1 : kIncCopy, NT == 1024 ? 1 : 4>(net, inc, ig, x, jobs, nsw, planes, smem);
     __syncthreads();   // readout partials of every wave
     if ((int)threadIdx.x < nsw) {
       const int j = threadIdx.x, w = s_jslot[j];

@@ -237,6 +237,30 @@ struct Net {
   Geo g;
 };
 
+// FP64 wavefront sum through DPP lane moves (no LDS traffic), fixed order; the
+// total is returned to every lane.  Steps: pairs and quads (quad_perm), halves
+// of a row (row_half_mirror), rows of 16 (row_mirror), then row 0 -> 1 and
+// row 2 -> 3 (row_bcast:15) and rows 0-1 -> 2-3 (row_bcast:31); lane 63 holds
+// the sum.
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const unsigned long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROWS, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_f64<0xb1>(v);          // quad_perm(1,0,3,2)
+  v += dpp_f64<0x4e>(v);          // quad_perm(2,3,0,1)
+  v += dpp_f64<0x141>(v);         // row_half_mirror
+  v += dpp_f64<0x140>(v);         // row_mirror
+  v += dpp_f64<0x142, 0xa>(v);    // row_bcast:15 into rows 1 and 3
+  v += dpp_f64<0x143, 0xc>(v);    // row_bcast:31 into rows 2 and 3
+  const unsigned long long b = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)b, 63), hi = __builtin_amdgcn_readlane((unsigned)(b >> 32), 63);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // fixed-order FP64 wavefront sum (same order for every configuration)
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

@@ -88,6 +88,13 @@ def test_incremental_needs_tied_weights(lib):
     assert b"tied" in lib.gna_last_error(None)
 
 
+def test_incremental_needs_layers(lib):
+    c, keep = _cfg(n_layers=0, eloc_mode=1)
+    out = ctypes.c_void_p()
+    assert lib.gna_init(ctypes.byref(c), ctypes.byref(out)) == 3
+    assert b"n_layers" in lib.gna_last_error(None)
+
+
 def test_null_arguments(lib):
     out = ctypes.c_void_p()
     assert lib.gna_init(None, ctypes.byref(out)) == 1

@@ -1,0 +1,114 @@
+"""The device-resident step (gna_step): equal to its parts called one by one, and
+replayable from a HIP graph (captured through torch.cuda.graph on the library's
+stream) with results identical to eager execution on every replay."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda", 0)
+
+
+def _ctx(n, e, F, L, prec, B, mode):
+    from paper_2011_12453_amd import GNA
+    print(f"[gpu] step ctx N={n} F={F} L={L} {prec} {mode} B={B}", file=sys.stderr, flush=True)
+    return GNA(n, e, F, L, tied=True, precision=prec, max_batch=B, device=DEV, eloc_mode=mode)
+
+
+def _state(n, F, L, B, seed):
+    theta = torch.from_numpy(w.glorot_theta(F, L, True, seed=seed, weight_scale=1.5, bias_std=0.3)).to(DEV)
+    spins = torch.from_numpy(w.random_sz0_spins(B, n, seed + 100)).to(DEV)
+    return theta, spins
+
+
+@pytest.mark.parametrize("mode", ["full", "incremental"])
+def test_step_equals_its_parts(mode):
+    n, e = w.kagome(6, 6)
+    F, L, B, seed, lr = 32, 4, 32, 7, 1e-3
+    g = _ctx(n, e, F, L, "fp64", B, mode)
+    th1, sp1 = _state(n, F, L, B, 3)
+    th2, sp2 = th1.clone(), sp1.clone()
+    lp1 = torch.empty(B, 2, dtype=torch.float64, device=DEV)
+    counter = torch.zeros(1, dtype=torch.int64, device=DEV)
+    for k in range(2):
+        grad1, stats1, el1, acc1 = g.step(th1, sp1, lp1, 1, seed, counter, lr)
+        lp2 = g.logpsi(th2, sp2)
+        acc2 = g.metropolis_sweep(th2, sp2, lp2, n_sweeps=1, seed=seed, counter_base=k * n)
+        grad2, stats2, el2 = g.isgo_grad(th2, sp2, lp2)
+        g.sgd_update(th2, grad2, lr)
+        torch.cuda.synchronize()
+        assert torch.equal(sp1, sp2) and torch.equal(acc1, acc2) and torch.equal(lp1, lp2)
+        assert torch.equal(grad1, grad2) and torch.equal(stats1, stats2) and torch.equal(th1, th2)
+    assert int(counter.item()) == 2 * n
+    # the sampled configurations are the oracle's trajectory (FP64 decisions)
+    g.close()
+
+
+@pytest.mark.parametrize("mode,prec", [("incremental", "bf16"), ("full", "fp32"), ("incremental", "fp64")])
+def test_step_graph_replay_matches_eager(mode, prec):
+    n, e = w.kagome(6, 6)
+    F, L, B, seed, lr = 32, 4, 48, 11, 2e-3
+    g = _ctx(n, e, F, L, prec, B, mode)
+    P = g.num_params
+    th0, sp0 = _state(n, F, L, B, 5)
+    # eager reference: three steps
+    th_e, sp_e = th0.clone(), sp0.clone()
+    lp_e = torch.empty(B, 2, dtype=torch.float64, device=DEV)
+    cnt_e = torch.zeros(1, dtype=torch.int64, device=DEV)
+    ref = []
+    for k in range(3):
+        grad, stats, el, acc = g.step(th_e, sp_e, lp_e, 1, seed, cnt_e, lr)
+        torch.cuda.synchronize()
+        ref.append(tuple(t.clone() for t in (th_e, sp_e, lp_e, grad, stats, el, acc)))
+    # graph: static buffers, one captured step, replayed three times
+    th_g, sp_g = th0.clone(), sp0.clone()
+    lp_g = torch.empty(B, 2, dtype=torch.float64, device=DEV)
+    cnt_g = torch.zeros(1, dtype=torch.int64, device=DEV)
+    grad_g = torch.empty(P, dtype=torch.float64, device=DEV)
+    stats_g = torch.empty(8, dtype=torch.float64, device=DEV)
+    el_g = torch.empty(B, 2, dtype=torch.float64, device=DEV)
+    acc_g = torch.empty(B, dtype=torch.int32, device=DEV)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        g.set_stream(torch.cuda.current_stream())
+        g.step(th_g, sp_g, lp_g, 1, seed, cnt_g, lr, grad=grad_g, stats=stats_g, eloc=el_g, n_accept=acc_g)
+    g.set_stream(torch.cuda.current_stream())
+    other = torch.from_numpy(w.random_sz0_spins(B, n, 999)).to(DEV)
+    for k in range(3):
+        graph.replay()
+        torch.cuda.synchronize()
+        got = (th_g, sp_g, lp_g, grad_g, stats_g, el_g, acc_g)
+        for a, b in zip(got, ref[k]):
+            assert torch.equal(a, b), f"replay {k} differs from eager step {k}"
+        # the program's own eager work between replays
+        g.logpsi(th_g.clone(), other)
+        torch.cuda.synchronize()
+    assert int(cnt_g.item()) == 3 * n
+    print(f"[gpu] graph replay {mode} {prec}: 3 replays identical to eager; E/site "
+          f"{stats_g[0].item() / n:.6f}", file=sys.stderr, flush=True)
+    g.close()
+
+
+def test_step_sampler_matches_oracle_trajectory():
+    # gna_step's sweep with the device counter is the oracle's Metropolis chain
+    n, e = w.kagome(2, 2)
+    F, L, B, seed = 16, 2, 16, 21
+    g = _ctx(n, e, F, L, "fp64", B, "incremental")
+    theta = w.glorot_theta(F, L, True, seed=3, weight_scale=2.0, bias_std=0.3)
+    s0 = w.random_sz0_spins(B, n, 4)
+    th, sp = torch.from_numpy(theta).to(DEV), torch.from_numpy(s0).to(DEV)
+    lp = torch.empty(B, 2, dtype=torch.float64, device=DEV)
+    counter = torch.tensor([5 * n], dtype=torch.int64, device=DEV)
+    g.step(th, sp, lp, 2, seed, counter, 0.0)
+    fn = lambda c: oracle.logpsi(theta, c, n, e, F, L)
+    rs, rlp, racc = oracle.metropolis_sweeps(fn, s0, fn(s0), e, 2, seed=seed, counter_base=5 * n)
+    assert np.array_equal(sp.cpu().numpy(), rs)
+    assert np.max(np.abs(lp.cpu().numpy() - rlp)) < 1e-11
+    g.close()
