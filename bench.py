@@ -107,6 +107,7 @@ def main():
     ap.add_argument("--cpu-samples", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline steps only (for profilers)")
+    ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay timing")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -156,12 +157,16 @@ def main():
     lp = torch.empty((B, 2), dtype=torch.float64, device=dev)
     alpha = 1e-3
     seed = 20201124
+    counter = torch.zeros(1, dtype=torch.int64, device=dev)   # sampler's Philox counter base
+    grad_buf = torch.empty(g.num_params, dtype=torch.float64, device=dev)
+    el_buf = torch.empty((B, 2), dtype=torch.float64, device=dev)
+    acc_buf = torch.empty(B, dtype=torch.int32, device=dev)
 
-    def step(k):
-        g.logpsi(theta, spins, out=lp)
-        g.metropolis_sweep(theta, spins, lp, n_sweeps=1, seed=seed, counter_base=k * n)
-        grad, stats, _ = g.isgo_grad(theta, spins, lp)
-        g.sgd_update(theta, grad, alpha)
+    def step(k, stats=None):
+        # gna_step: log psi, one sweep (counter advanced on the device), ISGO gradient, SGD
+        stats = torch.empty(8, dtype=torch.float64, device=dev) if stats is None else stats
+        g.step(theta, spins, lp, 1, seed, counter, alpha, grad=grad_buf, stats=stats, eloc=el_buf,
+               n_accept=acc_buf)
         return stats
 
     log(f"[bench] {p.name}: N={n} |E|={len(e)} F={F} L={L} B={B} {args.precision}; warmup {args.warmup}")
@@ -202,6 +207,29 @@ def main():
                 "traffic": stored_traffic(p.name, args.precision, kname),
                 "launch_ms": eloc_ms,
                 "flops_per_eval": (kflops / args.steps) / max(1.0, evals / args.steps - B)}
+
+    # ---------------- the same step replayed from a captured HIP graph ----------------
+    graph_info = None
+    if not args.no_graph and not args.quick:
+        stats_g = torch.empty(8, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            g.set_stream(torch.cuda.current_stream())
+            step(0, stats=stats_g)
+        g.set_stream(torch.cuda.current_stream())
+        graph.replay()                   # warm
+        torch.cuda.synchronize()
+        tg0 = time.perf_counter()
+        for _ in range(args.steps):
+            graph.replay()
+        torch.cuda.synchronize()
+        tg1 = time.perf_counter()
+        gms = 1e3 * (tg1 - tg0) / args.steps
+        graph_info = {"ms_per_step": gms, "evals_per_s": (evals / args.steps) / (gms * 1e-3),
+                      "note": "whole step captured once and replayed; evals per step from the timed eager steps"}
+        log(f"[bench] graph replay: {gms:.2f} ms/step, {graph_info['evals_per_s']:.4g} evals/s")
+        del graph
 
     # ---------------- E_loc alone: both modes, every precision ----------------
     per_prec = {}
@@ -274,11 +302,12 @@ def main():
         "dtype": args.precision, "data": "synthetic",
         "config": {"workload": p.name, "lattice": "12x12x3 kagome torus", "sites": n, "bonds": len(e),
                    "layers": L, "features": F, "tied": True, "batch": B,
-                   "step": "logpsi + 1 Metropolis sweep + ISGO update (logpsi, E_loc, stats, VJP) + SGD",
+                   "step": "gna_step: logpsi + 1 Metropolis sweep + ISGO update (logpsi, E_loc, stats, VJP) + SGD",
                    "eloc_mode": args.eloc_mode,
                    "evals_per_step": evals / args.steps},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "graph": graph_info,
         "precisions": per_prec,
         "kernels_ms_per_step": {k: v[1] / args.steps for k, v in sorted(prof.items())},
     }
