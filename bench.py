@@ -108,6 +108,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline steps only (for profilers)")
     ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay timing")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default incremental shape")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -169,6 +170,12 @@ def main():
                n_accept=acc_buf)
         return stats
 
+    tuned = None
+    if args.eloc_mode == "incremental" and not args.no_tune:
+        # the tuner times the incremental kernels' shapes on this batch (before any timing)
+        tuned = g.autotune(theta, spins)
+        log(f"[bench] autotune: {tuned}")
+    shape = g.config_info()
     log(f"[bench] {p.name}: N={n} |E|={len(e)} F={F} L={L} B={B} {args.precision}; warmup {args.warmup}")
     for k in range(args.warmup):
         step(k)
@@ -304,6 +311,7 @@ def main():
                    "layers": L, "features": F, "tied": True, "batch": B,
                    "step": "gna_step: logpsi + 1 Metropolis sweep + ISGO update (logpsi, E_loc, stats, VJP) + SGD",
                    "eloc_mode": args.eloc_mode,
+                   "shape": shape,
                    "evals_per_step": evals / args.steps},
         "roofline": roofline,
         "cpu_baseline": cpu,

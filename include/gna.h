@@ -168,6 +168,23 @@ gna_status gna_step(gna_ctx *ctx, double *theta, int8_t *spins, double *logpsi, 
                     int32_t n_sweeps, uint64_t seed, uint64_t *counter, double lr, double *grad,
                     double *stats, double *eloc, int32_t *n_accept);
 
+/* Tile and workgroup shapes of the incremental kernels chosen by measurement:
+ * times gna_local_energy on (theta, spins[B]) for the candidate shapes (jobs in
+ * flight per workgroup, 8 or 16 waves, one or two samples in flight per XCD),
+ * keeps the fastest for this context and for every later context of the same
+ * signature (N, n_edges, degree histogram, F, L, precision) in this process.
+ * Unlike the compute calls it synchronises the context's stream; call it after
+ * gna_init, outside any graph capture.  chosen [4] (host, may be NULL): jobs in
+ * flight, waves, samples per XCD, microseconds per local-energy call.  In
+ * GNA_ELOC_FULL mode there is nothing to tune: returns GNA_OK, chosen zeros.   */
+gna_status gna_autotune(gna_ctx *ctx, const double *theta, const int8_t *spins, int32_t B,
+                        int32_t *chosen);
+
+/* Shape in use (host array, n entries at most 8): eloc_mode, jobs in flight,
+ * waves per workgroup, tiles per wave, samples per XCD, precision, F, L.
+ * Returns 8, or -1 for a NULL context.                                       */
+int32_t gna_config_info(const gna_ctx *ctx, int32_t *info, int32_t n);
+
 /* Reverse pass: grad[P] = sum_x cot[x][0] d log|psi(s_x)|/dtheta
  *                         + cot[x][1] d phase(s_x)/dtheta   (overwritten).
  * Computed in FP64 for every precision mode; per-layer activations are

@@ -63,6 +63,9 @@ _EXPORTS = {
                                   ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_void_p,
                                   ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.c_void_p]),
+    "gna_autotune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                      ctypes.POINTER(ctypes.c_int32)]),
+    "gna_config_info": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]),
     "gna_profile_enable": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "gna_profile_read": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_char_p,
                                           ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
@@ -238,6 +241,23 @@ class GNA:
                                        ctypes.c_uint64(seed), _ptr(counter), float(lr), _ptr(grad),
                                        _ptr(stats), _ptr(eloc), _ptr(acc)))
         return grad, stats, eloc, acc
+
+    def autotune(self, theta, spins) -> dict:
+        """Measure the incremental kernels' shapes on this batch and keep the fastest
+        (``gna_autotune``; synchronises).  Returns the choice."""
+        theta, spins = self._theta(theta), self._spins(spins)
+        out = (ctypes.c_int32 * 4)()
+        self._check(self._lib.gna_autotune(self._ctx, _ptr(theta), _ptr(spins), spins.shape[0], out))
+        return {"jobs_in_flight": out[0], "waves": out[1], "samples_per_xcd": out[2], "us_per_call": out[3]}
+
+    def config_info(self) -> dict:
+        """Shape in use (``gna_config_info``)."""
+        v = (ctypes.c_int32 * 8)()
+        if self._lib.gna_config_info(self._ctx, v, 8) != 8:
+            raise GnaError(1, "gna_config_info failed")
+        keys = ("eloc_mode", "jobs_in_flight", "waves", "tiles_per_wave", "samples_per_xcd", "precision",
+                "features", "layers")
+        return dict(zip(keys, list(v)))
 
     def set_stream(self, stream):
         """Enqueue later calls on ``stream`` (a torch.cuda.Stream), e.g. a graph-capture stream."""

@@ -536,6 +536,11 @@ struct gna_ctx {
   IncKern ik{};
   int grid_inc_base = 1, grid_inc = 1, grid_sweep_inc = 1, inc_r8 = 8, inc_chunk_cap = 64;
   bool inc_wide = false;   // 16-wave incremental kernels
+  int inc_per_xcd = 2;     // samples in flight per XCD (local energy work items)
+  int inc_maxt = 1;        // tiles per wave
+  int inc_max_rows = 2, inc_max_ball = 2, inc_max_tiles = 1;
+  size_t inc_w_bytes = 0, lds_max = 0;
+  std::string tune_key;    // shape signature for the tuner's cache
   int2* d_ball_meta = nullptr;
   int* d_ball_cnt = nullptr;
   uint16_t* d_ball_tab = nullptr;
@@ -695,10 +700,10 @@ gna_status run_eloc(gna_ctx* c, const double* theta, const int8_t* spins, int B,
   long long chunk = work / (16LL * c->grid_eloc);
   chunk = std::max<long long>(16, std::min<long long>(chunk, std::max(1, c->E)));
   if (c->eloc_mode == GNA_ELOC_INCREMENTAL) {
-    // two samples per XCD at a time: half as many chunks per sample as blocks per XCD;
+    // inc_per_xcd samples per XCD at a time: per_x / inc_per_xcd chunks per sample;
     // a chunk holds at most one bond per thread of the workgroup
     const int per_x = std::max(1, c->grid_inc / 8);
-    const int per_sample = std::max(1, per_x / 2);
+    const int per_sample = std::max(1, per_x / c->inc_per_xcd);
     chunk = std::max<long long>(8, (std::max(1, c->E) + per_sample - 1) / per_sample);
     chunk = std::min<long long>(chunk, c->inc_chunk_cap);
   }
@@ -817,6 +822,116 @@ gna_status run_vjp(gna_ctx* c, const double* theta, const int8_t* spins, int B, 
 }
 
 bool valid_ptr(const void* p) { return p != nullptr; }
+
+// ---------------------------------------------------------------------------
+// Shape of the incremental kernels: jobs in flight per workgroup (S), wave shape
+// (8 waves of up to 4 tiles, or 16 waves of one tile) and samples in flight per
+// XCD.  inc_configure derives the LDS layout, picks the instantiation and sizes
+// the persistent grids; S < 0 asks for the largest S <= -S that fits.
+// ---------------------------------------------------------------------------
+struct IncShape {
+  int S;
+  bool wide;
+  int per_xcd;
+};
+
+std::mutex g_tune_mu;
+std::vector<std::pair<std::string, IncShape>> g_tune;   // tuner cache (this process)
+
+bool tune_lookup(const std::string& key, IncShape* out) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (auto& kv : g_tune)
+    if (kv.first == key) {
+      *out = kv.second;
+      return true;
+    }
+  return false;
+}
+
+void tune_store(const std::string& key, const IncShape& v) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (auto& kv : g_tune)
+    if (kv.first == key) {
+      kv.second = v;
+      return;
+    }
+  g_tune.push_back({key, v});
+}
+
+gna_status inc_configure(gna_ctx* c, IncShape shp) {
+  const int F = c->F, N = c->N, dmax = c->dmax;
+  const int max_rows = c->inc_max_rows, max_ball = c->inc_max_ball, max_tiles = c->inc_max_tiles;
+  IncGeo base{};
+  base.xcd = 8;   // MI355X: 8 XCDs, workgroups assigned round-robin
+  base.rows = max_rows;
+  base.tabw = (c->inc_r8 + max_ball * dmax + 7) / 8 * 8;
+  base.row_elems = (int)((4 * (F / 4) * c->sz_Acc + kRowPadBytes) / c->sz_Acc);
+  const int chunk_cap = 64 * kMaxWaves / 2;   // bonds per work item: at most one per thread
+  auto geometry = [&](int S, bool wide, IncGeo* out, int* maxt) {
+    const int tiles = S * max_tiles;
+    const int nw = std::min(wide ? kMaxWaves : kMaxWaves / 2, tiles);
+    const int mt = (tiles + nw - 1) / nw;   // tiles per wave
+    if (mt > (wide ? 1 : 4)) return false;
+    size_t o = 0;
+    auto al = [](size_t x) { return (x + 15) & ~(size_t)15; };
+    IncGeo t = base;
+    t.S = S;
+    t.nw = nw;
+    t.off_w = (int)o; o = al(o + c->inc_w_bytes);
+    t.off_buf = (int)o; o = al(o + (size_t)S * max_rows * base.row_elems * c->sz_Acc);
+    t.off_tab = (int)o; o = al(o + (size_t)S * base.tabw * 2);
+    t.spw = (int)al(c->geo.npad);
+    t.off_sp = (int)o; o = al(o + (size_t)S * t.spw);
+    t.off_red = (int)o; o = al(o + (size_t)kIncMaxSwaps * 2 * kMaxWaves * 8);
+    t.off_bias = (int)o; o = al(o + (size_t)F * c->sz_Acc);
+    t.off_emb = (int)o; o = al(o + (size_t)2 * F * c->sz_Acc);
+    t.off_head = (int)o; o = al(o + (size_t)2 * (F + 3) * 8);
+    t.off_ev = (int)o; o = al(o + (size_t)N * dmax * c->sz_Acc);
+    t.off_list = (int)o; o = al(o + (size_t)chunk_cap * 4);
+    t.off_cpy = (int)o; o = al(o + (size_t)S * max_rows * 16);
+    t.lds_bytes = (int)o;
+    if (o + 2048 > c->lds_max) return false;   // static LDS of the kernels
+    *out = t;
+    *maxt = mt;
+    return true;
+  };
+  IncGeo ig{};
+  int maxt = 0;
+  if (shp.S < 0) {
+    for (int S = std::min(-shp.S, kIncMaxSwaps); S >= 1 && !maxt; --S)
+      if (geometry(S, shp.wide, &ig, &maxt)) shp.S = S;
+  } else if (shp.S >= 1 && shp.S <= kIncMaxSwaps) {
+    geometry(shp.S, shp.wide, &ig, &maxt);
+  }
+  if (maxt == 0) return fail(c, GNA_UNSUPPORTED, "incremental local energy does not fit in LDS");
+  const int tpw = c->tpw, nch = c->nch;
+  IncKern ik;
+  switch (c->prec) {
+    case GNA_FP64: ik = inc_pick_f<PF64>(F, tpw, nch, maxt, shp.wide); break;
+    case GNA_FP32: ik = inc_pick_f<PF32>(F, tpw, nch, maxt, shp.wide); break;
+    default:
+      if (F == 16) ik = inc_pick<PBF16, 16>(tpw, nch, maxt, shp.wide);
+      else if (F == 32) ik = inc_pick<PBF16W, 32>(tpw, nch, maxt, shp.wide);
+      else ik = inc_pick<PBF16W, 64>(tpw, nch, maxt, shp.wide);
+  }
+  auto occ2 = [&](const void* fn, int threads_, int lds) {
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, threads_, lds) != hipSuccess || nb < 1) nb = 1;
+    (void)hipGetLastError();
+    return nb;
+  };
+  c->igeo = ig;
+  c->ik = ik;
+  c->inc_wide = shp.wide;
+  c->inc_maxt = maxt;
+  c->inc_per_xcd = std::max(1, shp.per_xcd);
+  c->inc_chunk_cap = std::min(chunk_cap, 64 * ig.nw);
+  c->grid_inc_base = c->n_cu * occ2(ik.base, 64 * c->geo.wpc, c->geo.lds_bytes);
+  c->grid_inc = c->n_cu * occ2(ik.eloc, 64 * ig.nw, ig.lds_bytes);
+  c->grid_sweep_inc = c->n_cu * occ2(ik.sweep, 64 * ig.nw, ig.lds_bytes);
+  return GNA_OK;
+}
 
 }  // namespace
 
@@ -1119,70 +1234,29 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
         for (int nd : lst) pos[nd] = -1;
       }
     }
-    IncGeo& ig = c->igeo;
-    ig.xcd = 8;   // MI355X: 8 XCDs, workgroups assigned round-robin
-    ig.rows = max_rows;
-    ig.tabw = (r8 + max_ball * dmax + 7) / 8 * 8;
-    ig.row_elems = (int)((4 * (F / 4) * c->sz_Acc + kRowPadBytes) / c->sz_Acc);
-    const int chunk_cap = 64 * kMaxWaves / 2;   // bonds per work item: at most one per thread
-    // largest number of exchanges in flight that fits in LDS and in four tiles per wave
-    int maxt = 0;
+    c->inc_r8 = r8;
+    c->inc_max_rows = max_rows;
+    c->inc_max_ball = max_ball;
+    c->inc_max_tiles = max_tiles;
+    c->inc_w_bytes = w_bytes;
+    c->lds_max = lds_max;
+    {
+      // shape signature: N, |E|, degree histogram, F, L, precision
+      std::vector<int> hist;
+      for (int d : deg) {
+        if ((int)hist.size() <= d) hist.resize(d + 1, 0);
+        ++hist[d];
+      }
+      std::string k = std::to_string(N) + "/" + std::to_string(E) + "/";
+      for (int h : hist) k += std::to_string(h) + ",";
+      k += "/" + std::to_string(F) + "/" + std::to_string(L) + "/" + std::to_string(c->prec);
+      c->tune_key = k;
+    }
     int s_cap = kIncMaxSwaps;
     if (const char* ev = std::getenv("GNA_INC_MAX_SWAPS")) s_cap = std::max(1, std::min(kIncMaxSwaps, std::atoi(ev)));
-    // 8 waves with up to 4 tiles each; the 16-wave shape (one tile per wave, 128
-    // VGPRs) is kept for the tuner
-    const bool wide = c->inc_wide;
-    for (int S = s_cap; S >= 1; --S) {
-      const int tiles = S * max_tiles;
-      const int nw = std::min(wide ? kMaxWaves : kMaxWaves / 2, tiles);
-      const int mt = (tiles + nw - 1) / nw;   // tiles per wave: 1 .. 4
-      if (mt > (wide ? 1 : 4)) continue;
-      size_t o = 0;
-      auto al = [](size_t x) { return (x + 15) & ~(size_t)15; };
-      IncGeo t = ig;
-      t.S = S;
-      t.nw = nw;
-      t.off_w = (int)o; o = al(o + w_bytes);
-      t.off_buf = (int)o; o = al(o + (size_t)S * max_rows * ig.row_elems * c->sz_Acc);
-      t.off_tab = (int)o; o = al(o + (size_t)S * ig.tabw * 2);
-      t.spw = (int)al(g.npad);
-      t.off_sp = (int)o; o = al(o + (size_t)S * t.spw);
-      t.off_red = (int)o; o = al(o + (size_t)kIncMaxSwaps * 2 * kMaxWaves * 8);
-      t.off_bias = (int)o; o = al(o + (size_t)F * c->sz_Acc);
-      t.off_emb = (int)o; o = al(o + (size_t)2 * F * c->sz_Acc);
-      t.off_head = (int)o; o = al(o + (size_t)2 * (F + 3) * 8);
-      t.off_ev = (int)o; o = al(o + (size_t)N * dmax * c->sz_Acc);
-      t.off_list = (int)o; o = al(o + (size_t)chunk_cap * 4);
-      t.off_cpy = (int)o; o = al(o + (size_t)S * max_rows * 16);
-      t.lds_bytes = (int)o;
-      if (o + 2048 > lds_max) continue;   // static LDS of the kernels
-      ig = t;
-      maxt = mt;
-      break;
-    }
-    if (maxt == 0) return bail(GNA_UNSUPPORTED, "incremental local energy does not fit in LDS");
-    c->inc_chunk_cap = std::min(chunk_cap, 64 * ig.nw);
-    switch (c->prec) {
-      case GNA_FP64: c->ik = inc_pick_f<PF64>(F, tpw, nch, maxt, wide); break;
-      case GNA_FP32: c->ik = inc_pick_f<PF32>(F, tpw, nch, maxt, wide); break;
-      default:
-        if (F == 16) c->ik = inc_pick<PBF16, 16>(tpw, nch, maxt, wide);
-        else if (F == 32) c->ik = inc_pick<PBF16W, 32>(tpw, nch, maxt, wide);
-        else c->ik = inc_pick<PBF16W, 64>(tpw, nch, maxt, wide);
-    }
-    {
-      auto occ2 = [&](const void* fn, int threads_, int lds) {
-        hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-        int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, threads_, lds) != hipSuccess || nb < 1) nb = 1;
-        (void)hipGetLastError();
-        return nb;
-      };
-      c->grid_inc_base = c->n_cu * occ2(c->ik.base, 64 * g.wpc, g.lds_bytes);
-      c->grid_inc = c->n_cu * occ2(c->ik.eloc, 64 * ig.nw, ig.lds_bytes);
-      c->grid_sweep_inc = c->n_cu * occ2(c->ik.sweep, 64 * ig.nw, ig.lds_bytes);
-    }
-    c->inc_r8 = r8;
+    IncShape shp{0, false, 2};
+    if (!tune_lookup(c->tune_key, &shp)) shp.S = -s_cap;   // default: the largest S <= s_cap that fits
+    if ((st = inc_configure(c, shp)) != GNA_OK) return bail(st, c->err);
     const size_t plane_bytes = (size_t)g.npad * F * c->sz_Acc;
     if ((st = dev_alloc(c, &c->d_ball_meta, meta.size() * 8)) ||
         (st = dev_alloc(c, &c->d_ball_cnt, cnt.size() * 4)) ||
@@ -1379,6 +1453,75 @@ gna_status gna_step(gna_ctx* c, double* theta, int8_t* spins, double* logpsi, in
   if (gna_status st = check_launch(c, "k_add_u64")) return st;
   if (gna_status st = gna_isgo_grad(c, theta, spins, logpsi, nullptr, B, grad, stats, eloc)) return st;
   return gna_sgd_update(c, theta, grad, lr);
+}
+
+gna_status gna_autotune(gna_ctx* c, const double* theta, const int8_t* spins, int32_t B, int32_t* chosen) {
+  if (!c) return GNA_INVALID_ARG;
+  if (gna_status st = check_batch(c, B)) return st;
+  if (B < 1) return fail(c, GNA_INVALID_ARG, "autotune needs B >= 1");
+  if (!valid_ptr(theta) || !valid_ptr(spins)) return fail(c, GNA_INVALID_ARG, "NULL pointer argument");
+  if (c->eloc_mode != GNA_ELOC_INCREMENTAL) {   // the full evaluator's shape is fixed at init
+    if (chosen) chosen[0] = chosen[1] = chosen[2] = chosen[3] = 0;
+    return GNA_OK;
+  }
+  if (gna_status st = prepare(c, theta)) return st;
+  const IncShape before{c->igeo.S, c->inc_wide, c->inc_per_xcd};
+  // candidates: the four largest S that fit, both wave shapes, one or two samples per XCD
+  std::vector<IncShape> cand;
+  int smax = 0;
+  for (int S = kIncMaxSwaps; S >= 1 && !smax; --S)
+    if (inc_configure(c, IncShape{S, false, 2}) == GNA_OK) smax = S;
+  for (int S = smax; S >= 1 && S > smax - 4; --S)
+    for (int wide = 0; wide < 2; ++wide)
+      for (int px = 1; px <= 2; ++px) cand.push_back(IncShape{S, wide != 0, px});
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(c, GNA_HIP_ERROR, "hipEventCreate failed");
+  const bool prof = c->prof_on;
+  c->prof_on = false;
+  IncShape best = before;
+  float best_ms = -1.f;
+  gna_status st = GNA_OK;
+  for (const IncShape& sh : cand) {
+    if (inc_configure(c, sh) != GNA_OK) continue;
+    if ((st = run_eloc(c, theta, spins, B, c->d_base, c->d_eloc, c->d_nev)) != GNA_OK) break;   // warm
+    (void)hipEventRecord(e0, c->stream);
+    for (int r = 0; r < 2 && st == GNA_OK; ++r) st = run_eloc(c, theta, spins, B, c->d_base, c->d_eloc, c->d_nev);
+    (void)hipEventRecord(e1, c->stream);
+    if (st != GNA_OK) break;
+    if (hipEventSynchronize(e1) != hipSuccess) { st = fail(c, GNA_HIP_ERROR, "hipEventSynchronize failed"); break; }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (best_ms < 0.f || ms < best_ms) {
+      best_ms = ms;
+      best = sh;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->prof_on = prof;
+  if (st != GNA_OK) {
+    (void)inc_configure(c, before);
+    return st;
+  }
+  if ((st = inc_configure(c, best)) != GNA_OK) return st;
+  tune_store(c->tune_key, best);
+  if (chosen) {
+    chosen[0] = best.S;
+    chosen[1] = best.wide ? 16 : 8;
+    chosen[2] = best.per_xcd;
+    chosen[3] = (int32_t)(best_ms * 500.f);   // microseconds per local-energy call
+  }
+  return GNA_OK;
+}
+
+int32_t gna_config_info(const gna_ctx* c, int32_t* info, int32_t n) {
+  if (!c || (n > 0 && !info)) return -1;
+  const int32_t v[8] = {c->eloc_mode, c->eloc_mode ? c->igeo.S : 0, c->eloc_mode ? c->igeo.nw : c->geo.wpc,
+                        c->eloc_mode ? c->inc_maxt : c->tpw, c->eloc_mode ? c->inc_per_xcd : 0, c->prec, c->F,
+                        c->L};
+  for (int k = 0; k < n && k < 8; ++k) info[k] = v[k];
+  return 8;
 }
 
 gna_status gna_profile_enable(gna_ctx* c, int32_t on) {

@@ -112,3 +112,45 @@ def test_step_sampler_matches_oracle_trajectory():
     assert np.array_equal(sp.cpu().numpy(), rs)
     assert np.max(np.abs(lp.cpu().numpy() - rlp)) < 1e-11
     g.close()
+
+
+def test_autotune_keeps_results_and_is_cached():
+    n, e = w.kagome(6, 6)
+    F, L, B = 32, 4, 64
+    th, sp = _state(n, F, L, B, 9)
+    g1 = _ctx(n, e, F, L, "bf16", B, "incremental")
+    el0, nev0 = g1.local_energy(th, sp)
+    choice = g1.autotune(th, sp)
+    info = g1.config_info()
+    print(f"[gpu] autotune kagome108 bf16: {choice} -> {info}", file=sys.stderr, flush=True)
+    assert info["jobs_in_flight"] == choice["jobs_in_flight"] >= 1
+    assert info["waves"] == choice["waves"] and info["samples_per_xcd"] == choice["samples_per_xcd"]
+    el1, nev1 = g1.local_energy(th, sp)
+    # the shape changes only the order of the final FP64 sums
+    scale = float(el0.abs().max())
+    assert int(nev0.item()) == int(nev1.item())
+    assert float((el1 - el0).abs().max()) < 1e-12 * scale
+    # a later context of the same signature starts from the tuned shape
+    g2 = _ctx(n, e, F, L, "bf16", B, "incremental")
+    assert g2.config_info() == info
+    el2, _ = g2.local_energy(th, sp)
+    assert torch.equal(el2, el1)
+    # and its sampler still takes the full sampler's decisions
+    lp = g2.logpsi(th, sp)
+    s_inc = sp.clone()
+    acc_i = g2.metropolis_sweep(th, s_inc, lp.clone(), n_sweeps=1, seed=3)
+    g3 = _ctx(n, e, F, L, "bf16", B, "full")
+    s_full = sp.clone()
+    acc_f = g3.metropolis_sweep(th, s_full, g3.logpsi(th, sp), n_sweeps=1, seed=3)
+    assert torch.equal(s_inc, s_full) and torch.equal(acc_i, acc_f)
+    for g in (g1, g2, g3):
+        g.close()
+
+
+def test_autotune_full_mode_is_a_no_op():
+    n, e = w.kagome(2, 2)
+    th, sp = _state(n, 16, 2, 8, 1)
+    g = _ctx(n, e, 16, 2, "fp32", 8, "full")
+    assert g.autotune(th, sp)["jobs_in_flight"] == 0
+    assert g.config_info()["eloc_mode"] == 0
+    g.close()
