@@ -993,9 +993,10 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
   c->sz_Acc = (c->prec == GNA_FP64) ? 8 : 4;
 
   auto bail = [&](gna_status st, const std::string& m) {
+    const std::string msg = m;   // m may be c->err
     free_all(c);
     delete c;
-    return init_fail(st, m);
+    return init_fail(st, msg);
   };
   hipError_t he = hipGetDevice(&c->device);
   if (he != hipSuccess) return bail(GNA_HIP_ERROR, std::string("hipGetDevice: ") + hipGetErrorString(he));
