@@ -833,6 +833,7 @@ struct IncShape {
   int S;
   bool wide;
   int per_xcd;
+  int nw = 0;   // waves per workgroup; 0: as many as useful (8, or 16 when wide)
 };
 
 std::mutex g_tune_mu;
@@ -867,9 +868,9 @@ gna_status inc_configure(gna_ctx* c, IncShape shp) {
   base.tabw = (c->inc_r8 + max_ball * dmax + 7) / 8 * 8;
   base.row_elems = (int)((4 * (F / 4) * c->sz_Acc + kRowPadBytes) / c->sz_Acc);
   const int chunk_cap = 64 * kMaxWaves / 2;   // bonds per work item: at most one per thread
-  auto geometry = [&](int S, bool wide, IncGeo* out, int* maxt) {
+  auto geometry = [&](int S, bool wide, int nw_req, IncGeo* out, int* maxt) {
     const int tiles = S * max_tiles;
-    const int nw = std::min(wide ? kMaxWaves : kMaxWaves / 2, tiles);
+    const int nw = std::min(nw_req > 0 ? nw_req : (wide ? kMaxWaves : kMaxWaves / 2), tiles);
     const int mt = (tiles + nw - 1) / nw;   // tiles per wave
     if (mt > (wide ? 1 : 4)) return false;
     size_t o = 0;
@@ -899,9 +900,9 @@ gna_status inc_configure(gna_ctx* c, IncShape shp) {
   int maxt = 0;
   if (shp.S < 0) {
     for (int S = std::min(-shp.S, kIncMaxSwaps); S >= 1 && !maxt; --S)
-      if (geometry(S, shp.wide, &ig, &maxt)) shp.S = S;
+      if (geometry(S, shp.wide, shp.nw, &ig, &maxt)) shp.S = S;
   } else if (shp.S >= 1 && shp.S <= kIncMaxSwaps) {
-    geometry(shp.S, shp.wide, &ig, &maxt);
+    geometry(shp.S, shp.wide, shp.nw, &ig, &maxt);
   }
   if (maxt == 0) return fail(c, GNA_UNSUPPORTED, "incremental local energy does not fit in LDS");
   const int tpw = c->tpw, nch = c->nch;
@@ -1466,15 +1467,21 @@ gna_status gna_autotune(gna_ctx* c, const double* theta, const int8_t* spins, in
     return GNA_OK;
   }
   if (gna_status st = prepare(c, theta)) return st;
-  const IncShape before{c->igeo.S, c->inc_wide, c->inc_per_xcd};
+  const IncShape before{c->igeo.S, c->inc_wide, c->inc_per_xcd, c->igeo.nw};
   // candidates: the four largest S that fit, both wave shapes, one or two samples per XCD
   std::vector<IncShape> cand;
   int smax = 0;
   for (int S = kIncMaxSwaps; S >= 1 && !smax; --S)
     if (inc_configure(c, IncShape{S, false, 2}) == GNA_OK) smax = S;
   for (int S = smax; S >= 1 && S > smax - 4; --S)
-    for (int wide = 0; wide < 2; ++wide)
-      for (int px = 1; px <= 2; ++px) cand.push_back(IncShape{S, wide != 0, px});
+    for (int px = 1; px <= 2; ++px) {
+      cand.push_back(IncShape{S, true, px, 0});
+      // 8 waves, and fewer waves where that evens out the tiles per wave
+      const int tiles = S * c->inc_max_tiles;
+      for (int nw = kMaxWaves / 2; nw >= 5; --nw)
+        if (nw == kMaxWaves / 2 || (tiles + nw - 1) / nw == (tiles + kMaxWaves / 2 - 1) / (kMaxWaves / 2))
+          cand.push_back(IncShape{S, false, px, nw});
+    }
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(c, GNA_HIP_ERROR, "hipEventCreate failed");
@@ -1509,7 +1516,7 @@ gna_status gna_autotune(gna_ctx* c, const double* theta, const int8_t* spins, in
   tune_store(c->tune_key, best);
   if (chosen) {
     chosen[0] = best.S;
-    chosen[1] = best.wide ? 16 : 8;
+    chosen[1] = c->igeo.nw;
     chosen[2] = best.per_xcd;
     chosen[3] = (int32_t)(best_ms * 500.f);   // microseconds per local-energy call
   }
