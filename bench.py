@@ -109,6 +109,7 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline steps only (for profilers)")
     ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay timing")
     ap.add_argument("--no-tune", action="store_true", help="keep the default incremental shape")
+    ap.add_argument("--graph-reps", type=int, default=20, help="timed graph replays per component")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -162,6 +163,8 @@ def main():
     grad_buf = torch.empty(g.num_params, dtype=torch.float64, device=dev)
     el_buf = torch.empty((B, 2), dtype=torch.float64, device=dev)
     acc_buf = torch.empty(B, dtype=torch.int32, device=dev)
+
+    theta_init, spins_init = theta.clone(), spins.clone()
 
     def step(k, stats=None):
         # gna_step: log psi, one sweep (counter advanced on the device), ISGO gradient, SGD
@@ -218,14 +221,19 @@ def main():
     # ---------------- the same step replayed from a captured HIP graph ----------------
     graph_info = None
     if not args.no_graph and not args.quick:
+        # replay the same trajectory as the eager run: initial state, warm-up steps, timed steps
         stats_g = torch.empty(8, dtype=torch.float64, device=dev)
+        theta.copy_(theta_init)
+        spins.copy_(spins_init)
+        counter.zero_()
         torch.cuda.synchronize()
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph):
             g.set_stream(torch.cuda.current_stream())
             step(0, stats=stats_g)
         g.set_stream(torch.cuda.current_stream())
-        graph.replay()                   # warm
+        for _ in range(args.warmup):
+            graph.replay()
         torch.cuda.synchronize()
         tg0 = time.perf_counter()
         for _ in range(args.steps):
@@ -234,11 +242,32 @@ def main():
         tg1 = time.perf_counter()
         gms = 1e3 * (tg1 - tg0) / args.steps
         graph_info = {"ms_per_step": gms, "evals_per_s": (evals / args.steps) / (gms * 1e-3),
-                      "note": "whole step captured once and replayed; evals per step from the timed eager steps"}
+                      "note": "whole step captured once and replayed from the same initial state as the "
+                              "eager run (same trajectory); evals per step from the timed eager steps"}
         log(f"[bench] graph replay: {gms:.2f} ms/step, {graph_info['evals_per_s']:.4g} evals/s")
         del graph
 
     # ---------------- E_loc alone: both modes, every precision ----------------
+    # one eager call with per-kernel events (kernel time for the roofline), then the call
+    # captured in a HIP graph: 3 warm-up and `--graph-reps` timed replays, median and min
+    def graph_times(fn, reps):
+        torch.cuda.synchronize()
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr):
+            fn(torch.cuda.current_stream())
+        for _ in range(3):
+            gr.replay()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in ev:
+            a.record()
+            gr.replay()
+            b.record()
+        torch.cuda.synchronize()
+        ms = sorted(a.elapsed_time(b) for a, b in ev)
+        del gr
+        return ms[len(ms) // 2], ms[0]
+
     per_prec = {}
     eloc_out = {}
     runs = [(args.precision, args.eloc_mode), (args.precision, "full" if args.eloc_mode == "incremental" else "incremental")]
@@ -272,10 +301,49 @@ def main():
                          "kernel": kn, "kernel_ms": kms2 / max(kl2, 1),
                          "kernel_tflops": kf / (kms2 / max(kl2, 1) * 1e-3) / 1e12,
                          "mfma_frac": kf / (kms2 / max(kl2, 1) * 1e-3) / PEAK[prec]}
+        if not args.no_graph and not args.quick:
+            el_g = torch.empty((Bp, 2), dtype=torch.float64, device=dev)
+            nev_g = torch.empty(1, dtype=torch.int64, device=dev)
+
+            def call(stream, gp=gp, th0=th0, sp0=sp0, el_g=el_g, nev_g=nev_g):
+                gp.set_stream(stream)
+                gp.local_energy(th0, sp0, out=el_g, n_evals=nev_g)
+            med, mn = graph_times(call, args.graph_reps)
+            gp.set_stream(torch.cuda.current_stream())
+            per_prec[key].update({"graph_ms_median": med, "graph_ms_min": mn,
+                                  "graph_evals_per_s": ne / (med * 1e-3)})
+            log(f"[bench] E_loc {prec} {mode}: graph replay median {med:.2f} ms (min {mn:.2f}), "
+                f"{ne / (med * 1e-3):.4g} evals/s")
         eloc_out[key] = el.cpu().numpy()
         log(f"[bench] E_loc {prec} {mode}: B={Bp} {rate:.4g} evals/s, {kn} {kms2 / max(kl2, 1):.2f} ms")
         if gp is not g:
             gp.close()
+
+    # ---------------- sampler (a6) and reverse pass (a8) on their own ----------------
+    components = None
+    if not args.no_graph and not args.quick:
+        th0 = torch.from_numpy(theta_np).to(dev)
+        sp_c = torch.from_numpy(spins_np).to(dev)
+        lp_c = g.logpsi(th0, sp_c)
+        acc_c = torch.empty(B, dtype=torch.int32, device=dev)
+        cot = torch.from_numpy(np.random.default_rng(0).normal(size=(B, 2))).to(dev)
+        gr_c = torch.empty(g.num_params, dtype=torch.float64, device=dev)
+
+        def sweep_call(stream):
+            g.set_stream(stream)
+            g.metropolis_sweep(th0, sp_c, lp_c, n_sweeps=1, seed=seed, counter_base=0, n_accept=acc_c)
+
+        def vjp_call(stream):
+            g.set_stream(stream)
+            g.logpsi_vjp(th0, sp_c, cot, out=gr_c)
+        sw_med, sw_min = graph_times(sweep_call, args.graph_reps)
+        vj_med, vj_min = graph_times(vjp_call, args.graph_reps)
+        g.set_stream(torch.cuda.current_stream())
+        components = {"sweep_ms_median": sw_med, "sweep_ms_min": sw_min,
+                      "sweep_proposals_per_s": B * n / (sw_med * 1e-3),
+                      "vjp_ms_median": vj_med, "vjp_ms_min": vj_min,
+                      "vjp_samples_per_s": B / (vj_med * 1e-3)}
+        log(f"[bench] sweep (1 sweep, {B} chains): {sw_med:.2f} ms; VJP ({B} samples): {vj_med:.2f} ms")
 
     # ---------------- CPU baseline (FP64 oracle) and error columns ----------------
     cpu = None
@@ -294,6 +362,18 @@ def main():
         ne_cpu = oracle.n_evals(sub, e)
         cpu = {"value": ne_cpu / tcpu, "unit": "evals/s", "cores": threads, "kind": "oracle",
                "sample": f"first {S} of {B} configurations ({ne_cpu} log-psi evals, {tcpu:.1f}s)"}
+        try:   # the same oracle on one thread, on a smaller sample
+            from threadpoolctl import threadpool_limits
+            with threadpool_limits(limits=1):
+                S1 = max(1, S // 4)
+                t1c = time.perf_counter()
+                oracle.local_energy(theta_np, spins_np[:S1], n, e, F, L)
+                t1c = time.perf_counter() - t1c
+            cpu["value_1_thread"] = oracle.n_evals(spins_np[:S1], e) / t1c
+            cpu["sample_1_thread"] = f"first {S1} configurations, {t1c:.1f}s"
+        except Exception as exc:   # threadpoolctl missing: the all-core figure stands alone
+            cpu["value_1_thread"] = None
+            cpu["sample_1_thread"] = f"not measured ({type(exc).__name__})"
         for prec, el in eloc_out.items():
             got = el[:S]
             es, rs = got[:, 0].mean() / n, ref.real.mean() / n
@@ -316,6 +396,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "graph": graph_info,
+        "components": components,
         "precisions": per_prec,
         "kernels_ms_per_step": {k: v[1] / args.steps for k, v in sorted(prof.items())},
     }
