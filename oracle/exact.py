@@ -41,8 +41,10 @@ def _keys(states: np.ndarray) -> np.ndarray:
     return bits @ (np.int64(1) << np.arange(states.shape[1], dtype=np.int64))
 
 
-def heisenberg_matrix(states: np.ndarray, edges, jz: float = 1.0, jxy: float = 1.0):
-    """Sparse H restricted to the span of ``states`` (closed under bond swaps)."""
+def heisenberg_matrix(states: np.ndarray, edges, jz: float = 1.0, jxy: float = 1.0,
+                      hb: float = 0.0, cb: float = 0.0):
+    """Sparse H restricted to the span of ``states`` (closed under bond swaps); with
+    ``hb, cb`` each bond also carries ``hb (S^z_i + S^z_j)/2 + cb``."""
     e = np.asarray(edges, dtype=np.int64)
     keys = _keys(states)
     index = {int(k): a for a, k in enumerate(keys)}
@@ -50,7 +52,7 @@ def heisenberg_matrix(states: np.ndarray, edges, jz: float = 1.0, jxy: float = 1
     for a, s in enumerate(states):
         diag = 0.0
         for i, j in e:
-            diag += jz * (s[i] / 2.0) * (s[j] / 2.0)
+            diag += jz * (s[i] / 2.0) * (s[j] / 2.0) + hb * (s[i] / 2.0 + s[j] / 2.0) / 2.0 + cb
             if s[i] != s[j]:
                 # S^+_i S^-_j + S^-_i S^+_j maps the pair to its swapped pair with amplitude 1
                 t = s.copy()

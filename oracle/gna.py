@@ -183,9 +183,12 @@ def n_evals(spins, edges) -> int:
 
 
 def local_energy_generic(logpsi_fn, spins, edges, jz: float = 1.0, jxy: float = 1.0,
-                         base=None, batch_target: int = 8192):
-    """``E(s) = sum_<ij> [jz s_i s_j/4 + (jxy/2)[s_i != s_j] exp(logpsi(s^ij) - logpsi(s))]``.
+                         base=None, batch_target: int = 8192, hb: float = 0.0, cb: float = 0.0):
+    """``E(s) = sum_<ij> [jz s_i s_j/4 + hb (s_i + s_j)/4 + cb
+                         + (jxy/2)[s_i != s_j] exp(logpsi(s^ij) - logpsi(s))]``.
 
+    The Heisenberg model of Section 3 is ``hb = cb = 0``; the hard-core bosons of
+    Eq. 4 map onto this bond form (``oracle.hcb.spin_couplings``).
     ``logpsi_fn(spins[b, N]) -> [b, 2]`` is any ansatz; terms are added in edge-list
     order.  Returns complex ``[B]``.
     """
@@ -214,7 +217,8 @@ def local_energy_generic(logpsi_fn, spins, edges, jz: float = 1.0, jxy: float = 
         rows = np.concatenate(rows) if rows else np.zeros(0, int)
         o = 0
         for b in range(a, min(B, a + per)):
-            diag = 0.25 * jz * float(np.sum(s[b, e[:, 0]].astype(np.int64) * s[b, e[:, 1]]))
+            si, sj = s[b, e[:, 0]].astype(np.int64), s[b, e[:, 1]].astype(np.int64)
+            diag = 0.25 * jz * float(np.sum(si * sj)) + 0.25 * hb * float(np.sum(si + sj)) + cb * len(e)
             k = int(np.sum(rows == b))
             d = lp[o:o + k] - base[b]
             ratio = np.exp(d[:, 0] + 1j * d[:, 1])          # psi(s^ij) / psi(s)
@@ -227,10 +231,10 @@ def local_energy_generic(logpsi_fn, spins, edges, jz: float = 1.0, jxy: float = 
 
 
 def local_energy(theta, spins, n, edges, F, L, tied=True, jz=1.0, jxy=1.0,
-                 formulation="sparse"):
+                 formulation="sparse", hb=0.0, cb=0.0):
     """E_loc of the GCN ansatz (complex ``[B]``)."""
     fn = lambda c: logpsi(theta, c, n, edges, F, L, tied, formulation)
-    return local_energy_generic(fn, spins, edges, jz, jxy)
+    return local_energy_generic(fn, spins, edges, jz, jxy, hb=hb, cb=cb)
 
 
 # ----------------------------------------------------------------------------------
@@ -307,7 +311,7 @@ def logpsi_vjp(theta, spins, cot, n, edges, F, L, tied=True, formulation="sparse
 
 
 def isgo_grad(theta, spins, logpsi_old, n, edges, F, L, tied=True, counts=None,
-              jz=1.0, jxy=1.0, formulation="sparse"):
+              jz=1.0, jxy=1.0, formulation="sparse", hb=0.0, cb=0.0):
     """One ISGO update's gradient (Eq. 3): new log psi, E_loc under the new psi,
     weights, then the reverse pass with the centred cotangents.
 
@@ -315,7 +319,7 @@ def isgo_grad(theta, spins, logpsi_old, n, edges, F, L, tied=True, counts=None,
     """
     new = logpsi(theta, spins, n, edges, F, L, tied, formulation)
     fn = lambda c: logpsi(theta, c, n, edges, F, L, tied, formulation)
-    E = local_energy_generic(fn, spins, edges, jz, jxy, base=new)
+    E = local_energy_generic(fn, spins, edges, jz, jxy, base=new, hb=hb, cb=cb)
     stats, cot = isgo_stats(logpsi_old, new, E, counts)
     stats["n_evals"] = n_evals(spins, edges)
     g = logpsi_vjp(theta, spins, cot, n, edges, F, L, tied, formulation)

@@ -6,12 +6,12 @@ pass, no energy.  Both the CPU oracle and the HIP path receive exactly these
 arrays as inputs.
 """
 from .lattices import kagome, triangular, erdos_renyi_connected, complete_graph, ring
-from .params import theta_layout, num_params, glorot_theta
+from .params import theta_layout, num_params, glorot_theta, param_slices
 from .spins import random_sz0_spins, random_spins
 from .presets import PRESETS, preset
 
 __all__ = [
     "kagome", "triangular", "erdos_renyi_connected", "complete_graph", "ring",
-    "theta_layout", "num_params", "glorot_theta",
+    "theta_layout", "num_params", "glorot_theta", "param_slices",
     "random_sz0_spins", "random_spins", "PRESETS", "preset",
 ]

@@ -36,11 +36,23 @@ def num_params(F: int, L: int, tied: bool = True) -> int:
     return int(sum(int(np.prod(shape)) for _, shape, _, _ in theta_layout(F, L, tied)))
 
 
+def param_slices(F: int, L: int, tied: bool = True) -> dict:
+    """``{name: (start, stop)}`` of each parameter block in the flat vector."""
+    out, o = {}, 0
+    for name, shape, _, _ in theta_layout(F, L, tied):
+        size = int(np.prod(shape))
+        out[name] = (o, o + size)
+        o += size
+    return out
+
+
 def glorot_theta(F: int, L: int, tied: bool = True, seed: int = 0,
-                 weight_scale: float = 1.0, bias_std: float = 0.0) -> np.ndarray:
+                 weight_scale: float = 1.0, bias_std: float = 0.0, real_head: bool = False) -> np.ndarray:
     """Glorot-normal weights ``N(0, 2/(fan_in+fan_out))`` drawn in layout order from
     ``PCG64(seed)``; biases are zero unless ``bias_std > 0`` (then drawn too, so that
     tests exercise every parameter).  ``weight_scale`` multiplies every weight.
+    ``real_head`` zeroes the phase head after the draw: a positive wavefunction, the
+    single real head the paper uses for hard-core bosons (Section 4).
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     parts = []
@@ -50,4 +62,9 @@ def glorot_theta(F: int, L: int, tied: bool = True, seed: int = 0,
             parts.append(rng.normal(0.0, bias_std, size) if bias_std > 0 else np.zeros(size))
         else:
             parts.append(weight_scale * rng.normal(0.0, np.sqrt(2.0 / (fi + fo)), size))
-    return np.concatenate(parts).astype(np.float64)
+    theta = np.concatenate(parts).astype(np.float64)
+    if real_head:
+        sl = param_slices(F, L, tied)
+        for name in ("v_p", "c_p"):
+            theta[sl[name][0]:sl[name][1]] = 0.0
+    return theta
