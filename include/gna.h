@@ -168,6 +168,15 @@ gna_status gna_step(gna_ctx *ctx, double *theta, int8_t *spins, double *logpsi, 
                     int32_t n_sweeps, uint64_t seed, uint64_t *counter, double lr, double *grad,
                     double *stats, double *eloc, int32_t *n_accept);
 
+/* The bond Hamiltonian of gna_local_energy (and so of gna_isgo_grad, gna_step):
+ *   E(s) = sum_<ij> [ jz s_i s_j / 4 + hb (s_i + s_j) / 4 + cb
+ *                     + (jxy / 2) [s_i != s_j] psi(s^ij) / psi(s) ]
+ * gna_init sets (jz, jxy) from the config and hb = cb = 0 (the Heisenberg model of
+ * Section 3).  The hard-core bosons of Eq. 4 (hopping t, interaction V, occupation
+ * n = (1 + s)/2) are jz = V, jxy = -2t, hb = V, cb = V/4.  Host-side, synchronous;
+ * applies to every later call.  INVALID_ARG for a non-finite value.          */
+gna_status gna_set_couplings(gna_ctx *ctx, double jz, double jxy, double hb, double cb);
+
 /* Tile and workgroup shapes of the incremental kernels chosen by measurement:
  * times gna_local_energy on (theta, spins[B]) for the candidate shapes (jobs in
  * flight per workgroup, 8 or 16 waves, one or two samples in flight per XCD),

@@ -66,6 +66,8 @@ _EXPORTS = {
     "gna_autotune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                       ctypes.POINTER(ctypes.c_int32)]),
     "gna_config_info": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]),
+    "gna_set_couplings": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_double]),
     "gna_profile_enable": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "gna_profile_read": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_char_p,
                                           ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
@@ -258,6 +260,14 @@ class GNA:
         keys = ("eloc_mode", "jobs_in_flight", "waves", "tiles_per_wave", "samples_per_xcd", "precision",
                 "features", "layers")
         return dict(zip(keys, list(v)))
+
+    def set_couplings(self, jz: float, jxy: float, hb: float = 0.0, cb: float = 0.0):
+        """Bond Hamiltonian ``jz s_i s_j/4 + hb (s_i + s_j)/4 + cb + (jxy/2)[s_i != s_j] swap``."""
+        self._check(self._lib.gna_set_couplings(self._ctx, float(jz), float(jxy), float(hb), float(cb)))
+
+    def set_hard_core_bosons(self, t: float, V: float):
+        """The hard-core bosons of Eq. 4 (occupation n = (1 + s)/2)."""
+        self.set_couplings(V, -2.0 * t, V, V / 4.0)
 
     def set_stream(self, stream):
         """Enqueue later calls on ``stream`` (a torch.cuda.Stream), e.g. a graph-capture stream."""

@@ -151,14 +151,18 @@ __global__ void k_add_u64(unsigned long long* p, unsigned long long d) {
 }
 
 __global__ void k_eloc_finalize(const int8_t* __restrict__ spins, int N, const int2* __restrict__ edges,
-                                int E, double jz, double jxy, int B, int n_chunks,
+                                int E, double jz, double jxy, double hb, double cb, int B, int n_chunks,
                                 const double* __restrict__ partial, const int* __restrict__ cnt,
                                 double* __restrict__ eloc, long long* n_evals) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
   const int8_t* sb = spins + (size_t)b * N;
-  long long diag = 0;
-  for (int e = 0; e < E; ++e) diag += (int)sb[edges[e].x] * (int)sb[edges[e].y];
+  long long diag = 0, field = 0;
+  for (int e = 0; e < E; ++e) {
+    const int si = sb[edges[e].x], sj = sb[edges[e].y];
+    diag += si * sj;
+    field += si + sj;
+  }
   double sr = 0, cr = 0, si = 0, ci = 0;
   long long ne = 1;
   for (int c = 0; c < n_chunks; ++c) {
@@ -169,7 +173,7 @@ __global__ void k_eloc_finalize(const int8_t* __restrict__ spins, int N, const i
     ci += o[3];
     ne += cnt[(size_t)b * n_chunks + c];
   }
-  eloc[2 * (size_t)b] = 0.25 * jz * (double)diag + 0.5 * jxy * (sr + cr);
+  eloc[2 * (size_t)b] = 0.25 * jz * (double)diag + 0.25 * hb * (double)field + cb * (double)E + 0.5 * jxy * (sr + cr);
   eloc[2 * (size_t)b + 1] = 0.5 * jxy * (si + ci);
   if (n_evals) atomicAdd(reinterpret_cast<unsigned long long*>(n_evals), (unsigned long long)ne);
 }
@@ -504,7 +508,7 @@ VKern vpick_f(int F, int tpw, int nch) {
 
 struct gna_ctx {
   int N = 0, E = 0, F = 0, L = 0, tied = 1, prec = 0, max_batch = 0;
-  double jz = 1.0, jxy = 1.0;
+  double jz = 1.0, jxy = 1.0, hb = 0.0, cb = 0.0;   // bond Hamiltonian (gna_set_couplings)
   hipStream_t stream = nullptr;
   int device = 0, n_cu = 0;
   int64_t P = 0;
@@ -746,7 +750,7 @@ gna_status run_eloc(gna_ctx* c, const double* theta, const int8_t* spins, int B,
   }
   Timed tm(c, "k_eloc_finalize");
   hipLaunchKernelGGL(k_eloc_finalize, dim3((B + 255) / 256), dim3(256), 0, c->stream, spins, c->N,
-                     c->d_edges, c->E, c->jz, c->jxy, B, n_chunks, partial, cnt, eloc, nev);
+                     c->d_edges, c->E, c->jz, c->jxy, c->hb, c->cb, B, n_chunks, partial, cnt, eloc, nev);
   return check_launch(c, "k_eloc_finalize");
 }
 
@@ -1530,6 +1534,17 @@ int32_t gna_config_info(const gna_ctx* c, int32_t* info, int32_t n) {
                         c->L};
   for (int k = 0; k < n && k < 8; ++k) info[k] = v[k];
   return 8;
+}
+
+gna_status gna_set_couplings(gna_ctx* c, double jz, double jxy, double hb, double cb) {
+  if (!c) return GNA_INVALID_ARG;
+  if (!std::isfinite(jz) || !std::isfinite(jxy) || !std::isfinite(hb) || !std::isfinite(cb))
+    return fail(c, GNA_INVALID_ARG, "couplings must be finite");
+  c->jz = jz;
+  c->jxy = jxy;
+  c->hb = hb;
+  c->cb = cb;
+  return GNA_OK;
 }
 
 gna_status gna_profile_enable(gna_ctx* c, int32_t on) {
