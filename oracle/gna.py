@@ -128,12 +128,44 @@ def _aggregate(H, n, edges, formulation, cache):
     raise ValueError(formulation)
 
 
+LN_EPS = 1e-5   # layer-normalisation epsilon (unstated in the paper; no affine parameters)
+
+
+def activate(P, act: str = "tanh"):
+    """The nonlinearity f of Eq. 1 on the last axis of ``P``.
+
+    ``tanh``; or ``relu_ln``, the paper's own choice (Section 2): ReLU, then a layer
+    normalisation over the F features of each node, ``(y - mean y) / sqrt(var y + eps)``
+    with the biased variance.  Returns ``(H, aux)``; ``aux = (y, r)`` for ``relu_ln``
+    (post-ReLU values and ``r = 1/sqrt(var + eps)``), ``None`` for tanh.
+    """
+    if act == "tanh":
+        return np.tanh(P), None
+    if act != "relu_ln":
+        raise ValueError(act)
+    y = np.maximum(P, 0.0)
+    mu = y.mean(axis=-1, keepdims=True)
+    var = ((y - mu) ** 2).mean(axis=-1, keepdims=True)
+    r = 1.0 / np.sqrt(var + LN_EPS)
+    return (y - mu) * r, (y, r)
+
+
+def activate_vjp(dH, H, aux, act: str = "tanh"):
+    """Cotangent of the pre-activation from that of ``H = f(P)`` (same shapes)."""
+    if act == "tanh":
+        return dH * (1.0 - H ** 2)
+    y, r = aux
+    # d xhat_i / d y_j = r (delta_ij - 1/F - xhat_i xhat_j / F)
+    dy = r * (dH - dH.mean(axis=-1, keepdims=True) - H * (dH * H).mean(axis=-1, keepdims=True))
+    return dy * (y > 0.0)
+
+
 def forward(theta, spins, n: int, edges, F: int, L: int, tied: bool = True,
-            formulation: str = "sparse", keep: bool = False):
+            formulation: str = "sparse", keep: bool = False, act: str = "tanh"):
     """Evaluate the ansatz on ``spins[B, N]`` in {-1, +1}.
 
     Returns ``logpsi[B, 2]`` = (log|psi|, phase); with ``keep=True`` also a dict of
-    per-layer inputs/outputs for the reverse pass.
+    per-layer inputs/outputs for the reverse pass.  ``act`` selects f (``activate``).
     """
     p = unpack_theta(theta, F, L, tied)
     s = np.asarray(spins)
@@ -141,32 +173,33 @@ def forward(theta, spins, n: int, edges, F: int, L: int, tied: bool = True,
         raise ValueError("spins must be [B, N]")
     x = (s.astype(np.int64) + 1) // 2                     # occupation in {0, 1}
     onehot = np.stack([x == 0, x == 1], axis=-1).astype(np.float64)   # [B, N, 2]
-    H = np.tanh(onehot @ p["W_e"] + p["b_e"])             # embedding
+    H, aux = activate(onehot @ p["W_e"] + p["b_e"], act)   # embedding
     cache: dict = {}
-    Hs, Ms = [H], []
+    Hs, Ms, auxs = [H], [], [aux]
     for l in range(L):
         W = p["W"][0 if tied else l]
         b = p["b"][0 if tied else l]
         M = _aggregate(H, n, edges, formulation, cache)
         P = np.concatenate([M, H], axis=-1) @ W + b        # Eq. (1), message first
-        H = np.tanh(P)
+        H, aux = activate(P, act)
         Ms.append(M)
         Hs.append(H)
+        auxs.append(aux)
     z = np.concatenate([H.sum(axis=1), onehot.sum(axis=1)], axis=-1)   # [B, F+2]
     logabs = z @ p["v_a"] + p["c_a"]
     phase = z @ p["v_p"] + p["c_p"]
     out = np.stack([logabs, phase], axis=-1)
     if keep:
-        return out, {"onehot": onehot, "H": Hs, "M": Ms, "z": z}
+        return out, {"onehot": onehot, "H": Hs, "M": Ms, "z": z, "aux": auxs}
     return out
 
 
-def logpsi(theta, spins, n, edges, F, L, tied=True, formulation="sparse", chunk=4096):
+def logpsi(theta, spins, n, edges, F, L, tied=True, formulation="sparse", chunk=4096, act="tanh"):
     """``forward`` over a large batch in chunks (same arithmetic per row)."""
     s = np.asarray(spins)
     out = np.empty((s.shape[0], 2))
     for a in range(0, s.shape[0], chunk):
-        out[a:a + chunk] = forward(theta, s[a:a + chunk], n, edges, F, L, tied, formulation)
+        out[a:a + chunk] = forward(theta, s[a:a + chunk], n, edges, F, L, tied, formulation, act=act)
     return out
 
 
@@ -231,9 +264,9 @@ def local_energy_generic(logpsi_fn, spins, edges, jz: float = 1.0, jxy: float = 
 
 
 def local_energy(theta, spins, n, edges, F, L, tied=True, jz=1.0, jxy=1.0,
-                 formulation="sparse", hb=0.0, cb=0.0):
+                 formulation="sparse", hb=0.0, cb=0.0, act="tanh"):
     """E_loc of the GCN ansatz (complex ``[B]``)."""
-    fn = lambda c: logpsi(theta, c, n, edges, F, L, tied, formulation)
+    fn = lambda c: logpsi(theta, c, n, edges, F, L, tied, formulation, act=act)
     return local_energy_generic(fn, spins, edges, jz, jxy, hb=hb, cb=cb)
 
 
@@ -270,14 +303,14 @@ def isgo_stats(logpsi_old, logpsi_new, eloc, counts=None):
     return stats, cot
 
 
-def logpsi_vjp(theta, spins, cot, n, edges, F, L, tied=True, formulation="sparse"):
+def logpsi_vjp(theta, spins, cot, n, edges, F, L, tied=True, formulation="sparse", act_fn="tanh"):
     """``g = sum_x cot[x,0] d log|psi(s_x)|/dtheta + cot[x,1] d phase(s_x)/dtheta``.
 
     Hand-derived reverse pass of ``forward`` (layout of ``g`` = layout of theta).
     """
     p = unpack_theta(theta, F, L, tied)
     cot = np.asarray(cot, dtype=np.float64)
-    _, act = forward(theta, spins, n, edges, F, L, tied, formulation, keep=True)
+    _, act = forward(theta, spins, n, edges, F, L, tied, formulation, keep=True, act=act_fn)
     g = {k: np.zeros_like(v, dtype=np.float64) for k, v in p.items()}
     ca, cp = cot[:, 0], cot[:, 1]
     z = act["z"]
@@ -292,7 +325,7 @@ def logpsi_vjp(theta, spins, cot, n, edges, F, L, tied=True, formulation="sparse
     for l in reversed(range(L)):
         wi = 0 if tied else l
         Hin, Hout, M = act["H"][l], act["H"][l + 1], act["M"][l]
-        dP = dH * (1.0 - Hout ** 2)                        # tanh'
+        dP = activate_vjp(dH, Hout, act["aux"][l + 1], act_fn)
         X = np.concatenate([M, Hin], axis=-1)              # [B, N, 2F]
         g["W"][wi] += np.einsum("bnk,bnf->kf", X, dP)
         g["b"][wi] += dP.sum(axis=(0, 1))
@@ -302,8 +335,7 @@ def logpsi_vjp(theta, spins, cot, n, edges, F, L, tied=True, formulation="sparse
         # A_hat is symmetric, so the transpose product is A_hat @ dM again
         dMsum = np.asarray(Ahat @ dM.transpose(1, 0, 2).reshape(N_, B_ * F)).reshape(N_, B_, F).transpose(1, 0, 2)
         dH = dself + dMsum
-    H0 = act["H"][0]
-    dP0 = dH * (1.0 - H0 ** 2)
+    dP0 = activate_vjp(dH, act["H"][0], act["aux"][0], act_fn)
     g["W_e"] += np.einsum("bnc,bnf->cf", act["onehot"], dP0)
     g["b_e"] += dP0.sum(axis=(0, 1))
     return np.concatenate([np.atleast_1d(g[k]).ravel() for k in
@@ -311,18 +343,18 @@ def logpsi_vjp(theta, spins, cot, n, edges, F, L, tied=True, formulation="sparse
 
 
 def isgo_grad(theta, spins, logpsi_old, n, edges, F, L, tied=True, counts=None,
-              jz=1.0, jxy=1.0, formulation="sparse", hb=0.0, cb=0.0):
+              jz=1.0, jxy=1.0, formulation="sparse", hb=0.0, cb=0.0, act="tanh"):
     """One ISGO update's gradient (Eq. 3): new log psi, E_loc under the new psi,
     weights, then the reverse pass with the centred cotangents.
 
     Returns ``(grad, stats, eloc)``; ``stats`` also carries ``n_evals``.
     """
-    new = logpsi(theta, spins, n, edges, F, L, tied, formulation)
-    fn = lambda c: logpsi(theta, c, n, edges, F, L, tied, formulation)
+    new = logpsi(theta, spins, n, edges, F, L, tied, formulation, act=act)
+    fn = lambda c: logpsi(theta, c, n, edges, F, L, tied, formulation, act=act)
     E = local_energy_generic(fn, spins, edges, jz, jxy, base=new, hb=hb, cb=cb)
     stats, cot = isgo_stats(logpsi_old, new, E, counts)
     stats["n_evals"] = n_evals(spins, edges)
-    g = logpsi_vjp(theta, spins, cot, n, edges, F, L, tied, formulation)
+    g = logpsi_vjp(theta, spins, cot, n, edges, F, L, tied, formulation, act_fn=act)
     return g, stats, E
 
 
