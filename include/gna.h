@@ -83,6 +83,15 @@ enum { GNA_FP64 = 0, GNA_FP32 = 1, GNA_BF16 = 2 };
  *     Needs tied weights and n_layers >= 1.                                   */
 enum { GNA_ELOC_FULL = 0, GNA_ELOC_INCREMENTAL = 1 };
 
+/* The nonlinearity f of Eq. 1, applied after every layer and to the embedding:
+ *   GNA_ACT_TANH:    f = tanh.
+ *   GNA_ACT_RELU_LN: the paper's choice (Section 2): ReLU, then a layer
+ *                    normalisation over the F features of each node,
+ *                    (y - mean y) / sqrt(var y + 1e-5), biased variance, no
+ *                    affine parameters.  The row statistics are reduced in a
+ *                    fixed order, so incremental and full evaluations agree. */
+enum { GNA_ACT_TANH = 0, GNA_ACT_RELU_LN = 1 };
+
 typedef struct {
   int32_t n_sites;          /* N >= 2 */
   int32_t n_edges;          /* |E| >= 0 */
@@ -97,6 +106,8 @@ typedef struct {
   double jz, jxy;           /* Heisenberg couplings; the isotropic model is 1, 1 */
   int32_t max_batch;        /* largest B any call will pass (sizes the workspace) */
   int32_t eloc_mode;        /* GNA_ELOC_FULL or GNA_ELOC_INCREMENTAL (tied weights) */
+  int32_t activation;       /* f of Eq. 1: GNA_ACT_TANH or GNA_ACT_RELU_LN */
+  int32_t reserved;         /* must be 0 */
   int64_t act_budget_bytes; /* device bytes the reverse pass may use for stored
                                per-layer activations; 0 = library default.  The
                                reverse pass recomputes activations per sample, so

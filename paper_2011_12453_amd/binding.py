@@ -35,6 +35,7 @@ class _Config(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("jz", ctypes.c_double), ("jxy", ctypes.c_double),
         ("max_batch", ctypes.c_int32), ("eloc_mode", ctypes.c_int32),
+        ("activation", ctypes.c_int32), ("reserved", ctypes.c_int32),
         ("act_budget_bytes", ctypes.c_int64),
         ("stream", ctypes.c_void_p),
     ]
@@ -112,7 +113,7 @@ class GNA:
     def __init__(self, n_sites: int, edges, n_features: int, n_layers: int, tied: bool = True,
                  precision: str | int = "fp64", jz: float = 1.0, jxy: float = 1.0,
                  max_batch: int = 4096, act_budget_bytes: int = 0, device=None, stream=None,
-                 eloc_mode: str | int = "full"):
+                 eloc_mode: str | int = "full", activation: str | int = "tanh"):
         self._lib = load_library()
         self._ctx = None
         if not torch.cuda.is_available():
@@ -128,12 +129,14 @@ class GNA:
         self.max_batch = int(max_batch)
         mode = {"full": 0, "incremental": 1}[eloc_mode] if isinstance(eloc_mode, str) else int(eloc_mode)
         self.eloc_mode = mode
+        act = {"tanh": 0, "relu_ln": 1}[activation] if isinstance(activation, str) else int(activation)
+        self.activation = act
         with torch.cuda.device(self.device):
             st = torch.cuda.current_stream() if stream is None else stream
             self._stream = st
             cfg = _Config(self.n_sites, self.n_edges, e.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                           self.n_features, self.n_layers, int(self.tied), prec, float(jz), float(jxy),
-                          self.max_batch, mode, int(act_budget_bytes), ctypes.c_void_p(st.cuda_stream))
+                          self.max_batch, mode, act, 0, int(act_budget_bytes), ctypes.c_void_p(st.cuda_stream))
             out = ctypes.c_void_p()
             status = self._lib.gna_init(ctypes.byref(cfg), ctypes.byref(out))
         if status != 0:

@@ -40,8 +40,12 @@ namespace {
 //   wfrag[w][s][t][lane][j] = W[w][blk*F + kk][row_feature(16t + lane%16)],
 //   s < F/KS: message block (blk 0), else self block (blk 1);
 //   kk = KS*(s mod F/KS) + VEC*(lane/16) + j.
+//   act 0 (tanh): W and b are multiplied by P::kScale, the argument scaling that
+//   P::act expects; act 1 (ReLU + layer normalisation): unscaled.  The embedding
+//   rows are f(W_e[x] + b_e) in FP64, rounded once.
 template <class P, int F>
-__global__ void k_prepare(const double* __restrict__ theta, int nW, void* wfrag, void* bias, void* emb) {
+__global__ void k_prepare(const double* __restrict__ theta, int nW, int act, void* wfrag, void* bias,
+                          void* emb) {
   using WT = typename P::WT;
   using Acc = typename P::Acc;
   constexpr int KSB = F / P::KS, MT = F / 16, VEC = P::VEC;
@@ -52,6 +56,7 @@ __global__ void k_prepare(const double* __restrict__ theta, int nW, void* wfrag,
   WT* wf = reinterpret_cast<WT*>(wfrag);
   const int per_layer = 2 * F * F;
   const int total = nW * per_layer;
+  const double scale = act == 0 ? P::kScale : 1.0;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
     int r = e;
     const int j = r % VEC; r /= VEC;
@@ -63,13 +68,27 @@ __global__ void k_prepare(const double* __restrict__ theta, int nW, void* wfrag,
     const int kk = P::KS * ss + VEC * (lane / 16) + j;
     const int f = P::row_feature(16 * t + lane % 16);
     const double v = W[(size_t)w * per_layer + (size_t)(blk * F + kk) * F + f];
-    wf[e] = P::to_w(P::kScale * v);
+    wf[e] = P::to_w(scale * v);
   }
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid < nW * F) reinterpret_cast<Acc*>(bias)[tid] = (Acc)(P::kScale * b[tid]);
+  if (tid < nW * F) reinterpret_cast<Acc*>(bias)[tid] = (Acc)(scale * b[tid]);
   if (tid < 2 * F) {
     const int x = tid / F, f = tid % F;
-    reinterpret_cast<Acc*>(emb)[tid] = (Acc)tanh(We[x * F + f] + be[f]);
+    double h;
+    if (act == 0) {
+      h = tanh(We[x * F + f] + be[f]);
+    } else {
+      double mu = 0.0, var = 0.0;
+      for (int g = 0; g < F; ++g) mu += fmax(We[x * F + g] + be[g], 0.0);
+      mu /= F;
+      for (int g = 0; g < F; ++g) {
+        const double d = fmax(We[x * F + g] + be[g], 0.0) - mu;
+        var += d * d;
+      }
+      var /= F;
+      h = (fmax(We[x * F + f] + be[f], 0.0) - mu) / sqrt(var + kLnEps);
+    }
+    reinterpret_cast<Acc*>(emb)[tid] = (Acc)h;
   }
 }
 
@@ -366,7 +385,7 @@ struct Kern {  // kernels of one (precision, F, TPW, NCH) instantiation
   const void* logpsi = nullptr;
   const void* eloc = nullptr;
   const void* sweep = nullptr;
-  void (*prepare)(const double*, int, void*, void*, void*, hipStream_t) = nullptr;
+  void (*prepare)(const double*, int, int, void*, void*, void*, hipStream_t) = nullptr;
 };
 
 template <class P, int F, int TPW, int NCH>
@@ -375,10 +394,10 @@ Kern make_kern() {
   k.logpsi = reinterpret_cast<const void*>(&k_logpsi<P, F, TPW, NCH>);
   k.eloc = reinterpret_cast<const void*>(&k_eloc<P, F, TPW, NCH>);
   k.sweep = reinterpret_cast<const void*>(&k_sweep<P, F, TPW, NCH>);
-  k.prepare = [](const double* th, int nW, void* wf, void* bias, void* emb, hipStream_t st) {
+  k.prepare = [](const double* th, int nW, int act, void* wf, void* bias, void* emb, hipStream_t st) {
     const int total = nW * 2 * F * F;
     const int blocks = std::max(1, std::min(1024, (total + 255) / 256));
-    hipLaunchKernelGGL((k_prepare<P, F>), dim3(blocks), dim3(256), 0, st, th, nW, wf, bias, emb);
+    hipLaunchKernelGGL((k_prepare<P, F>), dim3(blocks), dim3(256), 0, st, th, nW, act, wf, bias, emb);
   };
   return k;
 }
@@ -559,6 +578,7 @@ struct gna_ctx {
   void* d_wbwd = nullptr;
   void* d_planes = nullptr;     // [vjp_chunk][nplanes][npad][F] Acc
   int vjp_chunk = 1, nplanes = 1;
+  int act = 0;                  // GNA_ACT_*
   double* d_vjp_part = nullptr; // [vjp_rows][P]
   std::vector<void*> owned;
   // kernel timing (gna_profile_enable)
@@ -643,7 +663,7 @@ gna_status check_launch(gna_ctx* c, const char* what) {
 
 gna_status prepare(gna_ctx* c, const double* theta) {
   Timed tm(c, "k_prepare");
-  c->kern.prepare(theta, c->tied ? 1 : c->L, c->d_wfrag, c->d_bias, c->d_emb, c->stream);
+  c->kern.prepare(theta, c->tied ? 1 : c->L, c->act, c->d_wfrag, c->d_bias, c->d_emb, c->stream);
   return check_launch(c, "k_prepare");
 }
 
@@ -654,6 +674,7 @@ Net make_net(gna_ctx* c, const double* theta) {
   n.F = c->F;
   n.L = c->L;
   n.tied = c->tied;
+  n.act = c->act;
   n.dmax = c->dmax;
   n.ell_idx = c->d_idx;
   n.ell_val = c->d_val;
@@ -766,7 +787,7 @@ gna_status run_vjp(gna_ctx* c, const double* theta, const int8_t* spins, int B, 
   if (B > 0) {
     {
       Timed tm(c, "k_prepare_vjp");
-      c->vk.fk.prepare(theta, nW, c->d_vwfrag, c->d_vbias, c->d_vemb, c->stream);
+      c->vk.fk.prepare(theta, nW, c->act, c->d_vwfrag, c->d_vbias, c->d_vemb, c->stream);
       c->vk.prepare_bwd(theta, nW, c->d_wbwd, c->stream);
     }
     if (gna_status st = check_launch(c, "k_prepare_vjp")) return st;
@@ -777,6 +798,7 @@ gna_status run_vjp(gna_ctx* c, const double* theta, const int8_t* spins, int B, 
     net.g = c->vgeo;
     VNet v{};
     v.n = c->N; v.F = F; v.L = L; v.tied = c->tied; v.dmax = c->dmax;
+    v.act = c->act;
     v.npad = c->vgeo.npad; v.ntiles = c->vgeo.ntiles; v.wpc = c->vgeo.wpc;
     v.ell_idx = c->d_idx; v.ell_val = c->d_val; v.wbwd = c->d_wbwd; v.theta = theta;
     v.npar = (int)c->P;
@@ -964,6 +986,9 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
   if (cfg->precision < GNA_FP64 || cfg->precision > GNA_BF16) return init_fail(GNA_INVALID_ARG, "unknown precision");
   if (cfg->eloc_mode != GNA_ELOC_FULL && cfg->eloc_mode != GNA_ELOC_INCREMENTAL)
     return init_fail(GNA_INVALID_ARG, "unknown eloc_mode");
+  if (cfg->activation != GNA_ACT_TANH && cfg->activation != GNA_ACT_RELU_LN)
+    return init_fail(GNA_INVALID_ARG, "unknown activation");
+  if (cfg->reserved != 0) return init_fail(GNA_INVALID_ARG, "reserved must be 0");
   if (cfg->eloc_mode == GNA_ELOC_INCREMENTAL && !cfg->tied)
     return init_fail(GNA_UNSUPPORTED, "incremental local energy needs tied weights");
   if (cfg->eloc_mode == GNA_ELOC_INCREMENTAL && L < 1)
@@ -990,6 +1015,7 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
 
   gna_ctx* c = new gna_ctx();
   c->N = N; c->E = E; c->F = F; c->L = L; c->tied = cfg->tied; c->prec = cfg->precision;
+  c->act = cfg->activation;
   c->jz = cfg->jz; c->jxy = cfg->jxy; c->max_batch = cfg->max_batch;
   c->stream = reinterpret_cast<hipStream_t>(cfg->stream);
   c->P = param_count(F, L, cfg->tied);
@@ -1163,7 +1189,7 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
     c->vgrid_fwd = c->n_cu * vocc(c->vk.fwd, c->vgeo.lds_bytes);
     c->vgrid_dx = c->n_cu * vocc(c->vk.dx, (int)vw_bytes);
     c->vjp_rows = 2 * c->n_cu;
-    c->nplanes = 2 * L + 5;
+    c->nplanes = 2 * L + 5 + (c->act ? L : 0);   // + post-ReLU rows Y^1..Y^L
     const int64_t per_sample = (int64_t)c->nplanes * c->vgeo.npad * F * (int64_t)c->sz_Acc;
     const int64_t budget = cfg->act_budget_bytes ? cfg->act_budget_bytes : ((int64_t)16 << 30);
     int64_t chunk = std::max<int64_t>(1, budget / std::max<int64_t>(per_sample, 1));

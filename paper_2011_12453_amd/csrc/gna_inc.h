@@ -349,10 +349,19 @@ __device__ void inc_group(const Net& net, const IncNet& inc, const IncGeo& ig, c
           }
         }
       }
+      if (net.act == 0) {
 #pragma unroll
-      for (int t = 0; t < MT; ++t)
+        for (int t = 0; t < MT; ++t)
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) hn[k][4 * t + rr] = P::act(acc[k][t][rr] + m[4 * t + rr]);
+          for (int rr = 0; rr < 4; ++rr) hn[k][4 * t + rr] = P::act(acc[k][t][rr] + m[4 * t + rr]);
+      } else {   // the four lanes of a row are active together (tok is wave-uniform)
+        Acc pre[NS], y[NS];
+#pragma unroll
+        for (int t = 0; t < MT; ++t)
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) pre[4 * t + rr] = acc[k][t][rr] + m[4 * t + rr];
+        relu_ln_row<Acc, NS>(pre, y, hn[k]);
+      }
       if (last && (rd || WRITE)) {   // wave-uniform
         // readout partials of this node, formed as in the full evaluation
         Acc va[NS], vp[NS];

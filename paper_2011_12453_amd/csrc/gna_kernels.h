@@ -226,6 +226,7 @@ struct Geo {
 
 struct Net {
   int n, ne, F, L, tied, dmax;
+  int act;                 // 0: tanh (weights pre-scaled by kScale); 1: ReLU + layer normalisation (unscaled)
   const int* ell_idx;      // [npad][dmax] neighbour ids (padding points at the node itself)
   const void* ell_val;     // [npad][dmax] A_hat values in Acc precision (padding 0)
   const int2* edges;       // [ne] bond endpoints
@@ -266,6 +267,68 @@ __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
+}
+
+// ---------------------------------------------------------------------------
+// ReLU followed by a layer normalisation over a node's F features (the paper's f,
+// Section 2).  The node's features sit in the 4 lanes q = 0..3 of its column (NS
+// slots each); row sums go through a fixed butterfly (lane xor 16, then xor 32),
+// so all four lanes, and every evaluation of the same row, get identical values.
+// ---------------------------------------------------------------------------
+constexpr double kLnEps = 1e-5;
+
+template <class Acc>
+__device__ __forceinline__ Acc quad_sum(Acc v) {
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+// y = ReLU(x); mean and inverse standard deviation of y over the row
+template <class Acc, int NS>
+__device__ __forceinline__ void relu_ln_stats(const Acc (&x)[NS], Acc (&y)[NS], Acc& mu, Acc& r) {
+  constexpr int F = 4 * NS;
+  Acc s = 0;
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    y[i] = x[i] > (Acc)0 ? x[i] : (Acc)0;
+    s += y[i];
+  }
+  mu = quad_sum(s) / (Acc)F;
+  Acc v = 0;
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    const Acc d = y[i] - mu;
+    v += d * d;
+  }
+  r = (Acc)1 / sqrt(quad_sum(v) / (Acc)F + (Acc)kLnEps);
+}
+
+template <class Acc, int NS>
+__device__ __forceinline__ void relu_ln_row(const Acc (&x)[NS], Acc (&y)[NS], Acc (&h)[NS]) {
+  Acc mu, r;
+  relu_ln_stats<Acc, NS>(x, y, mu, r);
+#pragma unroll
+  for (int i = 0; i < NS; ++i) h[i] = (y[i] - mu) * r;
+}
+
+// cotangent of the pre-activation from that of h = LN(ReLU(x)), given y = ReLU(x)
+// and h: dy = r (dh - mean dh - h mean(dh h)), dx = dy [y > 0]
+template <class Acc, int NS>
+__device__ __forceinline__ void relu_ln_vjp(const Acc (&y)[NS], const Acc (&h)[NS], const Acc (&dh)[NS],
+                                            Acc (&dx)[NS]) {
+  constexpr int F = 4 * NS;
+  Acc yy[NS], mu, r;
+  relu_ln_stats<Acc, NS>(y, yy, mu, r);   // ReLU of y is y
+  Acc a = 0, b = 0;
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    a += dh[i];
+    b += dh[i] * h[i];
+  }
+  const Acc ma = quad_sum(a) / (Acc)F, mb = quad_sum(b) / (Acc)F;
+#pragma unroll
+  for (int i = 0; i < NS; ++i) dx[i] = y[i] > (Acc)0 ? r * (dh[i] - ma - h[i] * mb) : (Acc)0;
 }
 
 // vectorised LDS copy of N elements of T (alignment 16 B or of the chunk size)
@@ -423,7 +486,8 @@ __device__ void load_spins(const Net& net, const Smem<P>& s, const int8_t* __res
 //   STORE == 1: also write the layer inputs H^0..H^L and messages M^0..M^{L-1}
 //   (M^l = A_hat H^l, gathered for the reverse pass) to `store` as planes of
 //   npad x F values, element (node, q, i) at node * F + q * F/4 + i (slot
-//   order); H^l is plane l, M^l plane L + 1 + l.
+//   order); H^l is plane l, M^l plane L + 1 + l; with ReLU + layer normalisation
+//   also the post-ReLU rows Y^l (l = 1..L) as planes 2L + 4 + l.
 //   STORE == 2: write the base planes of the incremental local energy: layer
 //   outputs H^1..H^{L-1} as planes 0..L-2, the layer-L readout partials (per
 //   node and lane quad q, the pair (t_a, t_p) of Acc sums v . H^L over the
@@ -654,16 +718,36 @@ __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
       // readout partial of this node in Acc: identical inputs give identical
       // partials, so unchanged nodes still cancel exactly in log psi differences
       Acc ta = 0, tp = 0;
+      if (net.act == 0) {
 #pragma unroll
-      for (int t = 0; t < MT; ++t) {
+        for (int t = 0; t < MT; ++t) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const Acc v = P::act(acc[k][t][r]);
-          h[k][4 * t + r] = v;
-          if (last) {
-            const int f = P::lc(q, 4 * t + r);
-            ta += (Acc)head_a[f] * v;
-            tp += (Acc)head_p[f] * v;
+          for (int r = 0; r < 4; ++r) {
+            const Acc v = P::act(acc[k][t][r]);
+            h[k][4 * t + r] = v;
+            if (last) {
+              const int f = P::lc(q, 4 * t + r);
+              ta += (Acc)head_a[f] * v;
+              tp += (Acc)head_p[f] * v;
+            }
+          }
+        }
+      } else {
+        Acc pre[NS], y[NS];
+#pragma unroll
+        for (int t = 0; t < MT; ++t)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) pre[4 * t + r] = acc[k][t][r];
+        relu_ln_row<Acc, NS>(pre, y, h[k]);
+        if constexpr (STORE == 1) {
+          if (tile_ok[k]) lds_write<Acc, NS>(store + (2 * net.L + 5 + l) * plane + node[k] * F + q * NS, y);
+        }
+        if (last) {
+#pragma unroll
+          for (int i = 0; i < NS; ++i) {
+            const int f = P::lc(q, i);
+            ta += (Acc)head_a[f] * h[k][i];
+            tp += (Acc)head_p[f] * h[k][i];
           }
         }
       }

@@ -3,8 +3,8 @@
 // For a chunk of samples the forward pass is recomputed once and its per-layer
 // inputs H^l and messages M^l are kept as planes (npad x F, slot order, see
 // eval_config).  Then, layer by layer from the top, with P = [M | H] W + b and
-// H' = tanh(P):
-//   dP   = dH' * (1 - H'^2)
+// H' = f(P):
+//   dP   = dH' * (1 - H'^2)         (tanh; ReLU + layer normalisation: its VJP)
 //   dW  += [M | H]^T dP           (k_vjp_dw: rows of all samples are the
 //   db  += sum_rows dP             MFMA reduction dimension)
 //   dX   = dP W^T                  (k_vjp_dx: per sample, same register layout
@@ -20,19 +20,23 @@ namespace gna {
 
 struct VNet {
   int n, F, L, tied, dmax, npad, ntiles, wpc;
+  int act;               // 0: tanh, 1: ReLU + layer normalisation
   const int* ell_idx;    // [npad][dmax]
   const void* ell_val;   // [npad][dmax], Acc
   const void* wbwd;      // [nW][2F/16][F/4][64] fragments of W (not transposed), Acc
   const double* theta;   // FP64 parameters (heads are read from here)
   int npar;
   size_t plane;          // npad * F
-  int nplanes;           // planes per sample: 2L+1 forward + dP + dXm + dH(2)
+  int nplanes;           // planes per sample: 2L+1 forward + dP + dXm + dH(2) [+ Y^1..Y^L]
 };
 
-// planes of one sample: 0..L = H^l, L+1..2L = M^l, then dP, dXm, dH0, dH1
+// planes of one sample: 0..L = H^l, L+1..2L = M^l, then dP, dXm, dH0, dH1 and,
+// with ReLU + layer normalisation, Y^1..Y^L
 __device__ __forceinline__ int plane_dP(const VNet& v) { return 2 * v.L + 1; }
 __device__ __forceinline__ int plane_dXm(const VNet& v) { return 2 * v.L + 2; }
 __device__ __forceinline__ int plane_dH(const VNet& v, int which) { return 2 * v.L + 3 + (which & 1); }
+// post-ReLU rows Y^l (l = 1..L) of ReLU + layer normalisation
+__device__ __forceinline__ int plane_Y(const VNet& v, int l) { return 2 * v.L + 4 + l; }
 
 // Build the backward fragments: A[m = input feature][kd = output feature] = W,
 // fragment (w, tm, s, lane) = W[part*F + row_feature(16 (tm mod F/16) + lane%16)][4s + lane/16]
@@ -124,8 +128,16 @@ __global__ __launch_bounds__(512) void k_vjp_dx(VNet v, int layer, int b0, int B
       } else {
         lds_read<Acc, NS>(dHin + off, dh);
       }
+      if (v.act == 0) {
 #pragma unroll
-      for (int i = 0; i < NS; ++i) dp[i] = real ? dh[i] * ((Acc)1 - hn[i] * hn[i]) : (Acc)0;
+        for (int i = 0; i < NS; ++i) dp[i] = real ? dh[i] * ((Acc)1 - hn[i] * hn[i]) : (Acc)0;
+      } else {   // tile is wave-uniform: the four lanes of a row are active together
+        Acc y[NS];
+        lds_read<Acc, NS>(pb + (size_t)plane_Y(v, layer + 1) * v.plane + off, y);
+        relu_ln_vjp<Acc, NS>(y, hn, dh, dp);
+#pragma unroll
+        for (int i = 0; i < NS; ++i) dp[i] = real ? dp[i] : (Acc)0;
+      }
       lds_write<Acc, NS>(dPp + off, dp);
       CF dx[2 * MT];
 #pragma unroll
@@ -281,8 +293,14 @@ __global__ __launch_bounds__(256) void k_vjp_tail(VNet v, int b0, int Bc, const 
     double z = 0;
     for (int node = rs; node < v.n; node += nrs) {
       const size_t o = (size_t)node * F + p;
-      const double h0 = (double)H0[o];
-      const double dp0 = (v.L > 0 ? (double)dH0[o] : dz) * (1.0 - h0 * h0);
+      const double dh0 = v.L > 0 ? (double)dH0[o] : dz;
+      double dp0;
+      if (v.act == 0) {
+        const double h0 = (double)H0[o];
+        dp0 = dh0 * (1.0 - h0 * h0);
+      } else {   // the embedding row depends on the spin only: its VJP is applied to the sums
+        dp0 = dh0;
+      }
       if (sb[node] > 0) e1 += dp0; else e0 += dp0;
       z += (double)HL[o];
     }
@@ -290,20 +308,53 @@ __global__ __launch_bounds__(256) void k_vjp_tail(VNet v, int b0, int Bc, const 
     zp += cp * z;
   }
   __shared__ double red[4][256];
+  __shared__ double sdh[2][F];   // summed dH^0 per spin value, logical order
   red[0][threadIdx.x] = e0;
   red[1][threadIdx.x] = e1;
   red[2][threadIdx.x] = za;
   red[3][threadIdx.x] = zp;
   __syncthreads();
+  double s0 = 0, s1 = 0, sa = 0, sp = 0;
+  const int f = P::lc(p / NS, p % NS);
   if (threadIdx.x < F) {
-    double s0 = 0, s1 = 0, sa = 0, sp = 0;
     for (int r = 0; r < nrs; ++r) {
       s0 += red[0][r * F + p];
       s1 += red[1][r * F + p];
       sa += red[2][r * F + p];
       sp += red[3][r * F + p];
     }
-    const int f = P::lc(p / NS, p % NS);
+    sdh[0][f] = s0;
+    sdh[1][f] = s1;
+  }
+  __syncthreads();
+  if (v.act != 0 && threadIdx.x < F) {
+    // VJP of h = LN(ReLU(u)), u = W_e[x] + b_e, in FP64 from theta, for x = 0, 1
+    const double* We = v.theta;
+    const double* be = v.theta + 2 * F;
+    double dx[2];
+    for (int x = 0; x < 2; ++x) {
+      double mu = 0.0, var = 0.0;
+      for (int g = 0; g < F; ++g) mu += fmax(We[x * F + g] + be[g], 0.0);
+      mu /= F;
+      for (int g = 0; g < F; ++g) {
+        const double d = fmax(We[x * F + g] + be[g], 0.0) - mu;
+        var += d * d;
+      }
+      const double r = 1.0 / sqrt(var / F + kLnEps);
+      double a = 0.0, b = 0.0;
+      for (int g = 0; g < F; ++g) {
+        const double hg = (fmax(We[x * F + g] + be[g], 0.0) - mu) * r;
+        a += sdh[x][g];
+        b += sdh[x][g] * hg;
+      }
+      const double u = We[x * F + f] + be[f];
+      const double hf = (fmax(u, 0.0) - mu) * r;
+      dx[x] = u > 0.0 ? r * (sdh[x][f] - a / F - hf * b / F) : 0.0;
+    }
+    s0 = dx[0];
+    s1 = dx[1];
+  }
+  if (threadIdx.x < F) {
     const int nW = v.tied ? 1 : v.L;
     double* g = part + (size_t)blockIdx.x * v.npar;
     g[f] += s0;             // W_e[0][f]

@@ -36,9 +36,9 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_config_struct_matches_header_layout():
     from paper_2011_12453_amd.binding import _Config
-    # int32 x2, ptr, int32 x4, double x2, int32 x2, int64, ptr: no implicit padding
-    assert ctypes.sizeof(_Config) == 4 * 2 + 8 + 4 * 4 + 8 * 2 + 4 * 2 + 8 + 8
-    assert _Config.jz.offset == 32 and _Config.stream.offset == 64
+    # int32 x2, ptr, int32 x4, double x2, int32 x4, int64, ptr: no implicit padding
+    assert ctypes.sizeof(_Config) == 4 * 2 + 8 + 4 * 4 + 8 * 2 + 4 * 4 + 8 + 8
+    assert _Config.jz.offset == 32 and _Config.activation.offset == 56 and _Config.stream.offset == 72
 
 
 def _cfg(**kw):
@@ -47,7 +47,7 @@ def _cfg(**kw):
     n, e = w.kagome(2, 2)
     e = np.ascontiguousarray(kw.pop("edges", e), dtype=np.int32)
     base = dict(n_sites=n, n_edges=len(e), n_features=16, n_layers=2, tied=1, precision=0,
-                jz=1.0, jxy=1.0, max_batch=16, eloc_mode=0, act_budget_bytes=0)
+                jz=1.0, jxy=1.0, max_batch=16, eloc_mode=0, activation=0, reserved=0, act_budget_bytes=0)
     base.update(kw)
     c = _Config()
     for k, v in base.items():
@@ -60,7 +60,7 @@ def _cfg(**kw):
 @pytest.mark.parametrize("field,value,status", [
     ("n_sites", 1, 1), ("n_features", 24, 3), ("n_layers", -1, 3), ("n_layers", 17, 3),
     ("precision", 7, 1), ("tied", 2, 1), ("eloc_mode", 2, 1), ("max_batch", -1, 1),
-    ("jz", float("nan"), 1),
+    ("jz", float("nan"), 1), ("activation", 2, 1), ("reserved", 1, 1),
 ])
 def test_bad_config_rejected_before_device(lib, field, value, status):
     c, keep = _cfg(**{field: value})
