@@ -109,6 +109,11 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline steps only (for profilers)")
     ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay timing")
     ap.add_argument("--no-tune", action="store_true", help="keep the default incremental shape")
+    ap.add_argument("--shape", default=None, metavar="J,W,X",
+                    help="pin the incremental local-energy kernel's shape (jobs in flight, waves, "
+                         "samples per XCD) instead of tuning")
+    ap.add_argument("--sweep-shape", default=None, metavar="J,W",
+                    help="pin the incremental sweep kernel's shape (jobs in flight, waves)")
     ap.add_argument("--graph-reps", type=int, default=20, help="timed graph replays per component")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of this many MiB (counter calibration)")
@@ -174,7 +179,15 @@ def main():
         return stats
 
     tuned = None
-    if args.eloc_mode == "incremental" and not args.no_tune:
+    if args.shape or args.sweep_shape:
+        if args.shape:
+            j, wv, x = (int(v) for v in args.shape.split(","))
+            g.set_shape(j, wv, x, which="eloc")
+        if args.sweep_shape:
+            j, wv = (int(v) for v in args.sweep_shape.split(","))
+            g.set_shape(j, wv, 1, which="sweep")
+        log(f"[bench] pinned shape: {g.config_info()}")
+    elif args.eloc_mode == "incremental" and not args.no_tune:
         # the tuner times the incremental kernels' shapes on this batch (before any timing)
         tuned = g.autotune(theta, spins)
         log(f"[bench] autotune: {tuned}")

@@ -57,7 +57,7 @@ enum {
   GNA_INVALID_ARG = 1,   /* bad pointer, size, batch above max_batch, ... */
   GNA_BAD_GRAPH = 2,     /* endpoint out of range, self-loop, repeated bond */
   GNA_UNSUPPORTED = 3,   /* shape outside what the kernels are built for */
-  GNA_OUT_OF_MEMORY = 4, /* workspace allocation failed in gna_init */
+  GNA_OUT_OF_MEMORY = 4, /* workspace allocation failed (gna_init, gna_autotune) */
   GNA_HIP_ERROR = 5      /* a HIP runtime call or kernel launch failed */
 };
 
@@ -191,18 +191,37 @@ gna_status gna_set_couplings(gna_ctx *ctx, double jz, double jxy, double hb, dou
 /* Tile and workgroup shapes of the incremental kernels chosen by measurement:
  * times gna_local_energy on (theta, spins[B]) for the candidate shapes (jobs in
  * flight per workgroup, 8 or 16 waves, one or two samples in flight per XCD),
- * keeps the fastest for this context and for every later context of the same
- * signature (N, n_edges, degree histogram, F, L, precision) in this process.
- * Unlike the compute calls it synchronises the context's stream; call it after
- * gna_init, outside any graph capture.  chosen [4] (host, may be NULL): jobs in
- * flight, waves, samples per XCD, microseconds per local-energy call.  In
- * GNA_ELOC_FULL mode there is nothing to tune: returns GNA_OK, chosen zeros.   */
+ * then one Metropolis sweep of a copy of the batch (spins is not modified) for
+ * the same candidates; each kernel keeps its fastest shape, for this context and
+ * for every later context of the same signature (N, n_edges, degree histogram,
+ * F, L, precision) in this process.  Unlike the compute calls it synchronises
+ * the context's stream and allocates a temporary copy of the batch (B*N bytes
+ * plus 12*B) for the call: call it after gna_init, outside any graph capture.
+ * chosen [8] (host, may be NULL): local energy jobs in flight, waves, samples per
+ * XCD, microseconds per call; sweep jobs in flight, waves, tiles per wave,
+ * microseconds per one-sweep call.  In GNA_ELOC_FULL mode there is nothing to
+ * tune: returns GNA_OK, chosen zeros.  OUT_OF_MEMORY if the copy cannot be had.  */
 gna_status gna_autotune(gna_ctx *ctx, const double *theta, const int8_t *spins, int32_t B,
                         int32_t *chosen);
 
-/* Shape in use (host array, n entries at most 8): eloc_mode, jobs in flight,
- * waves per workgroup, tiles per wave, samples per XCD, precision, F, L.
- * Returns 8, or -1 for a NULL context.                                       */
+/* Pin the shape of the incremental kernels instead of measuring it (a shape
+ * reported by gna_autotune or gna_config_info earlier, or one to profile).
+ * which: 1 the local-energy kernel, 2 the sweep kernel, 3 both.  jobs_in_flight
+ * in [1, 8] exchanged configurations per workgroup; waves 16 (one tile each) or
+ * 1..8 (up to four tiles each), capped at the jobs' tile count (16-node tiles of
+ * the largest L-hop ball); samples_per_xcd in [1, 8] (local energy only).
+ * Results do not depend on the shape beyond the order of the final FP64 sums.
+ * INVALID_ARG outside those ranges or in GNA_ELOC_FULL mode; UNSUPPORTED when the
+ * shape does not fit in LDS or needs more than four tiles per wave; on error the
+ * previous shapes stay.  Host-side; applies to every later call.              */
+gna_status gna_set_shape(gna_ctx *ctx, int32_t which, int32_t jobs_in_flight, int32_t waves,
+                         int32_t samples_per_xcd);
+
+/* Shape in use (host array, n entries at most 11): eloc_mode, jobs in flight,
+ * waves per workgroup, tiles per wave, samples per XCD, precision, F, L, then the
+ * sweep kernel's jobs in flight, waves and tiles per wave (in GNA_ELOC_FULL mode
+ * the full evaluator's waves and tiles per wave).  Returns 11, or -1 for a NULL
+ * context.                                                                   */
 int32_t gna_config_info(const gna_ctx *ctx, int32_t *info, int32_t n);
 
 /* Reverse pass: grad[P] = sum_x cot[x][0] d log|psi(s_x)|/dtheta

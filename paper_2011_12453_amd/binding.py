@@ -67,6 +67,8 @@ _EXPORTS = {
     "gna_autotune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                       ctypes.POINTER(ctypes.c_int32)]),
     "gna_config_info": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]),
+    "gna_set_shape": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_int32]),
     "gna_set_couplings": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                            ctypes.c_double]),
     "gna_profile_enable": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
@@ -251,17 +253,25 @@ class GNA:
         """Measure the incremental kernels' shapes on this batch and keep the fastest
         (``gna_autotune``; synchronises).  Returns the choice."""
         theta, spins = self._theta(theta), self._spins(spins)
-        out = (ctypes.c_int32 * 4)()
+        out = (ctypes.c_int32 * 8)()
         self._check(self._lib.gna_autotune(self._ctx, _ptr(theta), _ptr(spins), spins.shape[0], out))
-        return {"jobs_in_flight": out[0], "waves": out[1], "samples_per_xcd": out[2], "us_per_call": out[3]}
+        return {"jobs_in_flight": out[0], "waves": out[1], "samples_per_xcd": out[2], "us_per_call": out[3],
+                "sweep_jobs_in_flight": out[4], "sweep_waves": out[5], "sweep_tiles_per_wave": out[6],
+                "sweep_us_per_call": out[7]}
+
+    def set_shape(self, jobs_in_flight: int, waves: int, samples_per_xcd: int = 2, which: str = "both"):
+        """Pin the incremental kernels' shape (``gna_set_shape``); which: "eloc",
+        "sweep" or "both"."""
+        w = {"eloc": 1, "sweep": 2, "both": 3}[which]
+        self._check(self._lib.gna_set_shape(self._ctx, w, int(jobs_in_flight), int(waves), int(samples_per_xcd)))
 
     def config_info(self) -> dict:
         """Shape in use (``gna_config_info``)."""
-        v = (ctypes.c_int32 * 8)()
-        if self._lib.gna_config_info(self._ctx, v, 8) != 8:
+        v = (ctypes.c_int32 * 11)()
+        if self._lib.gna_config_info(self._ctx, v, 11) != 11:
             raise GnaError(1, "gna_config_info failed")
         keys = ("eloc_mode", "jobs_in_flight", "waves", "tiles_per_wave", "samples_per_xcd", "precision",
-                "features", "layers")
+                "features", "layers", "sweep_jobs_in_flight", "sweep_waves", "sweep_tiles_per_wave")
         return dict(zip(keys, list(v)))
 
     def set_couplings(self, jz: float, jxy: float, hb: float = 0.0, cb: float = 0.0):

@@ -559,6 +559,9 @@ struct gna_ctx {
   IncKern ik{};
   int grid_inc_base = 1, grid_inc = 1, grid_sweep_inc = 1, inc_r8 = 8, inc_chunk_cap = 64;
   bool inc_wide = false;   // 16-wave incremental kernels
+  IncGeo igeo_sw{};        // shape of the incremental sweep kernel (tuned on its own)
+  bool inc_sw_wide = false;
+  int inc_sw_maxt = 1;
   int inc_per_xcd = 2;     // samples in flight per XCD (local energy work items)
   int inc_maxt = 1;        // tiles per wave
   int inc_max_rows = 2, inc_max_ball = 2, inc_max_tiles = 1;
@@ -862,10 +865,14 @@ struct IncShape {
   int nw = 0;   // waves per workgroup; 0: as many as useful (8, or 16 when wide)
 };
 
-std::mutex g_tune_mu;
-std::vector<std::pair<std::string, IncShape>> g_tune;   // tuner cache (this process)
+struct IncTune {
+  IncShape el, sw;   // local-energy and sweep kernel shapes
+};
 
-bool tune_lookup(const std::string& key, IncShape* out) {
+std::mutex g_tune_mu;
+std::vector<std::pair<std::string, IncTune>> g_tune;   // tuner cache (this process)
+
+bool tune_lookup(const std::string& key, IncTune* out) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   for (auto& kv : g_tune)
     if (kv.first == key) {
@@ -875,7 +882,7 @@ bool tune_lookup(const std::string& key, IncShape* out) {
   return false;
 }
 
-void tune_store(const std::string& key, const IncShape& v) {
+void tune_store(const std::string& key, const IncTune& v) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   for (auto& kv : g_tune)
     if (kv.first == key) {
@@ -885,7 +892,8 @@ void tune_store(const std::string& key, const IncShape& v) {
   g_tune.push_back({key, v});
 }
 
-gna_status inc_configure(gna_ctx* c, IncShape shp) {
+// which: 1 the local-energy kernel, 2 the sweep kernel, 3 both
+gna_status inc_configure(gna_ctx* c, IncShape shp, int which) {
   const int F = c->F, N = c->N, dmax = c->dmax;
   const int max_rows = c->inc_max_rows, max_ball = c->inc_max_ball, max_tiles = c->inc_max_tiles;
   IncGeo base{};
@@ -930,7 +938,8 @@ gna_status inc_configure(gna_ctx* c, IncShape shp) {
   } else if (shp.S >= 1 && shp.S <= kIncMaxSwaps) {
     geometry(shp.S, shp.wide, shp.nw, &ig, &maxt);
   }
-  if (maxt == 0) return fail(c, GNA_UNSUPPORTED, "incremental local energy does not fit in LDS");
+  if (maxt == 0)
+    return fail(c, GNA_UNSUPPORTED, "incremental kernel shape does not fit (LDS, or more than 4 tiles per wave)");
   const int tpw = c->tpw, nch = c->nch;
   IncKern ik;
   switch (c->prec) {
@@ -948,15 +957,24 @@ gna_status inc_configure(gna_ctx* c, IncShape shp) {
     (void)hipGetLastError();
     return nb;
   };
-  c->igeo = ig;
-  c->ik = ik;
-  c->inc_wide = shp.wide;
-  c->inc_maxt = maxt;
-  c->inc_per_xcd = std::max(1, shp.per_xcd);
-  c->inc_chunk_cap = std::min(chunk_cap, 64 * ig.nw);
+  c->ik.base = ik.base;   // the base pass does not depend on the shape
   c->grid_inc_base = c->n_cu * occ2(ik.base, 64 * c->geo.wpc, c->geo.lds_bytes);
-  c->grid_inc = c->n_cu * occ2(ik.eloc, 64 * ig.nw, ig.lds_bytes);
-  c->grid_sweep_inc = c->n_cu * occ2(ik.sweep, 64 * ig.nw, ig.lds_bytes);
+  if (which & 1) {
+    c->igeo = ig;
+    c->ik.eloc = ik.eloc;
+    c->inc_wide = shp.wide;
+    c->inc_maxt = maxt;
+    c->inc_per_xcd = std::max(1, shp.per_xcd);
+    c->inc_chunk_cap = std::min(chunk_cap, 64 * ig.nw);
+    c->grid_inc = c->n_cu * occ2(ik.eloc, 64 * ig.nw, ig.lds_bytes);
+  }
+  if (which & 2) {
+    c->igeo_sw = ig;
+    c->ik.sweep = ik.sweep;
+    c->inc_sw_wide = shp.wide;
+    c->inc_sw_maxt = maxt;
+    c->grid_sweep_inc = c->n_cu * occ2(ik.sweep, 64 * ig.nw, ig.lds_bytes);
+  }
   return GNA_OK;
 }
 
@@ -1284,11 +1302,12 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
       k += "/" + std::to_string(F) + "/" + std::to_string(L) + "/" + std::to_string(c->prec);
       c->tune_key = k;
     }
-    int s_cap = kIncMaxSwaps;
-    if (const char* ev = std::getenv("GNA_INC_MAX_SWAPS")) s_cap = std::max(1, std::min(kIncMaxSwaps, std::atoi(ev)));
-    IncShape shp{0, false, 2};
-    if (!tune_lookup(c->tune_key, &shp)) shp.S = -s_cap;   // default: the largest S <= s_cap that fits
-    if ((st = inc_configure(c, shp)) != GNA_OK) return bail(st, c->err);
+    // default: the largest S that fits, 8 waves; a shape tuned earlier in this
+    // process for the same signature wins
+    IncTune tt{IncShape{-kIncMaxSwaps, false, 2}, IncShape{-kIncMaxSwaps, false, 2}};
+    (void)tune_lookup(c->tune_key, &tt);
+    if ((st = inc_configure(c, tt.el, 1)) != GNA_OK || (st = inc_configure(c, tt.sw, 2)) != GNA_OK)
+      return bail(st, c->err);
     const size_t plane_bytes = (size_t)g.npad * F * c->sz_Acc;
     if ((st = dev_alloc(c, &c->d_ball_meta, meta.size() * 8)) ||
         (st = dev_alloc(c, &c->d_ball_cnt, cnt.size() * 4)) ||
@@ -1389,7 +1408,7 @@ static gna_status run_sweep(gna_ctx* c, const double* theta, int8_t* spins, doub
     }
     if (gna_status st = check_launch(c, "k_inc_base")) return st;
     IncNet inc = make_inc(c);
-    IncGeo ig = c->igeo;
+    IncGeo ig = c->igeo_sw;
     const int grid_s = std::max(1, std::min(c->grid_sweep_inc, (B + ig.S - 1) / ig.S));
     int Bv = B, ns = n_sweeps;
     unsigned long long sd = seed, cb = counter_base;
@@ -1493,16 +1512,18 @@ gna_status gna_autotune(gna_ctx* c, const double* theta, const int8_t* spins, in
   if (B < 1) return fail(c, GNA_INVALID_ARG, "autotune needs B >= 1");
   if (!valid_ptr(theta) || !valid_ptr(spins)) return fail(c, GNA_INVALID_ARG, "NULL pointer argument");
   if (c->eloc_mode != GNA_ELOC_INCREMENTAL) {   // the full evaluator's shape is fixed at init
-    if (chosen) chosen[0] = chosen[1] = chosen[2] = chosen[3] = 0;
+    if (chosen)
+      for (int k = 0; k < 8; ++k) chosen[k] = 0;
     return GNA_OK;
   }
   if (gna_status st = prepare(c, theta)) return st;
   const IncShape before{c->igeo.S, c->inc_wide, c->inc_per_xcd, c->igeo.nw};
+  const IncShape before_sw{c->igeo_sw.S, c->inc_sw_wide, 1, c->igeo_sw.nw};
   // candidates: the four largest S that fit, both wave shapes, one or two samples per XCD
   std::vector<IncShape> cand;
   int smax = 0;
   for (int S = kIncMaxSwaps; S >= 1 && !smax; --S)
-    if (inc_configure(c, IncShape{S, false, 2}) == GNA_OK) smax = S;
+    if (inc_configure(c, IncShape{S, false, 2}, 1) == GNA_OK) smax = S;
   for (int S = smax; S >= 1 && S > smax - 4; --S)
     for (int px = 1; px <= 2; ++px) {
       cand.push_back(IncShape{S, true, px, 0});
@@ -1512,54 +1533,123 @@ gna_status gna_autotune(gna_ctx* c, const double* theta, const int8_t* spins, in
         if (nw == kMaxWaves / 2 || (tiles + nw - 1) / nw == (tiles + kMaxWaves / 2 - 1) / (kMaxWaves / 2))
           cand.push_back(IncShape{S, false, px, nw});
     }
-  hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+  // the sweep runs on a copy of the batch (it moves the chains); these buffers live
+  // for the call only
+  int8_t* tsp = nullptr;
+  double* tlp = nullptr;
+  int32_t* tacc = nullptr;
+  if (hipMalloc(&tsp, (size_t)B * c->N) != hipSuccess || hipMalloc(&tlp, (size_t)B * 2 * sizeof(double)) != hipSuccess ||
+      hipMalloc(&tacc, (size_t)B * sizeof(int32_t)) != hipSuccess) {
+    (void)hipFree(tsp);
+    (void)hipFree(tlp);
+    (void)hipFree(tacc);
+    (void)inc_configure(c, before, 1);
+    return fail(c, GNA_OUT_OF_MEMORY, "autotune: temporary batch copy");
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    (void)hipFree(tsp);
+    (void)hipFree(tlp);
+    (void)hipFree(tacc);
+    (void)inc_configure(c, before, 1);
     return fail(c, GNA_HIP_ERROR, "hipEventCreate failed");
+  }
   const bool prof = c->prof_on;
   c->prof_on = false;
-  IncShape best = before;
-  float best_ms = -1.f;
   gna_status st = GNA_OK;
-  for (const IncShape& sh : cand) {
-    if (inc_configure(c, sh) != GNA_OK) continue;
-    if ((st = run_eloc(c, theta, spins, B, c->d_base, c->d_eloc, c->d_nev)) != GNA_OK) break;   // warm
-    (void)hipEventRecord(e0, c->stream);
-    for (int r = 0; r < 2 && st == GNA_OK; ++r) st = run_eloc(c, theta, spins, B, c->d_base, c->d_eloc, c->d_nev);
-    (void)hipEventRecord(e1, c->stream);
-    if (st != GNA_OK) break;
-    if (hipEventSynchronize(e1) != hipSuccess) { st = fail(c, GNA_HIP_ERROR, "hipEventSynchronize failed"); break; }
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    if (best_ms < 0.f || ms < best_ms) {
-      best_ms = ms;
-      best = sh;
+  // time `run` (warm-up, then two timed calls) under every candidate of `which`
+  auto tune = [&](int which, auto&& run, IncShape* best, float* best_ms) {
+    *best_ms = -1.f;
+    for (const IncShape& sh : cand) {
+      if (which == 2 && sh.per_xcd != 1) continue;   // the sweep has no per-XCD sample split
+      if (inc_configure(c, sh, which) != GNA_OK) continue;
+      if ((st = run()) != GNA_OK) return;   // warm
+      (void)hipEventRecord(e0, c->stream);
+      for (int r = 0; r < 2 && st == GNA_OK; ++r) st = run();
+      (void)hipEventRecord(e1, c->stream);
+      if (st != GNA_OK) return;
+      if (hipEventSynchronize(e1) != hipSuccess) {
+        st = fail(c, GNA_HIP_ERROR, "hipEventSynchronize failed");
+        return;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (*best_ms < 0.f || ms < *best_ms) {
+        *best_ms = ms;
+        *best = sh;
+      }
     }
-  }
+  };
+  IncShape best = before, best_sw = before_sw;
+  float ms_el = -1.f, ms_sw = -1.f;
+  tune(1, [&] { return run_eloc(c, theta, spins, B, c->d_base, c->d_eloc, c->d_nev); }, &best, &ms_el);
+  if (st == GNA_OK && (st = inc_configure(c, best, 1)) == GNA_OK)
+    tune(2, [&] {
+      if (hipMemcpyAsync(tsp, spins, (size_t)B * c->N, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+        return fail(c, GNA_HIP_ERROR, "autotune: batch copy");
+      return run_sweep(c, theta, tsp, tlp, B, 1, 0, 0, nullptr, tacc);
+    }, &best_sw, &ms_sw);
+  if (st == GNA_OK && hipStreamSynchronize(c->stream) != hipSuccess) st = fail(c, GNA_HIP_ERROR, "autotune sync");
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  (void)hipFree(tsp);
+  (void)hipFree(tlp);
+  (void)hipFree(tacc);
   c->prof_on = prof;
   if (st != GNA_OK) {
-    (void)inc_configure(c, before);
+    (void)inc_configure(c, before, 1);
+    (void)inc_configure(c, before_sw, 2);
     return st;
   }
-  if ((st = inc_configure(c, best)) != GNA_OK) return st;
-  tune_store(c->tune_key, best);
+  if ((st = inc_configure(c, best, 1)) != GNA_OK || (st = inc_configure(c, best_sw, 2)) != GNA_OK) return st;
+  tune_store(c->tune_key, IncTune{best, best_sw});
   if (chosen) {
     chosen[0] = best.S;
     chosen[1] = c->igeo.nw;
     chosen[2] = best.per_xcd;
-    chosen[3] = (int32_t)(best_ms * 500.f);   // microseconds per local-energy call
+    chosen[3] = (int32_t)(ms_el * 500.f);   // microseconds per local-energy call
+    chosen[4] = best_sw.S;
+    chosen[5] = c->igeo_sw.nw;
+    chosen[6] = c->inc_sw_maxt;
+    chosen[7] = (int32_t)(ms_sw * 500.f);   // microseconds per one-sweep call
+  }
+  return GNA_OK;
+}
+
+gna_status gna_set_shape(gna_ctx* c, int32_t which, int32_t jobs_in_flight, int32_t waves, int32_t samples_per_xcd) {
+  if (!c) return GNA_INVALID_ARG;
+  if (c->eloc_mode != GNA_ELOC_INCREMENTAL)
+    return fail(c, GNA_INVALID_ARG, "kernel shapes apply to the incremental mode only");
+  if (which < 1 || which > 3) return fail(c, GNA_INVALID_ARG, "which must be 1 (local energy), 2 (sweep) or 3");
+  if (jobs_in_flight < 1 || jobs_in_flight > kIncMaxSwaps)
+    return fail(c, GNA_INVALID_ARG, "jobs_in_flight must be in [1, 8]");
+  if (waves != kMaxWaves && (waves < 1 || waves > kMaxWaves / 2))
+    return fail(c, GNA_INVALID_ARG, "waves must be 16 or in [1, 8]");
+  if (samples_per_xcd < 1 || samples_per_xcd > 8) return fail(c, GNA_INVALID_ARG, "samples_per_xcd must be in [1, 8]");
+  const IncShape before{c->igeo.S, c->inc_wide, c->inc_per_xcd, c->igeo.nw};
+  const IncShape before_sw{c->igeo_sw.S, c->inc_sw_wide, 1, c->igeo_sw.nw};
+  const bool wide = waves == kMaxWaves;
+  const IncShape sh{jobs_in_flight, wide, samples_per_xcd, wide ? 0 : waves};
+  gna_status st = GNA_OK;
+  if (which & 1) st = inc_configure(c, sh, 1);
+  if (st == GNA_OK && (which & 2)) st = inc_configure(c, sh, 2);
+  if (st != GNA_OK) {
+    std::string msg = c->err;
+    (void)inc_configure(c, before, 1);
+    (void)inc_configure(c, before_sw, 2);
+    return fail(c, st, msg.c_str());
   }
   return GNA_OK;
 }
 
 int32_t gna_config_info(const gna_ctx* c, int32_t* info, int32_t n) {
   if (!c || (n > 0 && !info)) return -1;
-  const int32_t v[8] = {c->eloc_mode, c->eloc_mode ? c->igeo.S : 0, c->eloc_mode ? c->igeo.nw : c->geo.wpc,
-                        c->eloc_mode ? c->inc_maxt : c->tpw, c->eloc_mode ? c->inc_per_xcd : 0, c->prec, c->F,
-                        c->L};
-  for (int k = 0; k < n && k < 8; ++k) info[k] = v[k];
-  return 8;
+  const bool inc = c->eloc_mode == GNA_ELOC_INCREMENTAL;
+  const int32_t v[11] = {c->eloc_mode, inc ? c->igeo.S : 0, inc ? c->igeo.nw : c->geo.wpc,
+                         inc ? c->inc_maxt : c->tpw, inc ? c->inc_per_xcd : 0, c->prec, c->F, c->L,
+                         inc ? c->igeo_sw.S : 0, inc ? c->igeo_sw.nw : c->geo.wpc, inc ? c->inc_sw_maxt : c->tpw};
+  for (int k = 0; k < n && k < 11; ++k) info[k] = v[k];
+  return 11;
 }
 
 gna_status gna_set_couplings(gna_ctx* c, double jz, double jxy, double hb, double cb) {

@@ -102,6 +102,8 @@ def test_null_arguments(lib):
     assert lib.gna_init(ctypes.byref(c), None) == 1
     assert lib.gna_num_params(None) == -1
     assert lib.gna_logpsi(None, None, None, 0, None) == 1
+    assert lib.gna_set_shape(None, 3, 1, 8, 1) == 1
+    assert lib.gna_config_info(None, None, 0) == -1
     lib.gna_destroy(None)
 
 

@@ -125,6 +125,8 @@ def test_autotune_keeps_results_and_is_cached():
     print(f"[gpu] autotune kagome108 bf16: {choice} -> {info}", file=sys.stderr, flush=True)
     assert info["jobs_in_flight"] == choice["jobs_in_flight"] >= 1
     assert info["waves"] == choice["waves"] and info["samples_per_xcd"] == choice["samples_per_xcd"]
+    assert info["sweep_jobs_in_flight"] == choice["sweep_jobs_in_flight"] >= 1
+    assert info["sweep_waves"] == choice["sweep_waves"] and choice["sweep_us_per_call"] > 0
     el1, nev1 = g1.local_energy(th, sp)
     # the shape changes only the order of the final FP64 sums
     scale = float(el0.abs().max())
@@ -145,6 +147,61 @@ def test_autotune_keeps_results_and_is_cached():
     assert torch.equal(s_inc, s_full) and torch.equal(acc_i, acc_f)
     for g in (g1, g2, g3):
         g.close()
+
+
+def test_autotune_leaves_the_batch_alone():
+    # the sweep is tuned on a copy: the caller's configurations do not move
+    n, e = w.kagome(6, 6)
+    th, sp = _state(n, 32, 4, 16, 4)
+    before = sp.clone()
+    g = _ctx(n, e, 32, 4, "fp32", 16, "incremental")
+    g.autotune(th, sp)
+    assert torch.equal(sp, before)
+    g.close()
+
+
+@pytest.mark.parametrize("which", ["eloc", "sweep", "both"])
+def test_pinned_shapes_give_the_same_results(which):
+    n, e = w.kagome(6, 6)
+    F, L, B = 32, 4, 24
+    th, sp = _state(n, F, L, B, 5)
+    ref = _ctx(n, e, F, L, "bf16", B, "incremental")
+    el_r, _ = ref.local_energy(th, sp)
+    s_r = sp.clone()
+    acc_r = ref.metropolis_sweep(th, s_r, ref.logpsi(th, sp), n_sweeps=1, seed=11)
+    ref.close()
+    g = _ctx(n, e, F, L, "bf16", B, "incremental")
+    for jobs, waves, px in ((1, 8, 1), (2, 16, 2), (3, 6, 2)):
+        g.set_shape(jobs, waves, px, which=which)
+        info = g.config_info()
+        # waves are capped at the tiles the jobs have (4 per job here)
+        if which in ("eloc", "both"):
+            assert (info["jobs_in_flight"], info["samples_per_xcd"]) == (jobs, px)
+            assert info["waves"] == min(waves, 4 * jobs)
+        if which in ("sweep", "both"):
+            assert info["sweep_jobs_in_flight"] == jobs and info["sweep_waves"] == min(waves, 4 * jobs)
+        el, _ = g.local_energy(th, sp)
+        assert float((el - el_r).abs().max()) < 1e-12 * float(el_r.abs().max())
+        s1 = sp.clone()
+        acc = g.metropolis_sweep(th, s1, g.logpsi(th, sp), n_sweeps=1, seed=11)
+        assert torch.equal(s1, s_r) and torch.equal(acc, acc_r)
+    g.close()
+
+
+def test_set_shape_rejects_bad_shapes():
+    from paper_2011_12453_amd.binding import GnaError
+    n, e = w.kagome(6, 6)
+    g = _ctx(n, e, 32, 4, "bf16", 8, "incremental")
+    before = g.config_info()
+    for args in ((0, 8, 1), (9, 8, 1), (2, 12, 1), (2, 8, 0), (8, 1, 1)):
+        with pytest.raises(GnaError):
+            g.set_shape(*args)
+        assert g.config_info() == before
+    g.close()
+    f = _ctx(n, e, 32, 4, "bf16", 8, "full")
+    with pytest.raises(GnaError):
+        f.set_shape(2, 8, 1)
+    f.close()
 
 
 def test_autotune_full_mode_is_a_no_op():
