@@ -207,9 +207,12 @@ gna_status gna_autotune(gna_ctx *ctx, const double *theta, const int8_t *spins, 
 /* Pin the shape of the incremental kernels instead of measuring it (a shape
  * reported by gna_autotune or gna_config_info earlier, or one to profile).
  * which: 1 the local-energy kernel, 2 the sweep kernel, 3 both.  jobs_in_flight
- * in [1, 8] exchanged configurations per workgroup; waves 16 (one tile each) or
- * 1..8 (up to four tiles each), capped at the jobs' tile count (16-node tiles of
- * the largest L-hop ball); samples_per_xcd in [1, 8] (local energy only).
+ * in [1, 8] exchanged configurations per workgroup; waves 16 selects the
+ * one-tile-per-wave variant (1024-thread bound: it launches one wave per tile, at
+ * most 16), 1..8 the variant with up to four tiles per wave, capped at the jobs'
+ * tile count (16-node tiles of the largest L-hop ball); samples_per_xcd in
+ * [1, 8] (local energy only).  gna_autotune and gna_config_info report waves
+ * the same way, so a reported shape can be pinned again.
  * Results do not depend on the shape beyond the order of the final FP64 sums.
  * INVALID_ARG outside those ranges or in GNA_ELOC_FULL mode; UNSUPPORTED when the
  * shape does not fit in LDS or needs more than four tiles per wave; on error the

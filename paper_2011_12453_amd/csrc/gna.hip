@@ -1605,11 +1605,11 @@ gna_status gna_autotune(gna_ctx* c, const double* theta, const int8_t* spins, in
   tune_store(c->tune_key, IncTune{best, best_sw});
   if (chosen) {
     chosen[0] = best.S;
-    chosen[1] = c->igeo.nw;
+    chosen[1] = c->inc_wide ? kMaxWaves : c->igeo.nw;   // 16: the one-tile-per-wave variant
     chosen[2] = best.per_xcd;
     chosen[3] = (int32_t)(ms_el * 500.f);   // microseconds per local-energy call
     chosen[4] = best_sw.S;
-    chosen[5] = c->igeo_sw.nw;
+    chosen[5] = c->inc_sw_wide ? kMaxWaves : c->igeo_sw.nw;
     chosen[6] = c->inc_sw_maxt;
     chosen[7] = (int32_t)(ms_sw * 500.f);   // microseconds per one-sweep call
   }
@@ -1645,9 +1645,11 @@ gna_status gna_set_shape(gna_ctx* c, int32_t which, int32_t jobs_in_flight, int3
 int32_t gna_config_info(const gna_ctx* c, int32_t* info, int32_t n) {
   if (!c || (n > 0 && !info)) return -1;
   const bool inc = c->eloc_mode == GNA_ELOC_INCREMENTAL;
-  const int32_t v[11] = {c->eloc_mode, inc ? c->igeo.S : 0, inc ? c->igeo.nw : c->geo.wpc,
+  // waves: 16 names the one-tile-per-wave variant (it launches one wave per tile, at most 16)
+  const int32_t v[11] = {c->eloc_mode, inc ? c->igeo.S : 0, inc ? (c->inc_wide ? kMaxWaves : c->igeo.nw) : c->geo.wpc,
                          inc ? c->inc_maxt : c->tpw, inc ? c->inc_per_xcd : 0, c->prec, c->F, c->L,
-                         inc ? c->igeo_sw.S : 0, inc ? c->igeo_sw.nw : c->geo.wpc, inc ? c->inc_sw_maxt : c->tpw};
+                         inc ? c->igeo_sw.S : 0, inc ? (c->inc_sw_wide ? kMaxWaves : c->igeo_sw.nw) : c->geo.wpc,
+                         inc ? c->inc_sw_maxt : c->tpw};
   for (int k = 0; k < n && k < 11; ++k) info[k] = v[k];
   return 11;
 }

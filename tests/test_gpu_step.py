@@ -174,17 +174,24 @@ def test_pinned_shapes_give_the_same_results(which):
     for jobs, waves, px in ((1, 8, 1), (2, 16, 2), (3, 6, 2)):
         g.set_shape(jobs, waves, px, which=which)
         info = g.config_info()
-        # waves are capped at the tiles the jobs have (4 per job here)
+        # narrow variants are capped at the tiles the jobs have (4 per job here);
+        # 16 names the one-tile-per-wave variant
+        wv = waves if waves == 16 else min(waves, 4 * jobs)
         if which in ("eloc", "both"):
-            assert (info["jobs_in_flight"], info["samples_per_xcd"]) == (jobs, px)
-            assert info["waves"] == min(waves, 4 * jobs)
+            assert (info["jobs_in_flight"], info["waves"], info["samples_per_xcd"]) == (jobs, wv, px)
         if which in ("sweep", "both"):
-            assert info["sweep_jobs_in_flight"] == jobs and info["sweep_waves"] == min(waves, 4 * jobs)
+            assert (info["sweep_jobs_in_flight"], info["sweep_waves"]) == (jobs, wv)
         el, _ = g.local_energy(th, sp)
         assert float((el - el_r).abs().max()) < 1e-12 * float(el_r.abs().max())
         s1 = sp.clone()
         acc = g.metropolis_sweep(th, s1, g.logpsi(th, sp), n_sweeps=1, seed=11)
         assert torch.equal(s1, s_r) and torch.equal(acc, acc_r)
+    # a tuned shape pinned again is the same shape
+    tuned = g.autotune(th, sp)
+    info = g.config_info()
+    g.set_shape(tuned["jobs_in_flight"], tuned["waves"], tuned["samples_per_xcd"], which="eloc")
+    g.set_shape(tuned["sweep_jobs_in_flight"], tuned["sweep_waves"], 1, which="sweep")
+    assert g.config_info() == info
     g.close()
 
 
