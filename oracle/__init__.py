@@ -14,10 +14,11 @@ from .gna import (
 from .sampler import metropolis_sweeps
 from . import exact
 from . import hcb
+from .group import group_duplicates
 
 __all__ = [
     "philox4x32_10", "philox_uniform_and_edge", "unpack_theta", "num_params",
     "normalized_adjacency", "forward", "logpsi", "local_energy", "local_energy_generic",
     "n_evals", "isgo_stats", "logpsi_vjp", "isgo_grad", "sgd_update",
-    "metropolis_sweeps", "exact", "hcb",
+    "metropolis_sweeps", "exact", "hcb", "group_duplicates",
 ]
