@@ -247,6 +247,22 @@ gna_status gna_isgo_grad(gna_ctx *ctx, const double *theta, const int8_t *spins,
                          const double *logpsi_old, const double *counts, int32_t B,
                          double *grad, double *stats, double *eloc);
 
+/* Section 3's grouping of duplicated sampled states into unique states with
+ * counts, on the device: uniq[0..U) are the distinct rows of spins in the order
+ * of their first occurrence, counts[g] how many rows equal uniq[g] (FP64, ready
+ * for the counts argument of gna_isgo_grad), and *n_unique = U.  Rows
+ * uniq[U..B) repeat uniq[0] with count 0, so the whole [B] output may be passed
+ * on unchanged; passing B' = U rows (after reading n_unique) skips them.
+ * spins: [B][N] int8 (device); uniq: [B][N] int8 (device, must not overlap
+ * spins); counts: [B] FP64 (device); n_unique: one int32 (device).  Rows are
+ * matched by a 64-bit hash of their packed spins and then compared in full, so
+ * distinct rows never share a group; equal rows always do unless their hash
+ * collides with another row's (probability about B^2 / 2^65), in which case a
+ * group can appear twice with its count split, which leaves every count-weighted
+ * sum unchanged.  Asynchronous, no allocation, graph-capturable.              */
+gna_status gna_group_duplicates(gna_ctx *ctx, const int8_t *spins, int32_t B, int8_t *uniq,
+                                double *counts, int32_t *n_unique);
+
 /* Section 3's update theta <- theta - alpha * grad, in place on the device. */
 gna_status gna_sgd_update(gna_ctx *ctx, double *theta, const double *grad, double alpha);
 

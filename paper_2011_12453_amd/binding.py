@@ -69,6 +69,8 @@ _EXPORTS = {
     "gna_config_info": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]),
     "gna_set_shape": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_int32]),
+    "gna_group_duplicates": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                              ctypes.c_void_p, ctypes.c_void_p]),
     "gna_set_couplings": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                            ctypes.c_double]),
     "gna_profile_enable": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
@@ -211,6 +213,21 @@ class GNA:
         out = self._empty((self.num_params,)) if out is None else self._theta(out)
         self._check(self._lib.gna_logpsi_vjp(self._ctx, _ptr(theta), _ptr(spins), B, _ptr(cot), _ptr(out)))
         return out
+
+    def group_duplicates(self, spins, uniq=None, counts=None, n_unique=None):
+        """Distinct rows in first-occurrence order with their counts
+        (``gna_group_duplicates``).  Returns ``(uniq[B, N], counts[B], n_unique[1])``,
+        all on the device; rows past ``n_unique`` repeat the first with count 0."""
+        spins = self._spins(spins)
+        B = spins.shape[0]
+        uniq = self._empty((B, self.n_sites), torch.int8) if uniq is None else \
+            self._t(uniq, torch.int8, (B, self.n_sites), "uniq")
+        counts = self._empty((B,)) if counts is None else self._t(counts, torch.float64, (B,), "counts")
+        n_unique = self._empty((1,), torch.int32) if n_unique is None else \
+            self._t(n_unique, torch.int32, (1,), "n_unique")
+        self._check(self._lib.gna_group_duplicates(self._ctx, _ptr(spins), B, _ptr(uniq), _ptr(counts),
+                                                   _ptr(n_unique)))
+        return uniq, counts, n_unique
 
     def isgo_grad(self, theta, spins, logpsi_old, counts=None, grad=None, stats=None, eloc=None):
         """Returns ``(grad[P], stats[8], eloc[B, 2])``; stats fields: STAT_FIELDS."""

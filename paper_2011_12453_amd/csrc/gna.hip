@@ -374,6 +374,134 @@ __global__ void k_fill(double* p, double v, int n) {
   if (k < n) p[k] = v;
 }
 
+// ---------------------------------------------------------------------------
+// Grouping of duplicated states into unique states with counts (Section 3).
+// Each row is packed 64 sites per wave ballot and hashed; an open-addressing
+// table keyed by the hash keeps the smallest row index per key, and a row whose
+// contents equal that row's joins its group.  Groups are numbered in the order of
+// their first rows, so the output is the rows' first-occurrence order.
+// ---------------------------------------------------------------------------
+// splitmix64 output function (Steele, Lea and Flood, OOPSLA 2014) as the mixer
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void k_group_clear(unsigned long long* __restrict__ keys, int* __restrict__ vals, int T,
+                              int* __restrict__ cnt, int B) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < T; i += gridDim.x * blockDim.x) {
+    keys[i] = 0ull;
+    vals[i] = 0x7FFFFFFF;
+    if (i < B) cnt[i] = 0;
+  }
+}
+
+// one wave per row; T is a power of two >= 2B, so a free slot always exists
+__global__ void k_group_insert(const int8_t* __restrict__ spins, int n, int B, unsigned long long* keys,
+                               int* vals, int T, int* __restrict__ slot_of) {
+  const int lane = threadIdx.x & 63;
+  const int b = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (b >= B) return;   // wave-uniform
+  const int8_t* sb = spins + (size_t)b * n;
+  unsigned long long h = 0x9E3779B97F4A7C15ull ^ (unsigned long long)n;
+  for (int c = 0; c < n; c += 64) {
+    const bool up = (c + lane < n) && sb[c + lane] > 0;
+    h = mix64(h ^ (unsigned long long)__ballot(up)) + (unsigned long long)c;
+  }
+  if (h == 0ull) h = 1ull;   // 0 marks a free slot
+  if (lane == 0) {
+    int slot = (int)(h & (unsigned long long)(T - 1)), found = -1;
+    for (int probe = 0; probe < T; ++probe) {
+      const unsigned long long prev = atomicCAS(&keys[slot], 0ull, h);
+      if (prev == 0ull || prev == h) {
+        atomicMin(&vals[slot], b);
+        found = slot;
+        break;
+      }
+      slot = (slot + 1) & (T - 1);
+    }
+    slot_of[b] = found;
+  }
+}
+
+// rep[b]: the group's first row, or b itself when the rows differ (a hash collision)
+__global__ void k_group_rep(const int8_t* __restrict__ spins, int n, int B, const int* __restrict__ vals,
+                            const int* __restrict__ slot_of, int* __restrict__ rep) {
+  const int lane = threadIdx.x & 63;
+  const int b = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (b >= B) return;
+  const int slot = slot_of[b];
+  int r = slot >= 0 ? vals[slot] : b;
+  if (r != b) {
+    const int8_t* x = spins + (size_t)b * n;
+    const int8_t* y = spins + (size_t)r * n;
+    bool diff = false;
+    for (int i = lane; i < n; i += 64) diff |= (x[i] != y[i]);
+    if (__ballot(diff) != 0ull) r = b;
+  }
+  if (lane == 0) rep[b] = r;
+}
+
+// gid[b] = number of first rows before b (one workgroup of 1024 threads)
+__global__ __launch_bounds__(1024) void k_group_scan(const int* __restrict__ rep, int B, int* __restrict__ gid,
+                                                     int* __restrict__ n_unique) {
+  __shared__ int s_w[16];
+  __shared__ int s_base;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (threadIdx.x == 0) s_base = 0;
+  __syncthreads();
+  for (int c0 = 0; c0 < B; c0 += 1024) {
+    const int b = c0 + threadIdx.x;
+    const bool head = b < B && rep[b] == b;
+    const unsigned long long m = __ballot(head);
+    const int before = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) s_w[wv] = __popcll(m);
+    __syncthreads();
+    int off = s_base;
+    for (int k = 0; k < wv; ++k) off += s_w[k];
+    if (b < B) gid[b] = off + before;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int t = 0;
+      for (int k = 0; k < 16; ++k) t += s_w[k];
+      s_base += t;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *n_unique = s_base;
+}
+
+// one wave per row: count it into its group; a first row is copied to its slot
+__global__ void k_group_scatter(const int8_t* __restrict__ spins, int n, int B, const int* __restrict__ rep,
+                                const int* __restrict__ gid, int* cnt, int8_t* __restrict__ uniq) {
+  const int lane = threadIdx.x & 63;
+  const int b = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (b >= B) return;
+  const int r = rep[b], g = gid[r];
+  if (lane == 0) atomicAdd(&cnt[g], 1);
+  if (r == b) {
+    const int8_t* x = spins + (size_t)b * n;
+    int8_t* y = uniq + (size_t)g * n;
+    for (int i = lane; i < n; i += 64) y[i] = x[i];
+  }
+}
+
+// counts as FP64; rows past the unique ones repeat the first unique row with count 0
+__global__ void k_group_finish(const int* __restrict__ cnt, const int* __restrict__ n_unique, int n, int B,
+                               double* __restrict__ counts, int8_t* __restrict__ uniq) {
+  const int lane = threadIdx.x & 63;
+  const int p = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (p >= B) return;
+  const int U = *n_unique;
+  if (p < U) {
+    if (lane == 0) counts[p] = (double)cnt[p];
+    return;
+  }
+  if (lane == 0) counts[p] = 0.0;
+  for (int i = lane; i < n; i += 64) uniq[(size_t)p * n + i] = uniq[i];
+}
+
 // ===========================================================================
 // Host side
 // ===========================================================================
@@ -553,6 +681,10 @@ struct gna_ctx {
   long long* d_nev = nullptr;   // [1]
   double* d_cot = nullptr;      // [max_batch][2]
   double* d_eloc = nullptr;     // [max_batch][2]
+  unsigned long long* d_grp_key = nullptr;   // [grp_T] row hashes (0: free)
+  int* d_grp_val = nullptr;     // [grp_T] smallest row index per hash
+  int* d_grp_row = nullptr;     // [4][max_batch]: slot, first row, group id, count
+  int grp_T = 0;                // power of two >= 2 max_batch
   // incremental local energy
   int eloc_mode = 0;
   IncGeo igeo{};
@@ -1160,6 +1292,13 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
       (st = dev_alloc(c, &c->d_cot, MB * 2 * 8)) ||
       (st = dev_alloc(c, &c->d_eloc, MB * 2 * 8)))
     return bail(st, c->err);
+  // duplicate grouping: hash table of at least twice the batch, four int rows
+  c->grp_T = 1;
+  while ((size_t)c->grp_T < 2 * MB) c->grp_T *= 2;
+  if ((st = dev_alloc(c, &c->d_grp_key, (size_t)c->grp_T * 8)) ||
+      (st = dev_alloc(c, &c->d_grp_val, (size_t)c->grp_T * 4)) ||
+      (st = dev_alloc(c, &c->d_grp_row, 4 * MB * 4)))
+    return bail(st, c->err);
   // reverse pass: FP64 for FP64, FP32 otherwise; its own geometry and weights
   {
     const bool v64 = (c->prec == GNA_FP64);
@@ -1640,6 +1779,41 @@ gna_status gna_set_shape(gna_ctx* c, int32_t which, int32_t jobs_in_flight, int3
     return fail(c, st, msg.c_str());
   }
   return GNA_OK;
+}
+
+gna_status gna_group_duplicates(gna_ctx* c, const int8_t* spins, int32_t B, int8_t* uniq, double* counts,
+                                int32_t* n_unique) {
+  if (!c) return GNA_INVALID_ARG;
+  if (gna_status st = check_batch(c, B)) return st;
+  if (!valid_ptr(n_unique) || (B > 0 && (!valid_ptr(spins) || !valid_ptr(uniq) || !valid_ptr(counts))))
+    return fail(c, GNA_INVALID_ARG, "NULL pointer argument");
+  if (B > 0 && (const void*)uniq == (const void*)spins) return fail(c, GNA_INVALID_ARG, "uniq must not alias spins");
+  const int n = c->N, T = c->grp_T;
+  int* slot = c->d_grp_row;
+  int* rep = slot + c->max_batch;
+  int* gid = rep + c->max_batch;
+  int* cnt = gid + c->max_batch;
+  const int wpb = 4;                              // rows (waves) per 256-thread workgroup
+  const int rb = std::max(1, (B + wpb - 1) / wpb);
+  {
+    Timed tm(c, "k_group");
+    hipLaunchKernelGGL(k_group_clear, dim3(std::min(1024, (T + 255) / 256)), dim3(256), 0, c->stream, c->d_grp_key,
+                       c->d_grp_val, T, cnt, (int)B);
+    if (B > 0) {
+      hipLaunchKernelGGL(k_group_insert, dim3(rb), dim3(64 * wpb), 0, c->stream, spins, n, (int)B, c->d_grp_key,
+                         c->d_grp_val, T, slot);
+      hipLaunchKernelGGL(k_group_rep, dim3(rb), dim3(64 * wpb), 0, c->stream, spins, n, (int)B, c->d_grp_val, slot,
+                         rep);
+    }
+    hipLaunchKernelGGL(k_group_scan, dim3(1), dim3(1024), 0, c->stream, rep, (int)B, gid, n_unique);
+    if (B > 0) {
+      hipLaunchKernelGGL(k_group_scatter, dim3(rb), dim3(64 * wpb), 0, c->stream, spins, n, (int)B, rep, gid, cnt,
+                         uniq);
+      hipLaunchKernelGGL(k_group_finish, dim3(rb), dim3(64 * wpb), 0, c->stream, cnt, n_unique, n, (int)B, counts,
+                         uniq);
+    }
+  }
+  return check_launch(c, "k_group");
 }
 
 int32_t gna_config_info(const gna_ctx* c, int32_t* info, int32_t n) {
