@@ -9,9 +9,11 @@ One step is one pass of the whole hot path over a batch of 2048 chains on the
     reverse pass) -> SGD update
 
 ``value`` = local-energy log-psi evaluations (the library's exact count) per
-second of whole-step wall time, BF16 layer products.  Per-kernel durations come
-from HIP events the library records on its stream; the roofline entry is for
-the dominant kernel, k_eloc.  The CPU baseline times the FP64 oracle on a
+second of whole-step wall time, BF16 layer products (single-pass BF16 operands by
+default; the split-activation BF16, FP32 and FP64 modes are timed on the local
+energy alone beside it, each with its error against the oracle).  Per-kernel
+durations come from HIP events the library records on its stream; the roofline
+entry is for the dominant kernel.  The CPU baseline times the FP64 oracle on a
 bounded prefix of the same batch, and its outputs give the error columns.
 """
 from __future__ import annotations
@@ -26,7 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "log-psi evals/sec in E_loc (432-site Kagome), BF16 vs FP32 vs FP64 at stated err"
-PEAK = {"bf16": 2.5e15, "fp32": 157.3e12, "fp64": 78.6e12}   # MI355X dense MFMA, FLOP/s
+PEAK = {"bf16": 2.5e15, "bf16_1x": 2.5e15, "fp32": 157.3e12, "fp64": 78.6e12}   # MI355X dense MFMA, FLOP/s
 
 
 def flops_per_eval(n, n_edges, F, L):
@@ -98,10 +100,11 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="kagome432_L6F64")
-    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32", "fp64"])
+    ap.add_argument("--precision", default="bf16_1x", choices=["bf16", "bf16_1x", "fp32", "fp64"],
+                    help="bf16_1x: single-pass BF16 operands; bf16: split (hi + lo) BF16 activations")
     ap.add_argument("--eloc-mode", default="incremental", choices=["incremental", "full"],
                     help="how the timed step evaluates the exchanged configurations")
-    ap.add_argument("--compare", default="fp32,fp64", help="other precisions timed on E_loc alone")
+    ap.add_argument("--compare", default="bf16,fp32,fp64", help="other precisions timed on E_loc alone")
     ap.add_argument("--compare-batch", type=int, default=512)
     ap.add_argument("--eloc-reps", type=int, default=3)
     ap.add_argument("--cpu-samples", type=int, default=8)
@@ -399,7 +402,7 @@ def main():
         "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": args.precision, "data": "synthetic",
+        "dtype": "bf16" if args.precision.startswith("bf16") else args.precision, "data": "synthetic",
         "config": {"workload": p.name, "lattice": "12x12x3 kagome torus", "sites": n, "bonds": len(e),
                    "layers": L, "features": F, "tied": True, "batch": B,
                    "step": "gna_step: logpsi + 1 Metropolis sweep + ISGO update (logpsi, E_loc, stats, VJP) + SGD",
@@ -413,6 +416,12 @@ def main():
         "precisions": per_prec,
         "kernels_ms_per_step": {k: v[1] / args.steps for k, v in sorted(prof.items())},
     }
+    head = per_prec.get(f"{args.precision}_{args.eloc_mode}", {})
+    if "err_energy_per_site" in head:   # the stated error bound of the headline precision
+        bound = {"fp64": 1e-10, "fp32": 1e-5}.get(args.precision, 1e-3)
+        out["accuracy"] = {"precision": args.precision, "err_energy_per_site": head["err_energy_per_site"],
+                           "bound": bound, "within_bound": bool(head["err_energy_per_site"] < bound),
+                           "sample": cpu["sample"]}
     print(json.dumps(out))
     g.close()
 

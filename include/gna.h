@@ -65,10 +65,14 @@ enum {
  * energy sums, the ISGO weights and statistics are FP64 in every mode.
  *   GNA_FP64: everything FP64 (MFMA f64).
  *   GNA_FP32: operands, aggregation and tanh FP32, FP32 MFMA accumulation.
- *   GNA_BF16: weights and inter-layer embeddings rounded to bfloat16 as MFMA
- *             operands; aggregation, accumulation and tanh in FP32; the readout
- *             sum is taken in FP64 from the FP32 last-layer output.          */
-enum { GNA_FP64 = 0, GNA_FP32 = 1, GNA_BF16 = 2 };
+ *   GNA_BF16: weights rounded to bfloat16; each FP32 activation enters the
+ *             MFMA as the pair hi + lo of bfloat16 values (two products, about
+ *             16 significant bits); aggregation, accumulation and tanh in FP32;
+ *             the readout sum is taken in FP64 from the FP32 last-layer output.
+ *   GNA_BF16_1X: as GNA_BF16 but each activation is rounded to the nearest
+ *             bfloat16 and each product is a single MFMA (about 8 significant
+ *             bits per operand).                                             */
+enum { GNA_FP64 = 0, GNA_FP32 = 1, GNA_BF16 = 2, GNA_BF16_1X = 3 };
 
 /* How gna_local_energy and gna_metropolis_sweep evaluate log psi(s^ij):
  *   GNA_ELOC_FULL: every exchanged configuration through all L layers.
@@ -102,7 +106,7 @@ typedef struct {
   int32_t n_layers;         /* L: 0 .. 16 applications of Eq. 1 */
   int32_t tied;             /* 1: one W, b shared by all layers (the paper's
                                choice, Section 2); 0: one per layer */
-  int32_t precision;        /* GNA_FP64 / GNA_FP32 / GNA_BF16 */
+  int32_t precision;        /* GNA_FP64 / GNA_FP32 / GNA_BF16 / GNA_BF16_1X */
   double jz, jxy;           /* Heisenberg couplings; the isotropic model is 1, 1 */
   int32_t max_batch;        /* largest B any call will pass (sizes the workspace) */
   int32_t eloc_mode;        /* GNA_ELOC_FULL or GNA_ELOC_INCREMENTAL (tied weights) */

@@ -14,8 +14,8 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-FP64, FP32, BF16 = 0, 1, 2
-PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
+FP64, FP32, BF16, BF16_1X = 0, 1, 2, 3
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "bf16_1x": BF16_1X}
 STAT_FIELDS = ("e_re", "e_im", "var", "ess", "sum_r", "shift", "n_evals", "nonfinite")
 _STATUS = {0: "OK", 1: "INVALID_ARG", 2: "BAD_GRAPH", 3: "UNSUPPORTED", 4: "OUT_OF_MEMORY",
            5: "HIP_ERROR"}

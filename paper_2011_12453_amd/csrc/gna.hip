@@ -1077,6 +1077,11 @@ gna_status inc_configure(gna_ctx* c, IncShape shp, int which) {
   switch (c->prec) {
     case GNA_FP64: ik = inc_pick_f<PF64>(F, tpw, nch, maxt, shp.wide); break;
     case GNA_FP32: ik = inc_pick_f<PF32>(F, tpw, nch, maxt, shp.wide); break;
+    case GNA_BF16_1X:
+      if (F == 16) ik = inc_pick<PBF161, 16>(tpw, nch, maxt, shp.wide);
+      else if (F == 32) ik = inc_pick<PBF16W1, 32>(tpw, nch, maxt, shp.wide);
+      else ik = inc_pick<PBF16W1, 64>(tpw, nch, maxt, shp.wide);
+      break;
     default:
       if (F == 16) ik = inc_pick<PBF16, 16>(tpw, nch, maxt, shp.wide);
       else if (F == 32) ik = inc_pick<PBF16W, 32>(tpw, nch, maxt, shp.wide);
@@ -1133,7 +1138,7 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
   if (F != 16 && F != 32 && F != 64) return init_fail(GNA_UNSUPPORTED, "n_features must be 16, 32 or 64");
   if (L < 0 || L > 16) return init_fail(GNA_UNSUPPORTED, "n_layers must be in [0, 16]");
   if (cfg->tied != 0 && cfg->tied != 1) return init_fail(GNA_INVALID_ARG, "tied must be 0 or 1");
-  if (cfg->precision < GNA_FP64 || cfg->precision > GNA_BF16) return init_fail(GNA_INVALID_ARG, "unknown precision");
+  if (cfg->precision < GNA_FP64 || cfg->precision > GNA_BF16_1X) return init_fail(GNA_INVALID_ARG, "unknown precision");
   if (cfg->eloc_mode != GNA_ELOC_FULL && cfg->eloc_mode != GNA_ELOC_INCREMENTAL)
     return init_fail(GNA_INVALID_ARG, "unknown eloc_mode");
   if (cfg->activation != GNA_ACT_TANH && cfg->activation != GNA_ACT_RELU_LN)
@@ -1240,6 +1245,10 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
   switch (c->prec) {
     case GNA_FP64: c->kern = pick_f<PF64>(F, tpw, nch); break;
     case GNA_FP32: c->kern = pick_f<PF32>(F, tpw, nch); break;
+    case GNA_BF16_1X:
+      c->kern = (F == 16) ? pick_nch<PBF161, 16>(tpw, nch)
+                          : (F == 32 ? pick_nch<PBF16W1, 32>(tpw, nch) : pick_nch<PBF16W1, 64>(tpw, nch));
+      break;
     default:
       // bf16: the K=32 instruction where F allows, the K=16 one at F = 16
       c->kern = (F == 16) ? pick_nch<PBF16, 16>(tpw, nch)

@@ -187,6 +187,37 @@ struct PBF16W {
   __device__ static Acc act(Acc y) { return tanh_from_scaled(y); }
 };
 
+// Single-pass BF16: the activations are rounded to the nearest bfloat16 and each
+// product is one MFMA (the classic BF16 operand precision; about 8 significant
+// bits per operand instead of the split pair's 16).  Same layouts as above.
+struct PBF161 : PBF16 {
+  using BF = s4;
+  static constexpr int NPART = 1;
+  __device__ static BF make_b(const Acc* x) {
+    const unsigned l01 = pack_bf16_rne(x[0], x[1]), l23 = pack_bf16_rne(x[2], x[3]);
+    return __builtin_bit_cast(s4, (unsigned long long)l01 | ((unsigned long long)l23 << 32));
+  }
+  __device__ static CF mma(const AF& a, const BF& b, CF c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+  }
+  __device__ static CF mma_part(const AF& a, const BF& b, int, CF c) { return mma(a, b, c); }
+};
+
+struct PBF16W1 : PBF16W {
+  using BF = bf8v;
+  static constexpr int NPART = 1;
+  __device__ static BF make_b(const Acc* x) {
+    unsigned u[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) u[p] = pack_bf16_rne(x[2 * p], x[2 * p + 1]);
+    return __builtin_bit_cast(bf8v, uint4{u[0], u[1], u[2], u[3]});
+  }
+  __device__ static CF mma(const AF& a, const BF& b, CF c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+  __device__ static CF mma_part(const AF& a, const BF& b, int, CF c) { return mma(a, b, c); }
+};
+
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): 10 rounds of two 32x32->64 products,
 // XOR recombination with the key, key advanced by Weyl constants between rounds.
@@ -556,9 +587,9 @@ __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
       __syncthreads();
     }
     const Acc* bias = s.bias + (net.tied ? 0 : l) * F + q * NS;   // this lane group's slots
-    // B operands of every tile of the wave, built once per layer (split types
+    // B operands of every tile of the wave, built once per layer (BF16 types
     // only; FP32/FP64 operands are the activations themselves)
-    constexpr bool SPLIT = (P::NPART == 2);
+    constexpr bool SPLIT = (P::VEC > 1);   // multi-element (BF16) fragments
     BF bfr[SPLIT ? TPW : 1][SPLIT ? KSB : 1];
     if constexpr (SPLIT) {
 #pragma unroll

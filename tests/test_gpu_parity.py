@@ -16,7 +16,7 @@ import workloads as w
 pytestmark = pytest.mark.gpu
 
 DEV = torch.device("cuda", 0)
-EPS_SITE = {"fp64": 1e-10, "fp32": 1e-5, "bf16": 1e-3}
+EPS_SITE = {"fp64": 1e-10, "fp32": 1e-5, "bf16": 1e-3, "bf16_1x": 1e-3}
 
 
 def _ctx(n, e, F, L, tied=True, prec="fp64", max_batch=256, **kw):
@@ -71,10 +71,15 @@ def _compare(case, prec, theta_kind):
     return lp_err, el_err, site
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16", "bf16_1x"])
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_logpsi_and_local_energy_match_oracle(case, prec):
     lp_err, el_err, site = _compare(case, prec, "glorot")
+    if prec == "bf16_1x":
+        # activations also rounded to 8 bits: per-sample ratio errors of a few 1e-3
+        # (CPU emulation at 432 sites: 5e-3); the energy per site keeps the bound
+        assert lp_err < 2e-2 and el_err < 5e-2 and site < EPS_SITE[prec]
+        return
     assert site < EPS_SITE[prec]
     if prec == "fp64":
         assert lp_err < 1e-12 and el_err < 1e-11
@@ -102,7 +107,7 @@ def test_stress_weights_match_oracle(case, prec):
 
 FULL = [("kagome108_L4F32", "bf16"), ("kagome108_L4F32", "fp32"), ("triangular144_L4F32", "bf16"),
         ("er100_L4F32", "bf16"), ("kagome432_L6F64", "bf16"), ("kagome432_L6F64", "fp32"),
-        ("kagome432_L6F64", "fp64")]
+        ("kagome432_L6F64", "fp64"), ("kagome432_L6F64", "bf16_1x"), ("kagome108_L4F32", "bf16_1x")]
 
 
 @pytest.mark.parametrize("name,prec", FULL, ids=[f"{a}-{b}" for a, b in FULL])
@@ -124,7 +129,7 @@ def test_full_size_batch_sampled_parity(name, prec):
     site = _site_err(el[rows, 0], ref.real, n)
     print(f"[gpu] full {name} {prec}: sampled eloc rel {err:.2e} e/site rel {site:.2e}", file=sys.stderr, flush=True)
     assert site < EPS_SITE[prec]
-    assert err < {"fp64": 1e-11, "fp32": 1e-4, "bf16": 1e-2}[prec]
+    assert err < {"fp64": 1e-11, "fp32": 1e-4, "bf16": 1e-2, "bf16_1x": 5e-2}[prec]
     assert np.all(np.isfinite(el))
 
 
@@ -302,6 +307,29 @@ def test_autograd_function_backward():
 TIED = [c for c in CASES if c[4]]
 
 
+@pytest.mark.parametrize("case", TIED, ids=[c[0] for c in TIED])
+def test_incremental_single_pass_bf16_equals_full(case):
+    # the incremental rows repeat the full evaluation's arithmetic in every mode
+    name, build, F, L, tied, B = case
+    n, e = build()
+    theta = w.glorot_theta(F, L, tied, seed=0)
+    spins = np.concatenate([w.random_sz0_spins(B, n, 1000 + B), w.random_spins(2, n, 77)])
+    out = []
+    for mode in ("full", "incremental"):
+        g = _ctx(n, e, F, L, tied, "bf16_1x", max_batch=len(spins), eloc_mode=mode)
+        el, nev = g.local_energy(_dev(theta), _dev(spins))
+        out.append((el.cpu().numpy(), int(nev.item())))
+        g.close()
+    (ef, nf), (ei, ni) = out
+    ref = oracle.local_energy(theta, spins, n, e, F, L, tied)
+    scale = max(1.0, np.max(np.abs(ref)))
+    assert ni == nf == oracle.n_evals(spins, e)
+    assert np.max(np.abs(ei - ef)) < 1e-12 * scale
+    err = np.max(np.abs(ei[:, 0] - ref.real) + np.abs(ei[:, 1] - ref.imag)) / scale
+    print(f"[gpu] incremental {name} bf16_1x: eloc rel {err:.2e}", file=sys.stderr, flush=True)
+    assert err < 5e-2
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
 @pytest.mark.parametrize("case", TIED, ids=[c[0] for c in TIED])
 def test_incremental_local_energy_matches_oracle_and_full(case, prec):
@@ -381,7 +409,7 @@ def _sweep(g, theta, s0, n_sweeps, seed, counter_base=0):
     return sp.cpu().numpy(), lp.cpu().numpy(), acc.cpu().numpy()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16", "bf16_1x"])
 @pytest.mark.parametrize("case", TIED, ids=[c[0] for c in TIED])
 def test_incremental_sampler_matches_full_sampler(case, prec):
     # the proposals' log-psi differences agree to FP64 rounding, so both samplers
