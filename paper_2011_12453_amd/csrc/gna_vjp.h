@@ -14,6 +14,8 @@
 // order, so the result does not depend on timing.
 #pragma once
 
+#include <type_traits>
+
 #include "gna_kernels.h"
 
 namespace gna {
@@ -95,7 +97,8 @@ __global__ __launch_bounds__(512) void k_vjp_dx(VNet v, int layer, int b0, int B
     for (int k = threadIdx.x; k < 2 * F * F; k += blockDim.x) wfr[k] = src[k];
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, q = lane >> 4, col = lane & 15;
+  const int lane = threadIdx.x & 63, q = lane >> 4, col = lane & 15;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform: scalar branches
   const size_t per = (size_t)v.nplanes * v.plane;
   const int nW = v.tied ? 1 : v.L;
   const double* head_a = v.theta + 3 * F + (size_t)nW * (2 * F * F + F);
@@ -197,7 +200,8 @@ __global__ __launch_bounds__(256) void k_vjp_dw(VNet v, int layer, int Bc, const
   using Acc = typename P::Acc;
   using CF = typename P::CF;
   constexpr int NS = F / 4, MT = F / 16, MTW = (2 * MT + 3) / 4;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, q = lane >> 4, col = lane & 15;
+  const int lane = threadIdx.x & 63, q = lane >> 4, col = lane & 15;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform: scalar branches
   const size_t per = (size_t)v.nplanes * v.plane;
   const int rows_per_sample = v.npad;
   const long long total_steps = (long long)Bc * rows_per_sample / 4;   // npad is a multiple of 16
@@ -211,27 +215,48 @@ __global__ __launch_bounds__(256) void k_vjp_dw(VNet v, int layer, int Bc, const
   Acc dbp[MT];
 #pragma unroll
   for (int t = 0; t < MT; ++t) dbp[t] = (Acc)0;
-  for (long long st = s0; st < s1; ++st) {
-    const long long row = st * 4 + q;                 // this lane's row of the 4-row k-step
-    const int b = (int)(row / rows_per_sample), node = (int)(row % rows_per_sample);
-    const Acc* pb = planes + b * per;
-    const size_t off = (size_t)node * F;
-    Acc bf[MT];
+  // sample and first row of the current 4-row k-step, advanced without division
+  // (npad is a multiple of 16, so a k-step never straddles two samples)
+  int sb = (int)((s0 * 4) / rows_per_sample), node0 = (int)((s0 * 4) % rows_per_sample);
+  // m-tiles of this wave; with 2F/16 a multiple of 4 every wave has MTW of them
+  constexpr bool ALL_M = (2 * MT) % 4 == 0;
+  // U k-steps per round: all their loads are issued before their MFMAs
+  constexpr int U = 4;
+  auto round = [&](auto u_const) {
+    constexpr int UU = decltype(u_const)::value;
+    Acc bf[UU][MT], af[UU][MTW];
 #pragma unroll
-    for (int t = 0; t < MT; ++t) {
-      bf[t] = pb[(size_t)plane_dP(v) * v.plane + off + 16 * t + col];
-      dbp[t] += bf[t];
+    for (int u = 0; u < UU; ++u) {
+      const Acc* pb = planes + (size_t)sb * per;
+      const size_t off = (size_t)(node0 + q) * F;     // this lane's row of the k-step
+      node0 += 4;
+      const bool wrap = node0 == rows_per_sample;
+      sb += wrap ? 1 : 0;
+      node0 = wrap ? 0 : node0;
+#pragma unroll
+      for (int t = 0; t < MT; ++t) bf[u][t] = pb[(size_t)plane_dP(v) * v.plane + off + 16 * t + col];
+#pragma unroll
+      for (int a = 0; a < MTW; ++a) {
+        const int tm = wv + 4 * a;
+        const int pl = (tm < MT) ? (v.L + 1 + layer) : layer;   // M^l or H^l
+        af[u][a] = (ALL_M || tm < 2 * MT) ? pb[(size_t)pl * v.plane + off + 16 * (tm % MT) + col] : (Acc)0;
+      }
     }
 #pragma unroll
-    for (int a = 0; a < MTW; ++a) {
-      const int tm = wv + 4 * a;
-      if (tm >= 2 * MT) break;
-      const int pl = (tm < MT) ? (v.L + 1 + layer) : layer;   // M^l or H^l
-      const Acc af = pb[(size_t)pl * v.plane + off + 16 * (tm % MT) + col];
+    for (int u = 0; u < UU; ++u) {
 #pragma unroll
-      for (int t = 0; t < MT; ++t) acc[a][t] = P::mma(af, bf[t], acc[a][t]);
+      for (int t = 0; t < MT; ++t) dbp[t] += bf[u][t];
+#pragma unroll
+      for (int a = 0; a < MTW; ++a) {
+        if (!ALL_M && wv + 4 * a >= 2 * MT) continue;   // wave-uniform
+#pragma unroll
+        for (int t = 0; t < MT; ++t) acc[a][t] = P::mma(af[u][a], bf[u][t], acc[a][t]);
+      }
     }
-  }
+  };
+  long long st = s0;
+  for (; st + U <= s1; st += U) round(std::integral_constant<int, U>{});
+  for (; st < s1; ++st) round(std::integral_constant<int, 1>{});
   // scatter to theta layout: position p = qq*NS + i holds logical feature lc(qq, i)
   double* g = part + (size_t)blockIdx.x * v.npar;
   const int wi = v.tied ? 0 : layer;
@@ -278,6 +303,7 @@ __global__ __launch_bounds__(256) void k_vjp_tail(VNet v, int b0, int Bc, const 
   const int p = threadIdx.x % F;           // feature position
   const int rs = threadIdx.x / F, nrs = blockDim.x / F;
   double e0 = 0, e1 = 0, za = 0, zp = 0;
+  double ua = 0, up = 0, sca = 0, scp = 0;   // one-hot part: sum c * #up over this thread's nodes
   for (int b = blockIdx.x; b < Bc; b += gridDim.x) {
     const Acc* pb = planes + b * per;
     const Acc* H0 = pb;
@@ -291,8 +317,10 @@ __global__ __launch_bounds__(256) void k_vjp_tail(VNet v, int b0, int Bc, const 
     const int fl = P::lc(p / NS, p % NS);
     const double dz = ca * ha[fl] + cp * ha[F + 3 + fl];
     double z = 0;
+    int nup = 0;
     for (int node = rs; node < v.n; node += nrs) {
       const size_t o = (size_t)node * F + p;
+      nup += sb[node] > 0;
       const double dh0 = v.L > 0 ? (double)dH0[o] : dz;
       double dp0;
       if (v.act == 0) {
@@ -306,8 +334,17 @@ __global__ __launch_bounds__(256) void k_vjp_tail(VNet v, int b0, int Bc, const 
     }
     za += ca * z;
     zp += cp * z;
+    ua += ca * nup;
+    up += cp * nup;
+    sca += ca;
+    scp += cp;
   }
   __shared__ double red[4][256];
+  __shared__ double red_up[2][256 / F];   // per row slot rs (the p == 0 threads)
+  if (p == 0) {
+    red_up[0][rs] = ua;
+    red_up[1][rs] = up;
+  }
   __shared__ double sdh[2][F];   // summed dH^0 per spin value, logical order
   red[0][threadIdx.x] = e0;
   red[1][threadIdx.x] = e1;
@@ -366,25 +403,17 @@ __global__ __launch_bounds__(256) void k_vjp_tail(VNet v, int b0, int Bc, const 
   }
   // one-hot counts and head biases: z[F] = #down, z[F+1] = #up
   if (threadIdx.x == 0) {
-    double cdn = 0, cup = 0, sca = 0, scp = 0, pdn = 0, pup = 0;
-    for (int b = blockIdx.x; b < Bc; b += gridDim.x) {
-      const int8_t* sb = spins + (size_t)(b0 + b) * v.n;
-      int up = 0;
-      for (int node = 0; node < v.n; ++node) up += sb[node] > 0;
-      const double ca = cot[2 * (size_t)(b0 + b)], cp = cot[2 * (size_t)(b0 + b) + 1];
-      cdn += ca * (v.n - up);
-      cup += ca * up;
-      sca += ca;
-      pdn += cp * (v.n - up);
-      pup += cp * up;
-      scp += cp;
+    double cup = 0, pup = 0;
+    for (int r = 0; r < nrs; ++r) {
+      cup += red_up[0][r];
+      pup += red_up[1][r];
     }
     const int nW = v.tied ? 1 : v.L;
     double* gva = part + (size_t)blockIdx.x * v.npar + 3 * F + (size_t)nW * (2 * F * F + F);
-    gva[F] += cdn;
+    gva[F] += v.n * sca - cup;
     gva[F + 1] += cup;
     gva[F + 2] += sca;
-    gva[F + 3 + F] += pdn;
+    gva[F + 3 + F] += v.n * scp - pup;
     gva[F + 3 + F + 1] += pup;
     gva[F + 3 + F + 2] += scp;
   }
