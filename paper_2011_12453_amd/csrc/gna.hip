@@ -847,8 +847,11 @@ IncNet make_inc(const gna_ctx* c) {
   return inc;
 }
 
+// planes_ready (incremental mode): the planes and `base` already hold the base pass
+// of exactly these configurations under this theta (an incremental sweep just left
+// them so), and the base pass is skipped.
 gna_status run_eloc(gna_ctx* c, const double* theta, const int8_t* spins, int B, const double* base,
-                    double* eloc, long long* nev) {
+                    double* eloc, long long* nev, bool planes_ready = false) {
   {
     Timed tm(c, "k_zero_i64");
     hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, c->stream, nev, 1);
@@ -880,7 +883,7 @@ gna_status run_eloc(gna_ctx* c, const double* theta, const int8_t* spins, int B,
   if (c->eloc_mode == GNA_ELOC_INCREMENTAL) {
     void* planes = c->d_inc_planes;
     double* lp_out = const_cast<double*>(base);   // the base pass also yields log psi(s)
-    {
+    if (!planes_ready) {
       Timed tm(c, "k_inc_base");
       void* a1[] = {&net, &spins, &B, &planes, &lp_out};
       hipError_t e = hipLaunchKernel(c->ik.base, dim3(std::min(B, c->grid_inc_base)), dim3(64 * c->geo.wpc), a1,
@@ -1598,6 +1601,27 @@ gna_status gna_logpsi_vjp(gna_ctx* c, const double* theta, const int8_t* spins, 
   return run_vjp(c, theta, spins, B, cot, grad);
 }
 
+// One ISGO update's gradient.  base_ready (incremental mode only): log psi of the
+// configurations under theta, with the planes holding their base pass (as an
+// incremental sweep under the same theta leaves them); the base pass is skipped.
+static gna_status isgo_impl(gna_ctx* c, const double* theta, const int8_t* spins, const double* logpsi_old,
+                            const double* counts, int32_t B, double* grad, double* stats, double* eloc,
+                            const double* base_ready) {
+  if (gna_status st = prepare(c, theta)) return st;
+  if (c->eloc_mode == GNA_ELOC_FULL)   // the incremental base pass writes log psi itself
+    if (gna_status st = run_logpsi(c, theta, spins, B, c->d_base)) return st;
+  const double* base = base_ready ? base_ready : c->d_base;
+  double* el = eloc ? eloc : c->d_eloc;
+  if (gna_status st = run_eloc(c, theta, spins, B, base, el, c->d_nev, base_ready != nullptr)) return st;
+  {
+    Timed tm(c, "k_isgo_stats");
+    hipLaunchKernelGGL(k_isgo_stats, dim3(1), dim3(kStatThreads), 0, c->stream, B, logpsi_old, base, el,
+                     counts, c->d_nev, stats, c->d_cot);
+  }
+  if (gna_status st = check_launch(c, "k_isgo_stats")) return st;
+  return run_vjp(c, theta, spins, B, c->d_cot, grad);
+}
+
 gna_status gna_isgo_grad(gna_ctx* c, const double* theta, const int8_t* spins, const double* logpsi_old,
                          const double* counts, int32_t B, double* grad, double* stats, double* eloc) {
   if (!c) return GNA_INVALID_ARG;
@@ -1605,18 +1629,7 @@ gna_status gna_isgo_grad(gna_ctx* c, const double* theta, const int8_t* spins, c
   if (!valid_ptr(theta) || !valid_ptr(grad) || !valid_ptr(stats) ||
       (B > 0 && (!valid_ptr(spins) || !valid_ptr(logpsi_old))))
     return fail(c, GNA_INVALID_ARG, "NULL pointer argument");
-  if (gna_status st = prepare(c, theta)) return st;
-  if (c->eloc_mode == GNA_ELOC_FULL)   // the incremental base pass writes log psi itself
-    if (gna_status st = run_logpsi(c, theta, spins, B, c->d_base)) return st;
-  double* el = eloc ? eloc : c->d_eloc;
-  if (gna_status st = run_eloc(c, theta, spins, B, c->d_base, el, c->d_nev)) return st;
-  {
-    Timed tm(c, "k_isgo_stats");
-    hipLaunchKernelGGL(k_isgo_stats, dim3(1), dim3(kStatThreads), 0, c->stream, B, logpsi_old, c->d_base, el,
-                     counts, c->d_nev, stats, c->d_cot);
-  }
-  if (gna_status st = check_launch(c, "k_isgo_stats")) return st;
-  return run_vjp(c, theta, spins, B, c->d_cot, grad);
+  return isgo_impl(c, theta, spins, logpsi_old, counts, B, grad, stats, eloc, nullptr);
 }
 
 gna_status gna_sgd_update(gna_ctx* c, double* theta, const double* grad, double alpha) {
@@ -1641,7 +1654,11 @@ gna_status gna_step(gna_ctx* c, double* theta, int8_t* spins, double* logpsi, in
     return fail(c, GNA_INVALID_ARG, "NULL pointer argument");
   if (c->E == 0 && n_sweeps > 0) return fail(c, GNA_INVALID_ARG, "graph has no bonds to propose");
   if (gna_status st = prepare(c, theta)) return st;
-  if (gna_status st = run_logpsi(c, theta, spins, B, logpsi)) return st;
+  const bool inc = c->eloc_mode == GNA_ELOC_INCREMENTAL;
+  // the full sampler starts from log psi of the chains; the incremental one evaluates
+  // the final configurations itself and leaves their base pass in the planes
+  if (!inc)
+    if (gna_status st = run_logpsi(c, theta, spins, B, logpsi)) return st;
   unsigned long long* cd = reinterpret_cast<unsigned long long*>(counter);
   if (gna_status st = run_sweep(c, theta, spins, logpsi, B, n_sweeps, seed, 0, cd, n_accept)) return st;
   {
@@ -1650,7 +1667,10 @@ gna_status gna_step(gna_ctx* c, double* theta, int8_t* spins, double* logpsi, in
                        (unsigned long long)n_sweeps * (unsigned long long)c->N);
   }
   if (gna_status st = check_launch(c, "k_add_u64")) return st;
-  if (gna_status st = gna_isgo_grad(c, theta, spins, logpsi, nullptr, B, grad, stats, eloc)) return st;
+  // theta is unchanged since the sweep: its samples' log psi is the new log psi, and
+  // in incremental mode the planes are already the base pass of the local energy
+  if (gna_status st = isgo_impl(c, theta, spins, logpsi, nullptr, B, grad, stats, eloc, inc ? logpsi : nullptr))
+    return st;
   return gna_sgd_update(c, theta, grad, lr);
 }
 

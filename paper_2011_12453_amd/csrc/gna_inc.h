@@ -149,6 +149,7 @@ __device__ void inc_group(const Net& net, const IncNet& inc, const IncGeo& ig, c
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int q = lane >> 4, col = lane & 15;
   const int nw = ig.nw, Lr = net.L, dm = inc.dmax, bd = blockDim.x;
+  nsw = __builtin_amdgcn_readfirstlane(nsw);   // the same in every thread: scalar branches
   const size_t plane = (size_t)net.g.npad * F;
   const Acc* bias = x.sbias + q * NS;
 
@@ -213,7 +214,8 @@ __device__ void inc_group(const Net& net, const IncNet& inc, const IncGeo& ig, c
     V4 cvv[NCOPY];
     int cdst[NCOPY];
     {
-      const int2 lay = jobs.lay[l];
+      const int2 lay = make_int2(__builtin_amdgcn_readfirstlane(jobs.lay[l].x),
+                                 __builtin_amdgcn_readfirstlane(jobs.lay[l].y));
       const int ctot = lay.y * VPR;
       const Acc* Gl = planes + (size_t)(Lr + l - 1) * plane;
       // copy item idx -> (source vector, byte offset of the destination in LDS)
@@ -248,8 +250,8 @@ __device__ void inc_group(const Net& net, const IncNet& inc, const IncGeo& ig, c
       const int g = wv + k * nw;
       const int w = g % nsw, tt = g / nsw;
       tsw[k] = w;
-      tcl[k] = jobs.cnt[w][l];
-      tcp[k] = jobs.cnt[w][l - 1];
+      tcl[k] = __builtin_amdgcn_readfirstlane(jobs.cnt[w][l]);   // per job: uniform in the wave
+      tcp[k] = __builtin_amdgcn_readfirstlane(jobs.cnt[w][l - 1]);
       tok[k] = tt * 16 < tcl[k];
       trow[k] = tt * 16 + col;
       tnd[k] = trow[k] < tcl[k] ? (int)x.tab[w * ig.tabw + trow[k]] : -1;

@@ -27,11 +27,14 @@ def _state(n, F, L, B, seed):
     return theta, spins
 
 
-@pytest.mark.parametrize("mode", ["full", "incremental"])
-def test_step_equals_its_parts(mode):
+@pytest.mark.parametrize("mode,prec", [("full", "fp64"), ("incremental", "fp64"), ("incremental", "bf16_1x"),
+                                       ("incremental", "bf16")])
+def test_step_equals_its_parts(mode, prec):
+    # the step reuses the sweep's final log psi and (incremental) its planes as the
+    # ISGO update's base pass: bitwise the same as calling the parts one by one
     n, e = w.kagome(6, 6)
     F, L, B, seed, lr = 32, 4, 32, 7, 1e-3
-    g = _ctx(n, e, F, L, "fp64", B, mode)
+    g = _ctx(n, e, F, L, prec, B, mode)
     th1, sp1 = _state(n, F, L, B, 3)
     th2, sp2 = th1.clone(), sp1.clone()
     lp1 = torch.empty(B, 2, dtype=torch.float64, device=DEV)
