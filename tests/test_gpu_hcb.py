@@ -70,3 +70,30 @@ def test_hcb_isgo_vmc_reaches_exact_ground_energy(tv):
     assert abs(ev - e0) / abs(e0) < 2e-2
     assert abs(sampled - ev) / abs(e0) < 5e-2
     assert np.all(th[sl["v_p"][0]:sl["v_p"][1]] == 0) and th[sl["c_p"][0]] == 0   # single real head
+
+
+@pytest.mark.parametrize("tv", [0.2, 0.5, 1.0])
+def test_hcb_isgo_vmc_paper_activation_reaches_exact_ground_energy(tv):
+    # the paper's ansatz: ReLU + layer normalisation (Section 2), duplicates grouped
+    # (Section 3); a smaller step than with tanh, whose reuse of samples is stable at 0.1
+    from paper_2011_12453_amd import GNA
+    from paper_2011_12453_amd.vmc import isgo_vmc
+    n, e = w.kagome(2, 2)
+    F, L, B = 16, 2, 1024
+    print(f"[gpu] hcb relu_ln ctx t/V={tv}", file=sys.stderr, flush=True)
+    g = GNA(n, e, F, L, tied=True, precision="fp32", max_batch=B, device=DEV, eloc_mode="incremental",
+            activation="relu_ln")
+    g.set_hard_core_bosons(tv, 1.0)
+    theta = torch.from_numpy(w.glorot_theta(F, L, True, seed=0, real_head=True)).to(DEV)
+    spins = torch.from_numpy(w.random_sz0_spins(B, n, 1001)).to(DEV)
+    hist, _ = isgo_vmc(g, theta, spins, n_iters=40, n_updates=5, lr=0.05, n_sweeps=2, seed=17, group=True)
+    occ = hcb.occupations(n, n // 2)
+    states = (2 * occ.astype(np.int64) - 1).astype(np.int8)
+    lp = g.logpsi(theta, torch.from_numpy(states).to(DEV)).cpu().numpy()
+    g.close()
+    Hb = hcb.hcb_matrix(occ, e, tv, 1.0)
+    e0 = exact.lowest_eigenpairs(Hb, 1)[0][0]
+    ev = exact.variational_energy(exact.psi_from_logpsi(lp), Hb)
+    print(f"[gpu] hcb relu_ln t/V={tv}: E0 {e0:.6f}  exact E_v {ev:.6f} (rel {abs(ev - e0) / abs(e0):.2e})",
+          file=sys.stderr, flush=True)
+    assert abs(ev - e0) / abs(e0) < 1e-2
