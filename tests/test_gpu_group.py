@@ -112,3 +112,33 @@ def test_isgo_on_grouped_batch_equals_full_batch(mode):
         assert abs(ss[0] - st_full[0]) < 1e-12 * abs(st_full[0])
         assert abs(ss[2] - st_full[2]) < 1e-11 * st_full[2]
         assert np.max(np.abs(gg - g_full)) < 1e-11 * np.max(np.abs(g_full))
+
+
+def test_group_graph_replay():
+    # the grouping clears its table with fill kernels (no memset), so it can be captured
+    # and replayed: each replay on new rows copied into the captured input
+    n, e = w.kagome(2, 2)
+    B = 512
+    g = _ctx(n, e, B)
+    sp = torch.from_numpy(_dup_batch(B, n, 1, 100)).to(DEV)
+    u = torch.empty((B, n), dtype=torch.int8, device=DEV)
+    c = torch.empty(B, dtype=torch.float64, device=DEV)
+    nu = torch.empty(1, dtype=torch.int32, device=DEV)
+    g.group_duplicates(sp, u, c, nu)             # eager once before capture
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        g.set_stream(torch.cuda.current_stream())
+        g.group_duplicates(sp, u, c, nu)
+    g.set_stream(torch.cuda.current_stream())
+    for k in range(3):
+        s_new = _dup_batch(B, n, 10 + k, 50 + 100 * k)
+        sp.copy_(torch.from_numpy(s_new).to(DEV))
+        graph.replay()
+        torch.cuda.synchronize()
+        ru, rc, _ = oracle.group_duplicates(s_new)
+        U = int(nu.item())
+        assert U == len(ru) and np.array_equal(u[:U].cpu().numpy(), ru) and np.array_equal(c[:U].cpu().numpy(), rc)
+        g.group_duplicates(torch.from_numpy(s_new[::-1].copy()).to(DEV))   # eager work between replays
+        torch.cuda.synchronize()
+    g.close()

@@ -15,10 +15,10 @@ pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda", 0)
 
 
-def _ctx(n, e, F, L, prec, B, mode):
+def _ctx(n, e, F, L, prec, B, mode, act="tanh"):
     from paper_2011_12453_amd import GNA
-    print(f"[gpu] step ctx N={n} F={F} L={L} {prec} {mode} B={B}", file=sys.stderr, flush=True)
-    return GNA(n, e, F, L, tied=True, precision=prec, max_batch=B, device=DEV, eloc_mode=mode)
+    print(f"[gpu] step ctx N={n} F={F} L={L} {prec} {mode} {act} B={B}", file=sys.stderr, flush=True)
+    return GNA(n, e, F, L, tied=True, precision=prec, max_batch=B, device=DEV, eloc_mode=mode, activation=act)
 
 
 def _state(n, F, L, B, seed):
@@ -27,14 +27,15 @@ def _state(n, F, L, B, seed):
     return theta, spins
 
 
-@pytest.mark.parametrize("mode,prec", [("full", "fp64"), ("incremental", "fp64"), ("incremental", "bf16_1x"),
-                                       ("incremental", "bf16")])
-def test_step_equals_its_parts(mode, prec):
+@pytest.mark.parametrize("mode,prec,act", [("full", "fp64", "tanh"), ("incremental", "fp64", "tanh"),
+                                           ("incremental", "bf16_1x", "tanh"), ("incremental", "bf16", "tanh"),
+                                           ("incremental", "fp32", "relu_ln"), ("full", "bf16_1x", "relu_ln")])
+def test_step_equals_its_parts(mode, prec, act):
     # the step reuses the sweep's final log psi and (incremental) its planes as the
     # ISGO update's base pass: bitwise the same as calling the parts one by one
     n, e = w.kagome(6, 6)
     F, L, B, seed, lr = 32, 4, 32, 7, 1e-3
-    g = _ctx(n, e, F, L, prec, B, mode)
+    g = _ctx(n, e, F, L, prec, B, mode, act)
     th1, sp1 = _state(n, F, L, B, 3)
     th2, sp2 = th1.clone(), sp1.clone()
     lp1 = torch.empty(B, 2, dtype=torch.float64, device=DEV)
@@ -53,7 +54,8 @@ def test_step_equals_its_parts(mode, prec):
     g.close()
 
 
-@pytest.mark.parametrize("mode,prec", [("incremental", "bf16"), ("full", "fp32"), ("incremental", "fp64")])
+@pytest.mark.parametrize("mode,prec", [("incremental", "bf16"), ("full", "fp32"), ("incremental", "fp64"),
+                                       ("incremental", "bf16_1x")])
 def test_step_graph_replay_matches_eager(mode, prec):
     n, e = w.kagome(6, 6)
     F, L, B, seed, lr = 32, 4, 48, 11, 2e-3
