@@ -5,14 +5,19 @@
  * What the library computes (the paper: "Scalable variational Monte Carlo with
  * graph neural ansatz", Yang, Hu, Li; NeurIPS 2020 ML4PS workshop):
  *
- *   ansatz (Section 2, Eq. 1):  H0_i = tanh(onehot(x_i) W_e + b_e),
- *        H^{l+1} = tanh([A_hat H^l ; H^l] W + b),  A_hat = D^-1/2 A D^-1/2,
+ *   ansatz (Section 2, Eq. 1):  H0_i = f(onehot(x_i) W_e + b_e),
+ *        H^{l+1} = f([A_hat H^l ; H^l] W + b),  A_hat = D^-1/2 A D^-1/2,
  *        z = sum_i [H^L_i ; onehot(x_i)],  log psi = (v_a.z + c_a) + i (v_p.z + c_p)
- *        (the two-head complex form the paper names in Section 5);
+ *        (the two-head complex form the paper names in Section 5), with f = tanh
+ *        or the paper's ReLU followed by a layer normalisation (config field
+ *        activation);
  *   local energy (Section 3, E_x = sum_x' H_xx' Psi_x'/Psi_x) of the spin-1/2
  *        Heisenberg model:  E(s) = sum_<ij> [Jz s_i s_j/4
- *                                 + (Jxy/2)[s_i != s_j] psi(s^ij)/psi(s)];
- *   Metropolis spin-swap sampling of |psi|^2 (Section 3);
+ *                                 + (Jxy/2)[s_i != s_j] psi(s^ij)/psi(s)],
+ *        or any bond Hamiltonian of that form with a field and a constant per
+ *        bond, which covers the hard-core bosons of Eq. 4 (gna_set_couplings);
+ *   Metropolis spin-swap sampling of |psi|^2 (Section 3), and the grouping of
+ *        duplicated samples into unique states with counts (Section 3);
  *   ISGO gradient (Section 3, Eq. 3): samples drawn under psi_old reused with
  *        self-normalised weights p_x ~ n_x |psi_x|^2 / |psi_old,x|^2 and
  *        g = sum_x 2 p_x [Re(E_x - E) d log|psi_x| + Im(E_x - E) d phase_x].
@@ -31,7 +36,9 @@
  *   caller.  The library never frees or keeps them past the call.
  * - Every compute call only enqueues work on the context's stream and returns;
  *   none allocates device memory, synchronises, or copies device data to the
- *   host.  Results are valid once the stream has reached them.
+ *   host.  Results are valid once the stream has reached them.  The tuning call
+ *   gna_autotune is the exception (it synchronises and allocates for its own
+ *   duration).
  * - Argument and graph checks are synchronous: on failure the call returns a
  *   nonzero status, enqueues nothing, and gna_last_error() describes why.
  *   A launch failure returns GNA_HIP_ERROR.  Numerical trouble (non-finite
