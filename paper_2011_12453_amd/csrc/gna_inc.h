@@ -207,6 +207,9 @@ __device__ void inc_group(const Net& net, const IncNet& inc, const IncGeo& ig, c
     if (jobs.flags[w] & kJobSwap) v = (nd == ij.x) ? spw[ij.y] : ((nd == ij.y) ? spw[ij.x] : v);
     return v > 0 ? 1 : 0;
   };
+  // layer outputs of this wave's tiles: a tile belongs to the same wave at every
+  // layer, so H'^l of its rows in C_l stays in registers as the next layer's input
+  Acc hn[MAXT][NS];
   for (int l = 1; l <= Lr; ++l) {
     // ---- base G^{l-1} rows of the nodes at distance l+1 -> buffer (requested first,
     // stored after this wave's products)
@@ -257,7 +260,8 @@ __device__ void inc_group(const Net& net, const IncNet& inc, const IncGeo& ig, c
       tnd[k] = trow[k] < tcl[k] ? (int)x.tab[w * ig.tabw + trow[k]] : -1;
     }
     // ---- products: self -> registers, message -> buffer rows [0, |C_l|) in place
-    // layer input of tile k: embedding (l = 1), H'^{l-1} from the buffer, or base H^{l-1}
+    // layer input of tile k: embedding (l = 1), H'^{l-1} of the previous layer (this
+    // wave's registers), or base H^{l-1}
     auto load_in = [&](int k, Acc (&h)[NS]) {
       const int w = tsw[k], r = trow[k], nd = tnd[k];
       if (l == 1) {
@@ -265,7 +269,8 @@ __device__ void inc_group(const Net& net, const IncNet& inc, const IncGeo& ig, c
 #pragma unroll
         for (int i = 0; i < NS; ++i) h[i] = nd >= 0 ? x.semb[xs * F + P::lc(q, i)] : (Acc)0;
       } else if (r < tcp[k]) {
-        lds_read<Acc, NS>(x.buf + ((size_t)w * ig.rows + r) * ig.row_elems + q * NS, h);
+#pragma unroll
+        for (int i = 0; i < NS; ++i) h[i] = hn[k][i];
       } else if (nd >= 0) {
         gmem_read<Acc, NS>(planes + jobs.pboff[w] + (size_t)(l - 2) * plane + (size_t)nd * F + q * NS, h);
       } else {
@@ -311,7 +316,6 @@ __device__ void inc_group(const Net& net, const IncNet& inc, const IncGeo& ig, c
     // ---- gather, activation; readout difference at the last layer
     if (l == Lr && lane == 0)
       for (int w = 0; w < nsw; ++w) x.red[(2 * w) * kMaxWaves + wv] = x.red[(2 * w + 1) * kMaxWaves + wv] = 0.0;
-    Acc hn[MAXT][NS];
 #pragma unroll
     for (int k = 0; k < MAXT; ++k) {
       if (!tok[k]) continue;
@@ -393,15 +397,7 @@ __device__ void inc_group(const Net& net, const IncNet& inc, const IncGeo& ig, c
         lds_write<Acc, NS>(pw + (size_t)(l - 1) * plane + (size_t)nd * F + q * NS, hn[k]);
       }
     }
-    if (l < Lr) {
-      __syncthreads();   // every gather read of the buffers is done
-#pragma unroll
-      for (int k = 0; k < MAXT; ++k) {
-        if (!tok[k]) continue;
-        const int w = tsw[k], r = trow[k];
-        if (r < tcl[k]) lds_write<Acc, NS>(x.buf + ((size_t)w * ig.rows + r) * ig.row_elems + q * NS, hn[k]);
-      }
-    }
+    if (l < Lr) __syncthreads();   // every gather read of the buffers is done before new G rows
   }
 }
 
