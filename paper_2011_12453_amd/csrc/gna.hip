@@ -5,11 +5,14 @@
 //   k_logpsi         log psi of each sample (Eq. 1 + two-head readout)
 //   k_eloc           log psi of every bond-exchanged configuration, FP64
 //                    compensated sums of psi(s^ij)/psi(s) per (sample, bond chunk)
-//   k_eloc_finalize  diagonal term + chunk partials -> E_loc, evaluation count
+//   k_eloc_finalize  diagonal and field terms + chunk partials -> E_loc, evaluation count
 //   k_sweep          Metropolis spin-swap chains (Philox4x32-10 draws)
+//   k_inc_base, k_eloc_inc, k_sweep_inc   receptive-field (incremental) evaluation
+//                    of the local energy and the sampler's proposals (gna_inc.h)
 //   k_isgo_stats     ISGO weights, energy, variance, ESS, cotangents (FP64)
-//   k_vjp / k_vjp_reduce   reverse pass in FP64, deterministic reduction
+//   k_vjp_* / k_vjp_reduce   reverse pass (FP32, FP64 for FP64), deterministic reduction
 //   k_sgd            theta -= alpha * grad
+//   k_group_*        grouping of duplicated configurations with counts
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

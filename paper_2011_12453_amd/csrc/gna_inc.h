@@ -17,14 +17,15 @@
 // lockstep, layer by layer.  The balls are nested: the node list of a bond is
 // C_0, then the nodes at distance 1, 2, ... L, so C_l is a prefix of it.  Each
 // exchange owns one LDS buffer with a row per list position:
-//   - at the start of layer l, rows [0, |C_{l-1}|) hold H'^{l-1};
-//   - the layer's tiles (16 list positions each) read those rows (or base H^{l-1}
-//     for positions beyond |C_{l-1}|), form both products, and overwrite rows
-//     [0, |C_l|) with G^{l-1} in place; rows [|C_l|, |C_{l+1}|) receive base
-//     G^{l-1} rows, so that the gather reads only LDS (the list runs to C_{L+1});
-//   - after the gather, rows [0, |C_l|) receive H'^l.
+//   - the layer's tiles (16 list positions each) take H'^{l-1} of their rows in
+//     C_{l-1} from the registers of the previous layer (or base H^{l-1} for
+//     positions beyond |C_{l-1}|), form both products, and write rows [0, |C_l|)
+//     of the buffer with G^{l-1}; rows [|C_l|, |C_{l+1}|) receive base G^{l-1}
+//     rows, so that the gather reads only LDS (the list runs to C_{L+1});
+//   - the gather and the activation leave H'^l in the tile owner's registers.
 // Tile (job w, tile t) is owned by wave (t * njobs + w) % waves at every layer,
-// so a wave reads back only rows it wrote itself and a layer needs two barriers.
+// so a layer's outputs never cross waves, and a layer needs two barriers (the G
+// rows complete before the gather; the gather done before the next G rows).
 //
 // The same ball evaluation serves the Metropolis sampler (Section 3.2): there each
 // job belongs to its own chain, and the recomputed rows H'^l (C_l) and G'^{l-1}
