@@ -296,6 +296,8 @@ def main():
             GNA(n, e, F, L, tied=True, precision=prec, max_batch=Bp, device=dev, eloc_mode=mode)
         th0 = torch.from_numpy(theta_np).to(dev)
         sp0 = torch.from_numpy(spins_np[:Bp]).to(dev)
+        if gp is not g and mode == "incremental" and not args.no_tune:
+            log(f"[bench] autotune {prec}: {gp.autotune(th0, sp0)}")   # each precision in its own best shape
         el, nev = gp.local_energy(th0, sp0)        # warm
         torch.cuda.synchronize()
         gp.profile_read()
