@@ -68,14 +68,15 @@ enum {
   GNA_HIP_ERROR = 5      /* a HIP runtime call or kernel launch failed */
 };
 
-/* Arithmetic of the layer products (Eq. 1).  The log-psi differences, the local
+/* Arithmetic of the layer products (Eq. 1).  The readout (the per-node head dot
+ * products v . H^L and their sum over sites), the log-psi differences, the local
  * energy sums, the ISGO weights and statistics are FP64 in every mode.
  *   GNA_FP64: everything FP64 (MFMA f64).
  *   GNA_FP32: operands, aggregation and tanh FP32, FP32 MFMA accumulation.
  *   GNA_BF16: weights rounded to bfloat16; each FP32 activation enters the
  *             MFMA as the pair hi + lo of bfloat16 values (two products, about
  *             16 significant bits); aggregation, accumulation and tanh in FP32;
- *             the readout sum is taken in FP64 from the FP32 last-layer output.
+ *             the readout is taken in FP64 from the FP32 last-layer output.
  *   GNA_BF16_1X: as GNA_BF16 but each activation is rounded to the nearest
  *             bfloat16 and each product is a single MFMA (about 8 significant
  *             bits per operand).                                             */
@@ -100,7 +101,12 @@ enum { GNA_ELOC_FULL = 0, GNA_ELOC_INCREMENTAL = 1 };
  *                    normalisation over the F features of each node,
  *                    (y - mean y) / sqrt(var y + 1e-5), biased variance, no
  *                    affine parameters.  The row statistics are reduced in a
- *                    fixed order, so incremental and full evaluations agree. */
+ *                    fixed order, so incremental and full evaluations agree.
+ *                    Needs GNA_FP32 or GNA_FP64: with bfloat16 weights the
+ *                    normalised layers carry the weight rounding to the output
+ *                    at unit scale (about 0.1 per site at 432 sites, L = 6,
+ *                    F = 64), so gna_init returns GNA_UNSUPPORTED for GNA_BF16
+ *                    and GNA_BF16_1X with this activation.                    */
 enum { GNA_ACT_TANH = 0, GNA_ACT_RELU_LN = 1 };
 
 typedef struct {
@@ -238,10 +244,14 @@ gna_status gna_set_shape(gna_ctx *ctx, int32_t which, int32_t jobs_in_flight, in
  * context.                                                                   */
 int32_t gna_config_info(const gna_ctx *ctx, int32_t *info, int32_t n);
 
-/* Reverse pass: grad[P] = sum_x cot[x][0] d log|psi(s_x)|/dtheta
- *                         + cot[x][1] d phase(s_x)/dtheta   (overwritten).
- * Computed in FP64 for every precision mode; per-layer activations are
- * recomputed per sample, never stored for the whole batch.  cot: [B][2].   */
+/* Reverse pass of Eq. 1 and the readout, the vector-Jacobian product from
+ * which Eq. 2 and Eq. 3 form the energy gradient (Section 3):
+ *   grad[P] = sum_x cot[x][0] d log|psi(s_x)|/dtheta
+ *           + cot[x][1] d phase(s_x)/dtheta   (overwritten).
+ * The forward pass is recomputed per sample and its per-layer activations are
+ * held for the reverse pass (FP64 in GNA_FP64, FP32 in the other modes), at most
+ * act_budget_bytes of them at once: a larger batch is processed in chunks, whose
+ * per-parameter sums are accumulated in FP64.  cot: [B][2].                 */
 gna_status gna_logpsi_vjp(gna_ctx *ctx, const double *theta, const int8_t *spins,
                           int32_t B, const double *cot, double *grad);
 

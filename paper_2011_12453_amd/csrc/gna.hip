@@ -721,6 +721,7 @@ struct gna_ctx {
   std::vector<void*> owned;
   // kernel timing (gna_profile_enable)
   bool prof_on = false;
+  bool prof_err = false;        // an event could not be created or recorded since the last read
   struct Rec { const char* name; hipEvent_t a, b; };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> ev_pool;
@@ -754,19 +755,33 @@ hipEvent_t take_event(gna_ctx* c) {
   return e;
 }
 
-// Scope guard recording start/stop events around one launch when timing is on.
+// Scope guard recording start/stop events around one launch when timing is on.  A
+// failed event creation or record drops the launch from the record and marks it
+// (gna_profile_read then reports the failure instead of partial timings).
 struct Timed {
   gna_ctx* c;
   const char* name;
   hipEvent_t a = nullptr;
   Timed(gna_ctx* c_, const char* n) : c(c_), name(n) {
-    if (c->prof_on && (a = take_event(c))) hipEventRecord(a, c->stream);
+    if (!c->prof_on) return;
+    a = take_event(c);
+    if (!a) {
+      c->prof_err = true;
+    } else if (hipEventRecord(a, c->stream) != hipSuccess) {
+      c->ev_pool.push_back(a);
+      a = nullptr;
+      c->prof_err = true;
+    }
   }
   ~Timed() {
     if (!a) return;
     hipEvent_t b = take_event(c);
-    if (!b) return;
-    hipEventRecord(b, c->stream);
+    if (!b || hipEventRecord(b, c->stream) != hipSuccess) {
+      c->ev_pool.push_back(a);
+      if (b) c->ev_pool.push_back(b);
+      c->prof_err = true;
+      return;
+    }
     c->recs.push_back({name, a, b});
   }
 };
@@ -850,18 +865,9 @@ IncNet make_inc(const gna_ctx* c) {
   return inc;
 }
 
-// planes_ready (incremental mode): the planes and `base` already hold the base pass
-// of exactly these configurations under this theta (an incremental sweep just left
-// them so), and the base pass is skipped.
-gna_status run_eloc(gna_ctx* c, const double* theta, const int8_t* spins, int B, const double* base,
-                    double* eloc, long long* nev, bool planes_ready = false) {
-  {
-    Timed tm(c, "k_zero_i64");
-    hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, c->stream, nev, 1);
-  }
-  if (gna_status st = check_launch(c, "k_zero_i64")) return st;
-  if (B == 0) return GNA_OK;
-  // bonds per work item: enough items to balance the persistent grid
+// Bond chunks of the local energy's work items (item = sample x chunk of bonds):
+// enough items to balance the persistent grid, at most c->max_chunks per sample.
+void eloc_chunks(const gna_ctx* c, int B, int* n_chunks_out, int* chunk_out) {
   const long long work = (long long)B * std::max(1, c->E);
   long long chunk = work / (16LL * c->grid_eloc);
   chunk = std::max<long long>(16, std::min<long long>(chunk, std::max(1, c->E)));
@@ -878,11 +884,29 @@ gna_status run_eloc(gna_ctx* c, const double* theta, const int8_t* spins, int B,
     n_chunks = c->max_chunks;
     chunk = (c->E + n_chunks - 1) / n_chunks;
   }
-  int ichunk = (int)chunk;
+  *n_chunks_out = n_chunks;
+  *chunk_out = (int)chunk;
+}
+
+// planes_ready (incremental mode): the planes and `base` already hold the base pass
+// of exactly these configurations under this theta (an incremental sweep just left
+// them so), and the base pass is skipped.  partial / cnt: per-item scratch of at
+// least B * n_chunks entries (eloc_chunks); NULL selects the context's workspace.
+gna_status run_eloc(gna_ctx* c, const double* theta, const int8_t* spins, int B, const double* base,
+                    double* eloc, long long* nev, bool planes_ready = false, double* partial = nullptr,
+                    int* cnt = nullptr) {
+  {
+    Timed tm(c, "k_zero_i64");
+    hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, c->stream, nev, 1);
+  }
+  if (gna_status st = check_launch(c, "k_zero_i64")) return st;
+  if (B == 0) return GNA_OK;
+  int n_chunks = 1, ichunk = 1;
+  eloc_chunks(c, B, &n_chunks, &ichunk);
   Net net = make_net(c, theta);
   const int items = B * n_chunks;
-  double* partial = c->d_partial;
-  int* cnt = c->d_cnt;
+  if (!partial) partial = c->d_partial;
+  if (!cnt) cnt = c->d_cnt;
   if (c->eloc_mode == GNA_ELOC_INCREMENTAL) {
     void* planes = c->d_inc_planes;
     double* lp_out = const_cast<double*>(base);   // the base pass also yields log psi(s)
@@ -1093,15 +1117,21 @@ gna_status inc_configure(gna_ctx* c, IncShape shp, int which) {
       else if (F == 32) ik = inc_pick<PBF16W, 32>(tpw, nch, maxt, shp.wide);
       else ik = inc_pick<PBF16W, 64>(tpw, nch, maxt, shp.wide);
   }
+  bool attr_fail = false;
   auto occ2 = [&](const void* fn, int threads_, int lds) {
-    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) attr_fail = true;
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, threads_, lds) != hipSuccess || nb < 1) nb = 1;
     (void)hipGetLastError();
     return nb;
   };
+  const int g_base = c->n_cu * occ2(ik.base, 64 * c->geo.wpc, c->geo.lds_bytes);
+  const int g_el = (which & 1) ? c->n_cu * occ2(ik.eloc, 64 * ig.nw, ig.lds_bytes) : 0;
+  const int g_sw = (which & 2) ? c->n_cu * occ2(ik.sweep, 64 * ig.nw, ig.lds_bytes) : 0;
+  if (attr_fail)
+    return fail(c, GNA_HIP_ERROR, "hipFuncSetAttribute: the incremental kernels' LDS size was not accepted");
   c->ik.base = ik.base;   // the base pass does not depend on the shape
-  c->grid_inc_base = c->n_cu * occ2(ik.base, 64 * c->geo.wpc, c->geo.lds_bytes);
+  c->grid_inc_base = g_base;
   if (which & 1) {
     c->igeo = ig;
     c->ik.eloc = ik.eloc;
@@ -1109,14 +1139,14 @@ gna_status inc_configure(gna_ctx* c, IncShape shp, int which) {
     c->inc_maxt = maxt;
     c->inc_per_xcd = std::max(1, shp.per_xcd);
     c->inc_chunk_cap = std::min(chunk_cap, 64 * ig.nw);
-    c->grid_inc = c->n_cu * occ2(ik.eloc, 64 * ig.nw, ig.lds_bytes);
+    c->grid_inc = g_el;
   }
   if (which & 2) {
     c->igeo_sw = ig;
     c->ik.sweep = ik.sweep;
     c->inc_sw_wide = shp.wide;
     c->inc_sw_maxt = maxt;
-    c->grid_sweep_inc = c->n_cu * occ2(ik.sweep, 64 * ig.nw, ig.lds_bytes);
+    c->grid_sweep_inc = g_sw;
   }
   return GNA_OK;
 }
@@ -1150,6 +1180,13 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
   if (cfg->activation != GNA_ACT_TANH && cfg->activation != GNA_ACT_RELU_LN)
     return init_fail(GNA_INVALID_ARG, "unknown activation");
   if (cfg->reserved != 0) return init_fail(GNA_INVALID_ARG, "reserved must be 0");
+  // Six normalised layers carry the 8-bit rounding of bfloat16 weights to the
+  // output at unit scale (about 0.1 per site at 432 sites, L = 6, F = 64), far
+  // outside the BF16 accuracy bound of 1e-3 per site; this activation is served
+  // in FP32 and FP64 only.
+  if (cfg->activation == GNA_ACT_RELU_LN && (cfg->precision == GNA_BF16 || cfg->precision == GNA_BF16_1X))
+    return init_fail(GNA_UNSUPPORTED, "ReLU + layer normalisation needs FP32 or FP64 layer products "
+                                      "(bfloat16 weights miss the BF16 accuracy bound)");
   if (cfg->eloc_mode == GNA_ELOC_INCREMENTAL && !cfg->tied)
     return init_fail(GNA_UNSUPPORTED, "incremental local energy needs tied weights");
   if (cfg->eloc_mode == GNA_ELOC_INCREMENTAL && L < 1)
@@ -1262,8 +1299,10 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
       break;
   }
   const int threads = 64 * g.wpc;
+  bool attr_fail = false;
   auto occ = [&](const void* fn) {
-    hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, g.lds_bytes);
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, g.lds_bytes) != hipSuccess)
+      attr_fail = true;
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, threads, g.lds_bytes) != hipSuccess || nb < 1) nb = 1;
     (void)hipGetLastError();
@@ -1273,6 +1312,7 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
   c->grid_eloc = c->n_cu * occ(c->kern.eloc);
   c->grid_sweep = c->n_cu * occ(c->kern.sweep);
   c->max_chunks = std::max(1, (E + 7) / 8);
+  if (attr_fail) return bail(GNA_HIP_ERROR, "hipFuncSetAttribute: the evaluator's LDS size was not accepted");
 
   // ---- host graph tables: ELL (padding points at the node itself with value 0)
   std::vector<int> idx((size_t)g.npad * dmax);
@@ -1352,7 +1392,7 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
     c->vk = v64 ? vpick_f<PF64>(F, tpw, vnch) : vpick_f<PF32>(F, tpw, vnch);
     const int vthreads = 64 * c->vgeo.wpc;
     auto vocc = [&](const void* fn, int lds) {
-      hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+      if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) attr_fail = true;
       int nb = 0;
       if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, vthreads, lds) != hipSuccess || nb < 1) nb = 1;
       (void)hipGetLastError();
@@ -1360,6 +1400,7 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
     };
     c->vgrid_fwd = c->n_cu * vocc(c->vk.fwd, c->vgeo.lds_bytes);
     c->vgrid_dx = c->n_cu * vocc(c->vk.dx, (int)vw_bytes);
+    if (attr_fail) return bail(GNA_HIP_ERROR, "hipFuncSetAttribute: the reverse pass's LDS size was not accepted");
     c->vjp_rows = 2 * c->n_cu;
     c->nplanes = 2 * L + 5 + (c->act ? L : 0);   // + post-ReLU rows Y^1..Y^L
     const int64_t per_sample = (int64_t)c->nplanes * c->vgeo.npad * F * (int64_t)c->sz_Acc;
@@ -1735,16 +1776,25 @@ gna_status gna_autotune(gna_ctx* c, const double* theta, const int8_t* spins, in
       if (which == 2 && sh.per_xcd != 1) continue;   // the sweep has no per-XCD sample split
       if (inc_configure(c, sh, which) != GNA_OK) continue;
       if ((st = run()) != GNA_OK) return;   // warm
-      (void)hipEventRecord(e0, c->stream);
+      if (hipEventRecord(e0, c->stream) != hipSuccess) {
+        st = fail(c, GNA_HIP_ERROR, "hipEventRecord failed");
+        return;
+      }
       for (int r = 0; r < 2 && st == GNA_OK; ++r) st = run();
-      (void)hipEventRecord(e1, c->stream);
       if (st != GNA_OK) return;
+      if (hipEventRecord(e1, c->stream) != hipSuccess) {
+        st = fail(c, GNA_HIP_ERROR, "hipEventRecord failed");
+        return;
+      }
       if (hipEventSynchronize(e1) != hipSuccess) {
         st = fail(c, GNA_HIP_ERROR, "hipEventSynchronize failed");
         return;
       }
       float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        st = fail(c, GNA_HIP_ERROR, "hipEventElapsedTime failed");
+        return;
+      }
       if (*best_ms < 0.f || ms < *best_ms) {
         *best_ms = ms;
         *best = sh;
@@ -1880,10 +1930,12 @@ gna_status gna_profile_enable(gna_ctx* c, int32_t on) {
 int32_t gna_profile_read(gna_ctx* c, int32_t max_entries, char* names, int64_t* launches, double* total_ms) {
   if (!c || max_entries < 0 || (max_entries > 0 && (!names || !launches || !total_ms))) return -1;
   if (hipStreamSynchronize(c->stream) != hipSuccess) return -1;
+  bool bad = c->prof_err;
+  c->prof_err = false;
   std::vector<std::pair<std::string, std::pair<int64_t, double>>> agg;
   for (auto& r : c->recs) {
     float ms = 0.f;
-    hipEventElapsedTime(&ms, r.a, r.b);
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) bad = true;
     size_t k = 0;
     while (k < agg.size() && agg[k].first != r.name) ++k;
     if (k == agg.size()) agg.push_back({r.name, {0, 0.0}});
@@ -1893,6 +1945,10 @@ int32_t gna_profile_read(gna_ctx* c, int32_t max_entries, char* names, int64_t* 
     c->ev_pool.push_back(r.b);
   }
   c->recs.clear();
+  if (bad) {
+    c->err = "kernel timing: an event could not be created, recorded or read";
+    return -1;
+  }
   const int n = (int)agg.size();
   for (int k = 0; k < n && k < max_entries; ++k) {
     std::strncpy(names + 64 * k, agg[k].first.c_str(), 63);

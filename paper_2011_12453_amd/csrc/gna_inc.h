@@ -27,7 +27,7 @@
 // so a layer's outputs never cross waves, and a layer needs two barriers (the G
 // rows complete before the gather; the gather done before the next G rows).
 //
-// The same ball evaluation serves the Metropolis sampler (Section 3.2): there each
+// The same ball evaluation serves the Metropolis sampler (Section 3): there each
 // job belongs to its own chain, and the recomputed rows H'^l (C_l) and G'^{l-1}
 // (C_{l-1}) are written into that chain's planes as they are produced.  Rows read
 // later in the same evaluation are never among the rows written before them
@@ -92,7 +92,7 @@ struct IncLds {
   double* red;                 // [kIncMaxSwaps][2][kMaxWaves]
   typename P::Acc* sbias;
   typename P::Acc* semb;
-  typename P::Acc* shead;      // [2][F] readout weights v_a, v_p in Acc, slot order
+  double* shead;               // [2][F] readout weights v_a, v_p (FP64), slot order
   typename P::Acc* sev;
   int* slist;
   int4* cpy;                   // ring-row copy list of the group: (source offset lo, hi, LDS destination, 0)
@@ -105,7 +105,7 @@ struct IncLds {
     red = reinterpret_cast<double*>(smem + ig.off_red);
     sbias = reinterpret_cast<Acc*>(smem + ig.off_bias);
     semb = reinterpret_cast<Acc*>(smem + ig.off_emb);
-    shead = reinterpret_cast<Acc*>(smem + ig.off_head);
+    shead = reinterpret_cast<double*>(smem + ig.off_head);
     sev = reinterpret_cast<Acc*>(smem + ig.off_ev);
     slist = reinterpret_cast<int*>(smem + ig.off_list);
     cpy = reinterpret_cast<int4*>(smem + ig.off_cpy);
@@ -126,8 +126,8 @@ __device__ void inc_stage(const Net& net, const IncNet& inc, const IncLds<P>& x)
   for (int k = threadIdx.x; k < 2 * F; k += bd) x.semb[k] = reinterpret_cast<const Acc*>(net.emb)[k];
   for (int k = threadIdx.x; k < F; k += bd) {
     const int f = P::lc(k / NS, k % NS);
-    x.shead[k] = (Acc)net.head_a[f];
-    x.shead[F + k] = (Acc)net.head_p[f];
+    x.shead[k] = net.head_a[f];
+    x.shead[F + k] = net.head_p[f];
   }
   const Acc* ev = reinterpret_cast<const Acc*>(inc.ell_val);
   for (int k = threadIdx.x; k < net.n * inc.dmax; k += bd) x.sev[k] = ev[k];
@@ -327,9 +327,9 @@ __device__ void inc_group(const Net& net, const IncNet& inc, const IncGeo& ig, c
       Acc* pw = planes + jobs.pboff[w];
       const bool last = l == Lr;
       const bool rd = last && (jobs.flags[w] & kJobReadout);
-      Acc r0[2] = {(Acc)0, (Acc)0};   // base readout partials of the node
+      double r0[2] = {0.0, 0.0};   // base readout partials of the node (FP64)
       if (rd && nd >= 0) {
-        const Acc* rp = pw + (size_t)(Lr - 1) * plane + (size_t)nd * 8 + q * 2;
+        const double* rp = reinterpret_cast<const double*>(pw + (size_t)(Lr - 1) * plane) + (size_t)nd * 8 + q * 2;
         r0[0] = rp[0];
         r0[1] = rp[1];
       }
@@ -370,19 +370,18 @@ __device__ void inc_group(const Net& net, const IncNet& inc, const IncGeo& ig, c
         relu_ln_row<Acc, NS>(pre, y, hn[k]);
       }
       if (last && (rd || WRITE)) {   // wave-uniform
-        // readout partials of this node, formed as in the full evaluation
-        Acc va[NS], vp[NS];
-        lds_read<Acc, NS>(x.shead + q * NS, va);
-        lds_read<Acc, NS>(x.shead + F + q * NS, vp);
-        Acc ta1 = 0, tp1 = 0;
+        // FP64 readout partials of this node, formed as in the full evaluation
+        const double* va = x.shead + q * NS;
+        const double* vp = x.shead + F + q * NS;
+        double ta1 = 0, tp1 = 0;
 #pragma unroll
         for (int i = 0; i < NS; ++i) {
-          ta1 += va[i] * hn[k][i];
-          tp1 += vp[i] * hn[k][i];
+          ta1 += va[i] * (double)hn[k][i];
+          tp1 += vp[i] * (double)hn[k][i];
         }
         if (rd) {
-          double pa = nd >= 0 ? (double)ta1 - (double)r0[0] : 0.0;
-          double pp = nd >= 0 ? (double)tp1 - (double)r0[1] : 0.0;
+          double pa = nd >= 0 ? ta1 - r0[0] : 0.0;
+          double pp = nd >= 0 ? tp1 - r0[1] : 0.0;
           pa = wave_sum_dpp(pa);
           pp = wave_sum_dpp(pp);
           if (lane == 0) {
@@ -391,8 +390,8 @@ __device__ void inc_group(const Net& net, const IncNet& inc, const IncGeo& ig, c
           }
         }
         if (WRITE && nd >= 0) {   // after the base partials were read
-          const Acc rv[2] = {ta1, tp1};
-          lds_write<Acc, 2>(pw + (size_t)(Lr - 1) * plane + (size_t)nd * 8 + q * 2, rv);
+          const double rv[2] = {ta1, tp1};
+          lds_write<double, 2>(reinterpret_cast<double*>(pw + (size_t)(Lr - 1) * plane) + (size_t)nd * 8 + q * 2, rv);
         }
       } else if (WRITE && !last && nd >= 0) {   // H^l changed on C_l
         lds_write<Acc, NS>(pw + (size_t)(l - 1) * plane + (size_t)nd * F + q * NS, hn[k]);
@@ -511,7 +510,7 @@ __global__ __launch_bounds__(NT) void k_eloc_inc(Net net, IncNet inc, IncGeo ig,
   }
 }
 
-// Metropolis spin-swap sweeps (Section 3.2) with incremental proposals.  Slot w of
+// Metropolis spin-swap sweeps (Section 3) with incremental proposals.  Slot w of
 // block x runs chains x + (w + S k) * gridDim.x one after the other; the draws are
 // the ones of the full-recompute sampler (Philox4x32-10, counter (step, chain, 0),
 // key = seed), and a proposal is accepted when u < exp(2 Re Delta).  The chains'

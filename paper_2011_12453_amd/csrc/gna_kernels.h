@@ -521,9 +521,9 @@ __device__ void load_spins(const Net& net, const Smem<P>& s, const int8_t* __res
 //   also the post-ReLU rows Y^l (l = 1..L) as planes 2L + 4 + l.
 //   STORE == 2: write the base planes of the incremental local energy: layer
 //   outputs H^1..H^{L-1} as planes 0..L-2, the layer-L readout partials (per
-//   node and lane quad q, the pair (t_a, t_p) of Acc sums v . H^L over the
-//   quad's slots) in plane L-1 at node * 8 + q * 2, and message products
-//   G^l = H^l W_msg (l = 0..L-1) as planes L..2L-1, same element order.
+//   node and lane quad q, the pair (t_a, t_p) of FP64 sums v . H^L over the
+//   quad's slots) in plane L-1 as doubles at node * 8 + q * 2, and message
+//   products G^l = H^l W_msg (l = 0..L-1) as planes L..2L-1, same element order.
 // ---------------------------------------------------------------------------
 template <class P, int F, int TPW, int NCH, int STORE = 0>
 __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
@@ -746,9 +746,10 @@ __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
     const bool last = (l == net.L - 1);
 #pragma unroll
     for (int k = 0; k < TPW; ++k) {
-      // readout partial of this node in Acc: identical inputs give identical
-      // partials, so unchanged nodes still cancel exactly in log psi differences
-      Acc ta = 0, tp = 0;
+      // readout partial of this node (its lane group's slots) in FP64: identical
+      // inputs give identical partials, so unchanged nodes still cancel exactly in
+      // log psi differences
+      double ta = 0, tp = 0;
       if (net.act == 0) {
 #pragma unroll
         for (int t = 0; t < MT; ++t) {
@@ -756,11 +757,6 @@ __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
           for (int r = 0; r < 4; ++r) {
             const Acc v = P::act(acc[k][t][r]);
             h[k][4 * t + r] = v;
-            if (last) {
-              const int f = P::lc(q, 4 * t + r);
-              ta += (Acc)head_a[f] * v;
-              tp += (Acc)head_p[f] * v;
-            }
           }
         }
       } else {
@@ -773,25 +769,25 @@ __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
         if constexpr (STORE == 1) {
           if (tile_ok[k]) lds_write<Acc, NS>(store + (2 * net.L + 5 + l) * plane + node[k] * F + q * NS, y);
         }
-        if (last) {
+      }
+      if (last) {
 #pragma unroll
-          for (int i = 0; i < NS; ++i) {
-            const int f = P::lc(q, i);
-            ta += (Acc)head_a[f] * h[k][i];
-            tp += (Acc)head_p[f] * h[k][i];
-          }
+        for (int i = 0; i < NS; ++i) {
+          const int f = P::lc(q, i);
+          ta += head_a[f] * (double)h[k][i];
+          tp += head_p[f] * (double)h[k][i];
         }
       }
       if (last && real[k]) {
-        pa += (double)ta;
-        pp += (double)tp;
+        pa += ta;
+        pp += tp;
       }
       if constexpr (STORE == 2) {
         if (!last) {
           lds_write<Acc, NS>(store + l * plane + node[k] * F + q * NS, h[k]);
-        } else if (tile_ok[k]) {   // layer L: the node's readout partials, not its row
-          const Acc rv[2] = {ta, tp};
-          lds_write<Acc, 2>(store + l * plane + node[k] * 8 + q * 2, rv);
+        } else if (tile_ok[k]) {   // layer L: the node's FP64 readout partials, not its row
+          const double rv[2] = {ta, tp};
+          lds_write<double, 2>(reinterpret_cast<double*>(store + l * plane) + node[k] * 8 + q * 2, rv);
         }
       }
     }

@@ -95,6 +95,15 @@ def test_incremental_needs_layers(lib):
     assert b"n_layers" in lib.gna_last_error(None)
 
 
+@pytest.mark.parametrize("precision", [2, 3])
+def test_relu_ln_refused_with_bfloat16_products(lib, precision):
+    # bfloat16 weights miss the BF16 accuracy bound under ReLU + layer normalisation
+    c, keep = _cfg(precision=precision, activation=1)
+    out = ctypes.c_void_p()
+    assert lib.gna_init(ctypes.byref(c), ctypes.byref(out)) == 3 and not out.value
+    assert b"layer normalisation" in lib.gna_last_error(None)
+
+
 def test_null_arguments(lib):
     out = ctypes.c_void_p()
     assert lib.gna_init(None, ctypes.byref(out)) == 1

@@ -21,7 +21,7 @@ def test_stored_traffic_follows_the_source_hash(tmp_path, monkeypatch):
     import bench
     prof = tmp_path / "profiles"
     prof.mkdir()
-    f = prof / "k_x_kagome432_bf16_1x_hbm_traffic.md"
+    f = prof / "k_x_kagome432_L6F64_bf16_1x_hbm_traffic.md"
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     monkeypatch.setattr(bench, "source_hash", lambda: "abcd")
     assert bench.stored_traffic("kagome432_L6F64", "bf16_1x", "k_x") is None          # no summary

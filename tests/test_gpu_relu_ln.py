@@ -1,10 +1,13 @@
 """GPU parity of the paper's own nonlinearity (Section 2: ReLU followed by a layer
 normalisation over the F features of a node) against the FP64 oracle: log psi and
-the local energy in every precision, the incremental local energy and sampler
+the local energy in FP64 and FP32, the incremental local energy and sampler
 against the full ones, the reverse pass and the ISGO gradient.
 
-Tolerances follow the tanh tests: energy per site FP64 1e-10, FP32 1e-5, BF16 1e-3
-at Glorot weights; per-sample bounds are looser where stated, with the reason.
+Tolerances follow the tanh tests: energy per site FP64 1e-10, FP32 1e-5; per-sample
+bounds are looser where stated, with the reason.  Every comparison gives the oracle
+exactly the parameters the GPU receives.  The library refuses this activation with
+bfloat16 layer products (its 8-bit weights miss the BF16 bound at unit-scale
+normalised layers); that refusal is checked without a GPU in test_abi.py.
 """
 import sys
 
@@ -46,18 +49,7 @@ def _site_err(got, ref, n):
     return abs(e - r) / max(abs(r), 1e-2)
 
 
-def _bf16_weights(theta, F, L, tied):
-    """theta with the layer weights W rounded as the BF16 kernels store them
-    (FP64 -> FP32 -> BF16, round to nearest even); all else unchanged."""
-    sl = w.param_slices(F, L, tied)
-    out = theta.copy()
-    a, b = sl["W"]
-    wr = torch.from_numpy(theta[a:b].astype(np.float32)).to(torch.bfloat16).to(torch.float64)
-    out[a:b] = wr.numpy()
-    return out
-
-
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_logpsi_and_local_energy_match_oracle(case, prec):
     name, build, F, L, tied, B = case
@@ -79,27 +71,11 @@ def test_logpsi_and_local_energy_match_oracle(case, prec):
     site = _site_err(el[:, 0], el_ref.real, n)
     print(f"[gpu] relu_ln {name} {prec}: logpsi rel {lp_err:.2e} eloc rel {el_err:.2e} e/site rel {site:.2e}",
           file=sys.stderr, flush=True)
-    # BF16 stores W with 8 significant bits: a fixed perturbation of the ansatz
-    # whose energy shift does not average out over samples; the normalisation
-    # keeps it at unit scale where tanh would compress it.  The 1e-3 per-site
-    # bound holds at the 432-site workload (test_full_size_sampled_parity); here
-    # the BF16 path is pinned tightly against the oracle on the rounded weights.
-    tol = {"fp64": (1e-12, 1e-11, 1e-10), "fp32": (1e-5, 1e-4, 1e-5), "bf16": (2e-2, 1e-1, 1e-2)}[prec]
+    tol = {"fp64": (1e-12, 1e-11, 1e-10), "fp32": (1e-5, 1e-4, 1e-5)}[prec]
     assert lp_err < tol[0] and el_err < tol[1] and site < tol[2]
-    if prec == "bf16":
-        thr = _bf16_weights(theta, F, L, tied)
-        lp_r = oracle.logpsi(thr, spins, n, e, F, L, tied, act=ACT)
-        el_r = oracle.local_energy(thr, spins, n, e, F, L, tied, act=ACT)
-        lp_e = np.max(np.abs(lp - lp_r)) / max(1.0, np.max(np.abs(lp_r)))
-        el_e = np.max(np.abs(el[:, 0] - el_r.real) + np.abs(el[:, 1] - el_r.imag)) / max(1.0, np.max(np.abs(el_r)))
-        site_r = _site_err(el[:, 0], el_r.real, n)
-        print(f"[gpu] relu_ln {name} bf16 vs rounded-W oracle: logpsi rel {lp_e:.2e} eloc rel {el_e:.2e} "
-              f"e/site rel {site_r:.2e}", file=sys.stderr, flush=True)
-        # what remains is the activations' 16-bit split and FP32 accumulation
-        assert lp_e < 1e-4 and el_e < 1e-2 and site_r < 5e-4
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("case", [c for c in CASES if c[4]], ids=[c[0] for c in CASES if c[4]])
 def test_incremental_local_energy_equals_full(case, prec):
     name, build, F, L, tied, B = case
@@ -123,10 +99,10 @@ def test_incremental_local_energy_equals_full(case, prec):
     assert np.max(np.abs(ei - ef)) < 1e-12 * scale
     err = np.max(np.abs(ei[:, 0] - ref.real) + np.abs(ei[:, 1] - ref.imag)) / scale
     print(f"[gpu] relu_ln incremental {name} {prec}: eloc rel {err:.2e}", file=sys.stderr, flush=True)
-    assert err < {"fp64": 1e-11, "fp32": 1e-4, "bf16": 2e-1}[prec]
+    assert err < {"fp64": 1e-11, "fp32": 1e-4}[prec]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "bf16"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_incremental_sampler_matches_full_sampler(prec):
     n, e = w.kagome(6, 6)
     F, L = 32, 4
@@ -178,7 +154,7 @@ def test_vjp_matches_oracle(tied):
     assert err < 1e-11
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32"])
 def test_vjp_reduced_precision(prec):
     n, e = w.kagome(6, 6)
     F, L = 32, 4
@@ -191,9 +167,8 @@ def test_vjp_reduced_precision(prec):
     ref = oracle.logpsi_vjp(theta, spins, cot, n, e, F, L, True, act_fn=ACT)
     err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
     print(f"[gpu] relu_ln vjp {prec}: rel norm {err:.2e}", file=sys.stderr, flush=True)
-    # the reverse pass runs in the precision's accumulator type (FP32 for both);
-    # BF16 forward planes carry the weight rounding of the forward pass
-    assert err < {"fp32": 1e-5, "bf16": 3e-2}[prec]
+    # the reverse pass runs in FP32 in this mode
+    assert err < 1e-5
 
 
 @pytest.mark.parametrize("mode", ["full", "incremental"])
@@ -223,38 +198,35 @@ def test_isgo_grad_hard_core_bosons_matches_oracle(mode):
     assert stats[3] == pytest.approx(rs["ess"], rel=1e-12) and stats[6] == rs["n_evals"]
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
-def test_full_size_sampled_parity(prec):
-    # 432-site Kagome, 6 tied layers of width 64, incremental local energy
+@pytest.mark.parametrize("bias_std", [0.0, 0.1])
+def test_full_size_sampled_parity(bias_std):
+    # 432-site Kagome, 6 tied layers of width 64, incremental local energy, FP32,
+    # the whole batch of 64 in one launch; the oracle checks sampled rows on the
+    # same parameters
     p = w.preset("kagome432_L6F64")
     n, e = p.build_graph()
     F, L = p.n_features, p.n_layers
-    theta = w.glorot_theta(F, L, True, seed=p.theta_seed)
+    theta = w.glorot_theta(F, L, True, seed=p.theta_seed, bias_std=bias_std)
     spins = w.random_sz0_spins(64, n, p.spin_seed)
-    g = _ctx(n, e, F, L, True, prec, 64, "incremental")
+    g = _ctx(n, e, F, L, True, "fp32", 64, "incremental")
     el, nev = g.local_energy(_dev(theta), _dev(spins))
     el = el.cpu().numpy()
+    lp = g.logpsi(_dev(theta), _dev(spins)).cpu().numpy()
     g.close()
     assert int(nev.item()) == oracle.n_evals(spins, e)
-    rows = np.random.default_rng(4).choice(64, size=2, replace=False)
-
-    def errs(th):
-        ref = oracle.local_energy(th, spins[rows], n, e, F, L, act=ACT)
-        err = np.max(np.abs(el[rows, 0] - ref.real) + np.abs(el[rows, 1] - ref.imag)) / np.max(np.abs(ref))
-        return err, _site_err(el[rows, 0], ref.real, n)
-
-    err, site = errs(theta)
-    print(f"[gpu] relu_ln kagome432 {prec}: sampled eloc rel {err:.2e} e/site rel {site:.2e}",
-          file=sys.stderr, flush=True)
-    if prec == "fp32":
-        assert site < 1e-5 and err < 1e-4
-    else:
-        # six normalised layers carry the 8-bit rounding of W to the output at
-        # unit scale: against the exact weights BF16 misses the 1e-3 per-site bound
-        # (reported above); against the rounded weights it is the FP32-accumulated
-        # evaluation of that ansatz, within the BF16 per-site bound (the 16-bit
-        # activations and FP32 sums leave a few 1e-4 after six layers)
-        err_r, site_r = errs(_bf16_weights(theta, F, L, True))
-        print(f"[gpu] relu_ln kagome432 bf16 vs rounded-W oracle: eloc rel {err_r:.2e} e/site rel {site_r:.2e}",
-              file=sys.stderr, flush=True)
-        assert site_r < 1e-3 and err_r < 1e-3
+    rows = np.random.default_rng(4).choice(64, size=4, replace=False)
+    ref = oracle.local_energy(theta, spins[rows], n, e, F, L, act=ACT)
+    lp_ref = oracle.logpsi(theta, spins[rows], n, e, F, L, act=ACT)
+    err = np.max(np.abs(el[rows, 0] - ref.real) + np.abs(el[rows, 1] - ref.imag)) / np.max(np.abs(ref))
+    site = _site_err(el[rows, 0], ref.real, n)
+    # the part of E_loc a constant psi would get wrong: the off-diagonal sum
+    off = np.abs(ref - len(e) / 4.0)
+    off_err = np.max(np.abs(el[rows, 0] + 1j * el[rows, 1] - ref)) / np.max(off)
+    lp_err = np.max(np.abs(lp[rows] - lp_ref))
+    print(f"[gpu] relu_ln kagome432 fp32 bias {bias_std}: sampled eloc rel {err:.2e} e/site rel {site:.2e} "
+          f"off-diagonal err/part {off_err:.2e} logpsi abs {lp_err:.2e}", file=sys.stderr, flush=True)
+    # with biases the post-ReLU rows are less sparse and the normalisation divides
+    # by smaller deviations, which amplifies FP32 rounding through six layers: 2.8e-5
+    # per site measured, against 1e-5 at the workload's zero-bias initialisation
+    assert site < (1e-5 if bias_std == 0.0 else 1e-4)
+    assert err < 1e-4 and off_err < 1e-3 and lp_err < 1e-3

@@ -1,7 +1,8 @@
 """The sampling-iteration loop of Section 3 through the library: grouped duplicates
 give the same trajectory as the full batch, a run resumed from a checkpoint is the
 uninterrupted run, and parameters trained on 12 sites start larger lattices
-(Section 4.2's transfer), checked against the oracle at 432 sites."""
+(Section 4.2's transfer) at 108 and 432 sites, the transferred ansatz checked
+against the oracle on each."""
 import sys
 
 import numpy as np
@@ -80,27 +81,35 @@ def test_transfer_from_12_sites():
     g12.set_hard_core_bosons(0.5, 1.0)
     th, sp = _start(n12, F, L, 1024, 0)
     isgo_vmc(g12, th, sp, n_iters=30, n_updates=5, lr=0.1, n_sweeps=2, seed=17, group=True)
-    # 108 sites: energy per site at the transferred and at a fresh start, same chains
-    n, e = w.kagome(6, 6)
-    B = 512
-    res = {}
-    for name in ("fresh", "transferred"):
-        g = _ctx(n, e, F, L, "fp32", B)
-        g.set_hard_core_bosons(0.5, 1.0)
-        t0, s0 = _start(n, F, L, B, 1)
-        if name == "transferred":
-            t0 = transfer_theta(th, g12, g)
-        hist, _ = isgo_vmc(g, t0, s0, n_iters=1, n_updates=1, lr=0.0, n_sweeps=4, burn_in=20, seed=3)
-        res[name] = hist[0]["energy_per_site"]
-        if name == "transferred":
-            # parity of the transferred ansatz on the larger graph (two sampled rows)
-            rows = s0[:2].cpu().numpy()
-            el, _ = g.local_energy(t0, s0[:2].contiguous())
-            jz, jxy, hb_, cb = hcb.spin_couplings(0.5, 1.0)
-            ref = oracle.local_energy(t0.cpu().numpy(), rows, n, e, F, L, jz=jz, jxy=jxy, hb=hb_, cb=cb)
-            assert np.max(np.abs(el.cpu().numpy()[:, 0] - ref.real)) < 1e-4 * np.max(np.abs(ref))
-        g.close()
+    jz, jxy, hb_, cb = hcb.spin_couplings(0.5, 1.0)
+    # 108 and 432 sites: energy per site at the transferred and at a fresh start,
+    # same chains, and the transferred ansatz against the oracle on sampled rows
+    for cells in (6, 12):
+        n, e = w.kagome(cells, cells)
+        B = 512
+        res = {}
+        for name in ("fresh", "transferred"):
+            g = _ctx(n, e, F, L, "fp32", B)
+            g.set_hard_core_bosons(0.5, 1.0)
+            t0, s0 = _start(n, F, L, B, 1)
+            if name == "transferred":
+                t0 = transfer_theta(th, g12, g)
+            hist, _ = isgo_vmc(g, t0, s0, n_iters=1, n_updates=1, lr=0.0, n_sweeps=4, burn_in=20, seed=3)
+            res[name] = hist[0]["energy_per_site"]
+            if name == "transferred":
+                rows = s0[:3].contiguous()
+                el, _ = g.local_energy(t0, rows)
+                lp = g.logpsi(t0, rows).cpu().numpy()
+                rows = rows.cpu().numpy()
+                ref = oracle.local_energy(t0.cpu().numpy(), rows, n, e, F, L, jz=jz, jxy=jxy, hb=hb_, cb=cb)
+                lp_ref = oracle.logpsi(t0.cpu().numpy(), rows, n, e, F, L)
+                el = el.cpu().numpy()
+                err = np.max(np.abs(el[:, 0] - ref.real) + np.abs(el[:, 1] - ref.imag)) / np.max(np.abs(ref))
+                print(f"[gpu] transfer 12 -> {n} sites: E_loc rel {err:.2e}, log psi abs "
+                      f"{np.max(np.abs(lp - lp_ref)):.2e}", file=sys.stderr, flush=True)
+                assert err < 1e-5 and np.max(np.abs(lp - lp_ref)) < 1e-3
+            g.close()
+        print(f"[gpu] transfer 12 -> {n} sites: energy per site fresh {res['fresh']:.5f}, "
+              f"transferred {res['transferred']:.5f}", file=sys.stderr, flush=True)
+        assert res["transferred"] < res["fresh"]
     g12.close()
-    print(f"[gpu] transfer 12 -> 108 sites: energy per site fresh {res['fresh']:.5f}, "
-          f"transferred {res['transferred']:.5f}", file=sys.stderr, flush=True)
-    assert res["transferred"] < res["fresh"]
