@@ -165,6 +165,24 @@ gna_status gna_logpsi(gna_ctx *ctx, const double *theta, const int8_t *spins,
 gna_status gna_local_energy(gna_ctx *ctx, const double *theta, const int8_t *spins,
                             int32_t B, double *eloc, int64_t *n_evals);
 
+/* gna_local_energy for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same kernels and results, with the call's scratch (base log psi, per-work-item
+ * partial sums and counts, and the evaluation counter when n_evals is NULL) in a
+ * static device array of the library, 16 MiB on each GPU it runs on, held until
+ * the process ends, instead of the context's workspace.  The call performs no
+ * allocation of any kind; the context's persistent buffers (weight fragments,
+ * and in GNA_ELOC_INCREMENTAL mode the base planes) come from gna_init.
+ * Arguments as gna_local_energy.  GNA_INVALID_ARG, with nothing enqueued, when B
+ * needs more scratch than the array holds (about B * (16 + 36 * bond chunks)
+ * bytes; 2048 samples of the 432-site Kagome workload need under 10 MiB).
+ * Every call on one GPU shares that GPU's array: calls that overlap in time on
+ * one GPU (two streams, two host threads, two contexts) race and must be
+ * serialised by the caller.  GNA_HIP_ERROR if the array's address could not be
+ * obtained at gna_init.                                                      */
+gna_status gna_local_energy_noalloc(gna_ctx *ctx, const double *theta, const int8_t *spins,
+                                    int32_t B, double *eloc, int64_t *n_evals);
+
 /* n_sweeps * N Metropolis proposals per chain (one chain per row; Section 3's
  * Markov chain for |psi|^2).  Proposal k of chain b draws one Philox4x32-10
  * block with counter (low32(t), high32(t), b, 0), t = counter_base + k, and key

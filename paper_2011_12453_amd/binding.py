@@ -51,6 +51,8 @@ _EXPORTS = {
                                     ctypes.c_void_p]),
     "gna_local_energy": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                           ctypes.c_void_p, ctypes.c_void_p]),
+    "gna_local_energy_noalloc": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                  ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "gna_metropolis_sweep": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                               ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                               ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p]),
@@ -193,6 +195,18 @@ class GNA:
         nev = self._empty((1,), torch.int64) if n_evals is None else self._t(n_evals, torch.int64, (1,), "n_evals")
         self._check(self._lib.gna_local_energy(self._ctx, _ptr(theta), _ptr(spins), B, _ptr(out), _ptr(nev)))
         return out, nev
+
+    def local_energy_noalloc(self, theta, spins, out, n_evals=None):
+        """``gna_local_energy_noalloc``: as ``local_energy`` with the library's static
+        scratch; ``out`` [B, 2] (and ``n_evals`` [1] int64, optional) are caller-owned."""
+        theta, spins = self._theta(theta), self._spins(spins)
+        B = spins.shape[0]
+        out = self._t(out, torch.float64, (B, 2), "out")
+        if n_evals is not None:
+            n_evals = self._t(n_evals, torch.int64, (1,), "n_evals")
+        self._check(self._lib.gna_local_energy_noalloc(self._ctx, _ptr(theta), _ptr(spins), B, _ptr(out),
+                                                       _ptr(n_evals)))
+        return out, n_evals
 
     def metropolis_sweep(self, theta, spins, logpsi, n_sweeps: int, seed: int, counter_base: int = 0,
                          n_accept=None):

@@ -33,6 +33,13 @@
 
 using namespace gna;
 
+// Scratch of gna_local_energy_noalloc (per-call base log psi, per-item partial sums
+// and counts, the evaluation counter): a file-scope device array, one copy per GPU,
+// held until the process ends.  Host code never passes its name to a kernel: the
+// device address of each GPU's copy comes from hipGetSymbolAddress at gna_init.
+constexpr size_t kStaticScratchBytes = (size_t)16 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
 namespace {
 
 // ===========================================================================
@@ -719,6 +726,8 @@ struct gna_ctx {
   int act = 0;                  // GNA_ACT_*
   double* d_vjp_part = nullptr; // [vjp_rows][P]
   std::vector<void*> owned;
+  void* scratch_dev = nullptr;  // this device's copy of `scratch` (hipGetSymbolAddress), or NULL
+  std::string scratch_err;      // why scratch_dev is NULL
   // kernel timing (gna_profile_enable)
   bool prof_on = false;
   bool prof_err = false;        // an event could not be created or recorded since the last read
@@ -743,6 +752,26 @@ gna_status hip_fail(gna_ctx* c, hipError_t e, const char* what) {
     hipError_t e_ = (call);                                     \
     if (e_ != hipSuccess) return hip_fail((ctx), e_, #call);    \
   } while (0)
+
+// Device address of `scratch` on `device` (the current device), looked up once per
+// device and kept for the process.
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+void* g_scratch_dev[kMaxDevices] = {};
+
+hipError_t static_scratch(int device, void** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  if (!g_scratch_dev[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[device] = p;
+  }
+  *out = g_scratch_dev[device];
+  return hipSuccess;
+}
 
 hipEvent_t take_event(gna_ctx* c) {
   if (!c->ev_pool.empty()) {
@@ -1236,6 +1265,11 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
     return bail(GNA_UNSUPPORTED, std::string("built for gfx950, device is ") + prop.gcnArchName);
   c->n_cu = prop.multiProcessorCount;
   const size_t lds_max = prop.sharedMemPerBlock;
+  {
+    // the static scratch of gna_local_energy_noalloc on this device (the current one)
+    const hipError_t se = static_scratch(c->device, &c->scratch_dev);
+    if (se != hipSuccess) c->scratch_err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(se);
+  }
 
   // ---- geometry: tiles per wave, waves per workgroup, gather chunks, buffers
   Geo& g = c->geo;
@@ -1581,6 +1615,40 @@ gna_status gna_local_energy(gna_ctx* c, const double* theta, const int8_t* spins
     if (gna_status st = run_logpsi(c, theta, spins, B, c->d_base)) return st;
   long long* nev = n_evals ? reinterpret_cast<long long*>(n_evals) : c->d_nev;
   return run_eloc(c, theta, spins, B, c->d_base, eloc, nev);
+}
+
+gna_status gna_local_energy_noalloc(gna_ctx* c, const double* theta, const int8_t* spins, int32_t B,
+                                    double* eloc, int64_t* n_evals) {
+  if (!c) return GNA_INVALID_ARG;
+  if (gna_status st = check_batch(c, B)) return st;
+  if (!valid_ptr(theta) || (B > 0 && (!valid_ptr(spins) || !valid_ptr(eloc))))
+    return fail(c, GNA_INVALID_ARG, "NULL pointer argument");
+  if (!c->scratch_dev) return fail(c, GNA_HIP_ERROR, c->scratch_err);
+  // scratch layout (256-byte aligned parts): evaluation counter, base log psi [B][2],
+  // per-item partial sums [B * n_chunks][4], per-item counts [B * n_chunks]
+  int n_chunks = 1, chunk = 1;
+  eloc_chunks(c, std::max(B, 1), &n_chunks, &chunk);
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t items = (size_t)B * n_chunks;
+  const size_t off_base = 256;
+  const size_t off_part = al(off_base + (size_t)B * 2 * sizeof(double));
+  const size_t off_cnt = al(off_part + items * 4 * sizeof(double));
+  const size_t need = off_cnt + items * sizeof(int);
+  if (need > kStaticScratchBytes)
+    return fail(c, GNA_INVALID_ARG, "gna_local_energy_noalloc: B = " + std::to_string(B) + " needs " +
+                                        std::to_string(need) + " bytes of static scratch, above the maximum of " +
+                                        std::to_string(kStaticScratchBytes));
+  unsigned char* sc = reinterpret_cast<unsigned char*>(c->scratch_dev);
+  long long* nev = n_evals ? reinterpret_cast<long long*>(n_evals) : reinterpret_cast<long long*>(sc);
+  double* base = reinterpret_cast<double*>(sc + off_base);
+  double* partial = reinterpret_cast<double*>(sc + off_part);
+  int* cnt = reinterpret_cast<int*>(sc + off_cnt);
+  if (gna_status st = prepare(c, theta)) return st;
+  if (c->eloc_mode == GNA_ELOC_FULL)
+    if (gna_status st = run_logpsi(c, theta, spins, B, base)) return st;
+  // every item's partial sums and count are written by the kernel that owns the
+  // item; the counter is cleared by a fill kernel inside run_eloc
+  return run_eloc(c, theta, spins, B, base, eloc, nev, false, partial, cnt);
 }
 
 static gna_status run_sweep(gna_ctx* c, const double* theta, int8_t* spins, double* logpsi, int32_t B,
