@@ -828,7 +828,7 @@ gna_status dev_alloc(gna_ctx* c, X** p, size_t bytes) {
 }
 
 void free_all(gna_ctx* c) {
-  for (void* p : c->owned) hipFree(p);
+  for (void* p : c->owned) (void)hipFree(p);   // teardown: nothing to report to
   c->owned.clear();
 }
 
@@ -1115,6 +1115,13 @@ gna_status inc_configure(gna_ctx* c, IncShape shp, int which) {
     t.off_ev = (int)o; o = al(o + (size_t)N * dmax * c->sz_Acc);
     t.off_list = (int)o; o = al(o + (size_t)chunk_cap * 4);
     t.off_cpy = (int)o; o = al(o + (size_t)S * max_rows * 16);
+    // the sweep keeps the bond list in LDS for its proposal draws when it fits
+    t.off_edges = -1;
+    const size_t eb = al((size_t)std::max(c->E, 1) * 8);
+    if ((which & 2) && o + eb + 2048 <= c->lds_max) {
+      t.off_edges = (int)o;
+      o += eb;
+    }
     t.lds_bytes = (int)o;
     if (o + 2048 > c->lds_max) return false;   // static LDS of the kernels
     *out = t;
@@ -1562,12 +1569,13 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
 
 void gna_destroy(gna_ctx* ctx) {
   if (!ctx) return;
-  hipStreamSynchronize(ctx->stream);
+  // teardown has no status to return: a failure here leaves nothing to undo
+  (void)hipStreamSynchronize(ctx->stream);
   for (auto& r : ctx->recs) {
-    hipEventDestroy(r.a);
-    hipEventDestroy(r.b);
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
   }
-  for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   free_all(ctx);
   delete ctx;
 }

@@ -59,6 +59,7 @@ struct IncGeo {
   int tabw;         // entries per job table in LDS (r8 + max|C_L| * dmax, multiple of 8)
   int spw;          // bytes per spin configuration in LDS
   int off_w, off_buf, off_tab, off_sp, off_red, off_bias, off_emb, off_head, off_ev, off_list, off_cpy;
+  int off_edges;    // bond endpoints [n_edges] (int2) in LDS (the sweep kernel), or -1
   int xcd;          // items are grouped per XCD (blocks b with equal b % xcd share a sample)
   int lds_bytes;
 };
@@ -208,9 +209,24 @@ __device__ void inc_group(const Net& net, const IncNet& inc, const IncGeo& ig, c
     if (jobs.flags[w] & kJobSwap) v = (nd == ij.x) ? spw[ij.y] : ((nd == ij.y) ? spw[ij.x] : v);
     return v > 0 ? 1 : 0;
   };
-  // layer outputs of this wave's tiles: a tile belongs to the same wave at every
-  // layer, so H'^l of its rows in C_l stays in registers as the next layer's input
+  // layer inputs of this wave's tiles: a tile belongs to the same wave at every
+  // layer, so H'^l of its rows in C_l stays in registers as the next layer's input.
+  // The lanes of its rows in ring l+1 (list positions [|C_l|, |C_{l+1}|)) take the
+  // base H^l rows instead: they are read into those lanes of hn right after the
+  // tile's layer-l activation, so that they arrive during the rest of the layer
+  // (no layer of the group writes them).
   Acc hn[MAXT][NS];
+  auto prefetch_in = [&](int k, int l) {   // l >= 2: base H^{l-1} of ring l in tile k
+    const int g = wv + k * nw;
+    const int w = g % nsw, tt = g / nsw;
+    const int cl = __builtin_amdgcn_readfirstlane(jobs.cnt[w][l]);
+    const int cp = __builtin_amdgcn_readfirstlane(jobs.cnt[w][l - 1]);
+    const int r = tt * 16 + col;
+    if (tt * 16 < cl && r >= cp && r < cl) {
+      const int nd = (int)x.tab[w * ig.tabw + r];
+      gmem_read<Acc, NS>(planes + jobs.pboff[w] + (size_t)(l - 2) * plane + (size_t)nd * F + q * NS, hn[k]);
+    }
+  };
   for (int l = 1; l <= Lr; ++l) {
     // ---- base G^{l-1} rows of the nodes at distance l+1 -> buffer (requested first,
     // stored after this wave's products)
@@ -261,22 +277,17 @@ __device__ void inc_group(const Net& net, const IncNet& inc, const IncGeo& ig, c
       tnd[k] = trow[k] < tcl[k] ? (int)x.tab[w * ig.tabw + trow[k]] : -1;
     }
     // ---- products: self -> registers, message -> buffer rows [0, |C_l|) in place
-    // layer input of tile k: embedding (l = 1), H'^{l-1} of the previous layer (this
-    // wave's registers), or base H^{l-1}
+    // layer input of tile k: embedding (l = 1), else hn (H'^{l-1} of the previous
+    // layer on C_{l-1}, the prefetched base H^{l-1} on ring l); zero past |C_l|
     auto load_in = [&](int k, Acc (&h)[NS]) {
-      const int w = tsw[k], r = trow[k], nd = tnd[k];
+      const int w = tsw[k], nd = tnd[k];
       if (l == 1) {
         const int xs = nd >= 0 ? xspin(w, nd) : 0;
 #pragma unroll
         for (int i = 0; i < NS; ++i) h[i] = nd >= 0 ? x.semb[xs * F + P::lc(q, i)] : (Acc)0;
-      } else if (r < tcp[k]) {
-#pragma unroll
-        for (int i = 0; i < NS; ++i) h[i] = hn[k][i];
-      } else if (nd >= 0) {
-        gmem_read<Acc, NS>(planes + jobs.pboff[w] + (size_t)(l - 2) * plane + (size_t)nd * F + q * NS, h);
       } else {
 #pragma unroll
-        for (int i = 0; i < NS; ++i) h[i] = (Acc)0;
+        for (int i = 0; i < NS; ++i) h[i] = nd >= 0 ? hn[k][i] : (Acc)0;
       }
     };
     CF acc[MAXT][MT];
@@ -319,7 +330,10 @@ __device__ void inc_group(const Net& net, const IncNet& inc, const IncGeo& ig, c
       for (int w = 0; w < nsw; ++w) x.red[(2 * w) * kMaxWaves + wv] = x.red[(2 * w + 1) * kMaxWaves + wv] = 0.0;
 #pragma unroll
     for (int k = 0; k < MAXT; ++k) {
-      if (!tok[k]) continue;
+      if (!tok[k]) {
+        if (l < Lr) prefetch_in(k, l + 1);   // a tile that starts at the next layer
+        continue;
+      }
       const int w = tsw[k], r = trow[k];
       const uint16_t* tw = x.tab + w * ig.tabw;
       const int nd = tnd[k];
@@ -396,6 +410,7 @@ __device__ void inc_group(const Net& net, const IncNet& inc, const IncGeo& ig, c
       } else if (WRITE && !last && nd >= 0) {   // H^l changed on C_l
         lds_write<Acc, NS>(pw + (size_t)(l - 1) * plane + (size_t)nd * F + q * NS, hn[k]);
       }
+      if (l < Lr) prefetch_in(k, l + 1);   // after the rows' own values were used
     }
     if (l < Lr) __syncthreads();   // every gather read of the buffers is done before new G rows
   }
@@ -536,6 +551,13 @@ __global__ __launch_bounds__(NT) void k_sweep_inc(Net net, IncNet inc, IncGeo ig
   const long long total = (long long)n_sweeps * net.n;
   if (counter_dev) counter_base += *counter_dev;   // graph replays read the current base
   inc_stage<P, F>(net, inc, x);
+  // bond endpoints in LDS when they fit: the proposal draws look them up one after another
+  const int2* edges = net.edges;
+  if (ig.off_edges >= 0) {
+    int2* se = reinterpret_cast<int2*>(smem + ig.off_edges);
+    for (int k = threadIdx.x; k < net.ne; k += bd) se[k] = net.edges[k];
+    edges = se;
+  }
   if ((int)threadIdx.x < S) {
     const int w = threadIdx.x;
     const int b = blockIdx.x + w * gridDim.x;
@@ -566,7 +588,7 @@ __global__ __launch_bounds__(NT) void k_sweep_inc(Net net, IncNet inc, IncGeo ig
             uint32_t c[4] = {(uint32_t)step, (uint32_t)(step >> 32), (uint32_t)b, 0u};
             philox4x32_10(c, k0, k1);
             const int e = (int)(((unsigned long long)c[0] * (unsigned long long)net.ne) >> 32);
-            const int2 ij = net.edges[e];
+            const int2 ij = edges[e];
             if (spw[ij.x] != spw[ij.y]) {
               s_prop[w] = e;   // the proposal's bond
               s_u[w] = ((double)c[1] + 0.5) * 2.3283064365386963e-10;   // 2^-32
@@ -620,7 +642,7 @@ __global__ __launch_bounds__(NT) void k_sweep_inc(Net net, IncNet inc, IncGeo ig
       const int j = threadIdx.x, w = s_jslot[j];
       const int e = s_job[w] == 1 ? s_prop[w] : s_pend[w];
       jobs.e[j] = e;
-      jobs.ij[j] = net.edges[e];
+      jobs.ij[j] = edges[e];
       jobs.meta[j] = inc.ball_meta[e];
       for (int l = 0; l < net.L + 2; ++l) jobs.cnt[j][l] = inc.ball_cnt[e * (net.L + 2) + l];
       jobs.flags[j] = s_job[w] == 1 ? (kJobSwap | kJobReadout) : 0;
