@@ -17,7 +17,9 @@ durations (HIP events the library records on its stream) for the roofline
 entries of the local-energy and sweep kernels.  The CPU baseline times the FP64
 oracle on a bounded prefix of the same batch, and its outputs give the error
 columns: energy per site, and per sample the off-diagonal part E_loc - |E|/4,
-which a constant psi would get wrong.
+which a constant psi would get wrong (median of the per-sample error relative to
+each sample's part, and the largest error relative to the largest part; a
+constant psi scores 1 on both).
 """
 from __future__ import annotations
 
@@ -470,11 +472,12 @@ def main():
         for prec, el in eloc_out.items():
             got = el[:S, 0] + 1j * el[:S, 1]
             es, rs = got.real.mean() / n, ref.real.mean() / n
-            off_rel = np.abs(got - ref) / np.abs(off_ref)
+            off_rel = np.abs(got - ref) / np.abs(off_ref)           # per row
+            off_big = np.abs(got - ref) / np.max(np.abs(off_ref))   # over the largest part
             per_prec[prec].update({
                 "err_energy_per_site": abs(es - rs) / max(abs(rs), 1e-2),
                 "err_offdiag_rel_median": float(np.median(off_rel)),
-                "err_offdiag_rel_max": float(off_rel.max()),
+                "err_offdiag_max_over_largest_part": float(off_big.max()),
                 "err_offdiag_mean_rel": float(abs(np.mean(got - len(e) / 4.0) - np.mean(off_ref)) /
                                               abs(np.mean(off_ref))),
                 "err_eloc_max_rel": float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))),
@@ -512,7 +515,7 @@ def main():
         out["accuracy"] = {"precision": args.precision, "err_energy_per_site": head["err_energy_per_site"],
                            "bound": bound, "within_bound": bool(head["err_energy_per_site"] < bound),
                            "err_offdiag_rel_median": head["err_offdiag_rel_median"],
-                           "err_offdiag_rel_max": head["err_offdiag_rel_max"],
+                           "err_offdiag_max_over_largest_part": head["err_offdiag_max_over_largest_part"],
                            "sample": cpu["sample"]}
     print(json.dumps(out))
     g.close()
