@@ -123,6 +123,19 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def kernel_of(prof: dict, names) -> str:
+    """The first of `names` (local-energy or sweep kernels of a mode, pipelined or
+    grouped) that ran in a profile."""
+    for nm in names:
+        if prof.get(nm, (0, 0.0))[0]:
+            return nm
+    return names[0]
+
+
+ELOC_KERNELS = {"incremental": ("k_eloc_pipe", "k_eloc_inc"), "full": ("k_eloc",)}
+SWEEP_KERNELS = {"incremental": ("k_sweep_pipe", "k_sweep_inc"), "full": ("k_sweep",)}
+
+
 def stored_traffic(workload: str, precision: str, kernel: str = "k_eloc"):
     """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE summary
     (profiles/<kernel>_<workload>_<precision>_hbm_traffic.md), or None when there is
@@ -286,7 +299,7 @@ def main():
     # dominant kernel: algorithmic FLOPs per launch / mean launch time; the step's
     # local energy runs on the configurations its sweep left (spins_after per step
     # stands in for the profiled steps: the sweep moves chains but keeps bond statistics)
-    kname = "k_eloc_inc" if args.eloc_mode == "incremental" else "k_eloc"
+    kname = kernel_of(prof, ELOC_KERNELS[args.eloc_mode])
     kl, kms = prof.get(kname, (0, 0.0))
     eloc_ms = kms / max(kl, 1)
     kflops = kernel_flops(args.eloc_mode, spins_after)
@@ -301,7 +314,7 @@ def main():
     # the sampler: algorithmic bytes of its proposals (read for every anti-aligned
     # proposal, written for every accepted one) against the HBM peak
     roofline_sweep = None
-    sname = "k_sweep_inc" if args.eloc_mode == "incremental" else "k_sweep"
+    sname = kernel_of(prof, SWEEP_KERNELS[args.eloc_mode])
     sl, sms = prof.get(sname, (0, 0.0))
     if sl and args.eloc_mode == "incremental":
         a_frac = anti_of(np.concatenate([spins_before, spins_after])).mean(axis=0)   # per bond
@@ -396,7 +409,7 @@ def main():
         gp.profile_enable(False)
         ne = int(nev.item())
         rate = ne * reps / (tb - ta)
-        kn = "k_eloc_inc" if mode == "incremental" else "k_eloc"
+        kn = kernel_of(pr, ELOC_KERNELS[mode])
         kl2, kms2 = pr.get(kn, (1, 0.0))
         kf = kernel_flops(mode, spins_np[:Bp])
         key = f"{prec}_{mode}"

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgna.so")
-SOURCES = [os.path.join(CSRC, "gna.hip")]
+SOURCES = [os.path.join(CSRC, "gna.hip"), os.path.join(CSRC, "gna_pipe.hip")]
 HEADERS = [os.path.join(CSRC, "gna_kernels.h"), os.path.join(ROOT, "include", "gna.h")]
 
 
@@ -22,19 +22,39 @@ def hipcc() -> str:
 
 
 def build_library(verbose: bool = False) -> str:
-    """Compile every HIP source into ``libgna.so`` (always recompiles)."""
+    """Compile every HIP source into ``libgna.so`` (always recompiles).
+
+    The translation units are compiled in parallel into objects, then linked."""
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
-           # packed FP32 VALU forms are kept out of generated code
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           *SOURCES, "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), file=sys.stderr)
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    errs = "\n".join(l for l in res.stderr.splitlines() if "packed-fp32-ops" not in l)
-    if res.returncode != 0:
-        raise RuntimeError(f"hipcc failed ({res.returncode}):\n{errs}")
+    flags = [hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+             "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
+             # packed FP32 VALU forms are kept out of generated code
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+    objs = [os.path.join(HERE, "_" + os.path.splitext(os.path.basename(src))[0] + ".o") for src in SOURCES]
+    procs = []
+    for src, obj in zip(SOURCES, objs):
+        cmd = [*flags, "-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), file=sys.stderr)
+        procs.append(subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True))
+    errs = []
+    for pr in procs:
+        _, err = pr.communicate()
+        if pr.returncode != 0:
+            errs.append("\n".join(l for l in err.splitlines() if "packed-fp32-ops" not in l))
+    try:
+        if errs:
+            raise RuntimeError("hipcc failed:\n" + "\n".join(errs))
+        cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+        if verbose:
+            print(" ".join(cmd), file=sys.stderr)
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError(f"hipcc link failed ({res.returncode}):\n{res.stderr}")
+    finally:
+        for obj in objs:
+            if os.path.exists(obj):
+                os.remove(obj)
     os.replace(tmp, LIB)
     return LIB
 

@@ -9,6 +9,8 @@
 //   k_sweep          Metropolis spin-swap chains (Philox4x32-10 draws)
 //   k_inc_base, k_eloc_inc, k_sweep_inc   receptive-field (incremental) evaluation
 //                    of the local energy and the sampler's proposals (gna_inc.h)
+//   k_eloc_pipe, k_sweep_pipe   the same with the layers of several jobs pipelined
+//                    (gna_pipe.h, instantiated in gna_pipe.hip)
 //   k_isgo_stats     ISGO weights, energy, variance, ESS, cotangents (FP64)
 //   k_vjp_* / k_vjp_reduce   reverse pass (FP32, FP64 for FP64), deterministic reduction
 //   k_sgd            theta -= alpha * grad
@@ -30,6 +32,8 @@
 #include "gna_kernels.h"
 #include "gna_vjp.h"
 #include "gna_inc.h"
+#include "gna_pipe.h"
+#include "gna_pipe_api.h"
 
 using namespace gna;
 
@@ -713,6 +717,17 @@ struct gna_ctx {
   int* d_ball_cnt = nullptr;
   uint16_t* d_ball_tab = nullptr;
   void* d_inc_planes = nullptr;   // [max_batch][2L][npad][F] Acc
+  // layer-pipelined incremental kernels (gna_pipe.h)
+  bool pipe_ok = false;            // its bond tables exist (sizes within the 12-bit pool tags)
+  bool pipe_el = false, pipe_sw = false;   // the local energy / the sweep run pipelined
+  PipeGeo pgeo_el{}, pgeo_sw{};
+  PipeKern pk_el{}, pk_sw{};
+  int grid_pipe_el = 1, grid_pipe_sw = 1;
+  int pipe_tabw = 0;
+  std::vector<int> ball_cmax;      // max |C_l| over bonds, l = 0 .. L+1
+  std::vector<int> ball_ringmax;   // max |C_s| - |C_{s-1}| over bonds, s = 3 .. L+1 (index s)
+  uint2* d_sched = nullptr;        // [2][kPipeMaxD][kMaxWaves] tile schedules: local energy, sweep
+  uint16_t* d_pipe_tab = nullptr;  // per bond: header, node ids, pool tags of positions and neighbours
   // reverse pass (FP32 for the FP32/BF16 modes, FP64 for FP64)
   Geo vgeo{};
   VKern vk{};
@@ -947,6 +962,25 @@ gna_status run_eloc(gna_ctx* c, const double* theta, const int8_t* spins, int B,
       if (e != hipSuccess) return hip_fail(c, e, "k_inc_base");
     }
     IncNet inc = make_inc(c);
+    if (c->pipe_el) {
+      PipeGeo pg = c->pgeo_el;
+      int grid_p = std::min(items, c->grid_pipe_el);
+      if (grid_p < pg.xcd || grid_p % pg.xcd) pg.xcd = 1;   // small launches: plain order
+      const uint2* sched = c->d_sched;
+      const uint16_t* gtab = c->d_pipe_tab;
+      {
+        Timed tm(c, "k_eloc_pipe");
+        void* a2[] = {&net, &inc, &pg, &sched, &gtab, &spins, &B, &planes, &n_chunks, &ichunk, &partial, &cnt};
+        hipError_t e = hipLaunchKernel(c->pk_el.eloc, dim3(grid_p), dim3(64 * pg.nw), a2, (size_t)pg.lds_bytes,
+                                       c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "k_eloc_pipe");
+      }
+      if (gna_status st = check_launch(c, "k_eloc_pipe")) return st;
+      Timed tm(c, "k_eloc_finalize");
+      hipLaunchKernelGGL(k_eloc_finalize, dim3((B + 255) / 256), dim3(256), 0, c->stream, spins, c->N,
+                         c->d_edges, c->E, c->jz, c->jxy, c->hb, c->cb, B, n_chunks, partial, cnt, eloc, nev);
+      return check_launch(c, "k_eloc_finalize");
+    }
     IncGeo ig = c->igeo;
     int grid_i = std::min(items, c->grid_inc);
     if (grid_i < ig.xcd || grid_i % ig.xcd) ig.xcd = 1;   // small launches: plain order
@@ -1050,7 +1084,7 @@ bool valid_ptr(const void* p) { return p != nullptr; }
 // the persistent grids; S < 0 asks for the largest S <= -S that fits.
 // ---------------------------------------------------------------------------
 struct IncShape {
-  int S;
+  int S;        // 0: the layer-pipelined kernels (gna_pipe.h)
   bool wide;
   int per_xcd;
   int nw = 0;   // waves per workgroup; 0: as many as useful (8, or 16 when wide)
@@ -1081,6 +1115,159 @@ void tune_store(const std::string& key, const IncTune& v) {
       return;
     }
   g_tune.push_back({key, v});
+}
+
+// Tile schedule of the pipelined kernels: job slot j (setup at ticks = j mod D)
+// runs layer l at tick j + extra + l (mod D).  Tile t (list positions 16t ..
+// 16t+15) of a job holds registers from the first layer it computes or receives
+// base rows for the next layer, to layer L; it is busy (products) at layer l when
+// 16t < max(rows of the message product, |C_l|).  Every (slot, tile) gets one
+// (wave, register) pair whose live ticks it does not share, the busiest ones
+// first, each on the compute wave least loaded at its busy ticks.  sched[tick mod
+// D][wave] packs the (slot << 4 | tile) of registers 0..7 (0xff: none).  False
+// when the tiles do not fit in maxt registers per wave.
+bool pipe_schedule(const std::vector<int>& cmax, int L, int D, int extra, int nw, int sw, int maxt,
+                   std::vector<uint2>* sched, int* max_load) {
+  auto rows_at = [&](int l) { return std::max(l == 1 ? cmax[2] : cmax[l], cmax[l]); };   // products at layer l
+  int top = 0;
+  for (int l = 1; l <= L; ++l) top = std::max(top, rows_at(l));
+  const int tmax = (top + 15) / 16;
+  if (tmax > 16 || D > kPipeMaxD || maxt > kPipeMaxK) return false;
+  std::vector<int> lf(tmax, L + 1);
+  for (int t = 0; t < tmax; ++t)
+    for (int l = L; l >= 1; --l)
+      if (16 * t < rows_at(l) || (l < L && 16 * t < cmax[l + 1])) lf[t] = l;
+  struct Item { int j, t; };
+  std::vector<Item> items;
+  for (int t = 0; t < tmax; ++t)
+    for (int j = 0; j < D; ++j)
+      if (lf[t] <= L) items.push_back({j, t});
+  std::stable_sort(items.begin(), items.end(), [&](const Item& a, const Item& b) { return lf[a.t] < lf[b.t]; });
+  std::vector<int> occ((size_t)D * nw * maxt, -1), load((size_t)D * nw, 0);
+  for (const Item& it : items) {
+    int best_w = -1, best_k = -1;
+    long long best_cost = 0;
+    for (int w = 0; w < nw; ++w) {
+      if (w == sw) continue;
+      for (int k = 0; k < maxt; ++k) {
+        bool free_ = true;
+        int peak = 0, sum = 0;
+        for (int l = lf[it.t]; l <= L && free_; ++l) {
+          const int tau = (it.j + extra + l) % D;
+          if (occ[((size_t)tau * nw + w) * maxt + k] >= 0) free_ = false;
+          if (16 * it.t < rows_at(l)) {
+            peak = std::max(peak, load[(size_t)tau * nw + w] + 1);
+            sum += load[(size_t)tau * nw + w];
+          }
+        }
+        if (!free_) continue;
+        const long long cost = (long long)peak * 1000000 + sum * 100 + k;
+        if (best_w < 0 || cost < best_cost) {
+          best_w = w;
+          best_k = k;
+          best_cost = cost;
+        }
+        break;   // registers of one wave are interchangeable: the first free one
+      }
+    }
+    if (best_w < 0) return false;
+    for (int l = lf[it.t]; l <= L; ++l) {
+      const int tau = (it.j + extra + l) % D;
+      occ[((size_t)tau * nw + best_w) * maxt + best_k] = it.j << 4 | it.t;
+      if (16 * it.t < rows_at(l)) ++load[(size_t)tau * nw + best_w];
+    }
+  }
+  sched->assign((size_t)kPipeMaxD * kMaxWaves, uint2{0xffffffffu, 0xffffffffu});
+  int ml = 0;
+  for (int tau = 0; tau < D; ++tau)
+    for (int w = 0; w < nw; ++w) {
+      unsigned long long v = ~0ULL;
+      for (int k = 0; k < maxt; ++k) {
+        const int o = occ[((size_t)tau * nw + w) * maxt + k];
+        if (o >= 0) v = (v & ~(0xffULL << (8 * k))) | ((unsigned long long)o << (8 * k));
+      }
+      (*sched)[(size_t)tau * kMaxWaves + w] = uint2{(unsigned)v, (unsigned)(v >> 32)};
+      ml = std::max(ml, load[(size_t)tau * nw + w]);
+    }
+  if (max_load) *max_load = ml;
+  return true;
+}
+
+// Shape of a pipelined kernel (which: 1 local energy, 2 sweep): pools, LDS layout,
+// tile schedule, instantiation and persistent grid.
+gna_status pipe_configure(gna_ctx* c, IncShape shp, int which) {
+  if (!c->pipe_ok) return fail(c, GNA_UNSUPPORTED, "pipelined kernels: the graph's balls exceed their tables");
+  if (c->act != 0) return fail(c, GNA_UNSUPPORTED, "pipelined kernels: tanh only (ReLU + layer normalisation runs grouped)");
+  const int F = c->F, L = c->L, N = c->N, dmax = c->dmax;
+  const int nt = shp.wide ? 1024 : 512;
+  const PipeKern pk = pipe_pick(c->prec, F, nt);
+  if (!pk.eloc) return fail(c, GNA_UNSUPPORTED, "pipelined kernels: no instantiation for this precision");
+  PipeGeo g{};
+  g.nw = nt / 64;
+  g.sw = g.nw - 1;
+  g.extra = 1;
+  g.D = L + 1 + g.extra;
+  if (g.D > kPipeMaxD) return fail(c, GNA_UNSUPPORTED, "pipelined kernels: too many layers");
+  g.row_elems = (int)((F * c->sz_Acc + kRowPadBytes) / c->sz_Acc);
+  int rows = 0;
+  for (int pi = 0; pi < kPipeMaxL; ++pi) {
+    g.pool_cnt[pi] = 1;
+    g.pool_rows[pi] = 0;
+    g.pool_base[pi] = 0;
+  }
+  for (int pi = 0; pi < L; ++pi) {
+    g.pool_cnt[pi] = L - pi;
+    g.pool_rows[pi] = pi == 0 ? c->ball_cmax[2] : c->ball_ringmax[pi + 2];
+    g.pool_base[pi] = rows;
+    rows += g.pool_cnt[pi] * g.pool_rows[pi];
+  }
+  if (rows > 65535) return fail(c, GNA_UNSUPPORTED, "pipelined kernels: LDS rows exceed 16-bit indices");
+  g.tabw = c->pipe_tabw;
+  g.r8 = c->inc_r8;
+  g.ntab = L + 1;
+  g.spw = (int)((c->geo.npad + 15) / 16 * 16);
+  g.xcd = 8;   // MI355X: 8 XCDs, workgroups assigned round-robin
+  size_t o = 0;
+  auto al = [](size_t x) { return (x + 15) & ~(size_t)15; };
+  g.off_w = (int)o; o = al(o + c->inc_w_bytes);
+  g.off_arena = (int)o; o = al(o + (size_t)rows * g.row_elems * c->sz_Acc);
+  g.off_tab = (int)o; o = al(o + (size_t)g.ntab * g.tabw * 2);
+  g.off_sp = (int)o; o = al(o + (size_t)(g.D + 1) * g.spw);
+  g.off_red = (int)o; o = al(o + (size_t)4 * kMaxWaves * 8);
+  g.off_bias = (int)o; o = al(o + (size_t)F * c->sz_Acc);
+  g.off_emb = (int)o; o = al(o + (size_t)2 * F * c->sz_Acc);
+  g.off_head = (int)o; o = al(o + (size_t)2 * (F + 3) * 8);
+  g.off_ev = (int)o; o = al(o + (size_t)N * dmax * c->sz_Acc);
+  g.off_edges = (int)o; o = al(o + (size_t)std::max(c->E, 1) * 4);
+  g.off_mask = (int)o; o = al(o + (size_t)kPipeMaskWords * 4);
+  g.lds_bytes = (int)o;
+  if (o + sizeof(PipeState) + 256 > c->lds_max)
+    return fail(c, GNA_UNSUPPORTED, "pipelined kernels: the shape does not fit in LDS");
+  std::vector<uint2> sched;
+  int ml = 0;
+  if (!pipe_schedule(c->ball_cmax, L, g.D, g.extra, g.nw, g.sw, pk.maxt, &sched, &ml))
+    return fail(c, GNA_UNSUPPORTED, "pipelined kernels: the tiles do not fit in the wave registers");
+  const void* fn = which == 1 ? pk.eloc : pk.sweep;
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, g.lds_bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, GNA_HIP_ERROR, "hipFuncSetAttribute: the pipelined kernel's LDS size was not accepted");
+  }
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, nt, g.lds_bytes) != hipSuccess || nb < 1) nb = 1;
+  (void)hipGetLastError();
+  uint2* dst = c->d_sched + (size_t)(which == 1 ? 0 : 1) * kPipeMaxD * kMaxWaves;
+  if (hipMemcpy(dst, sched.data(), sched.size() * sizeof(uint2), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(c, GNA_HIP_ERROR, "hipMemcpy: pipelined tile schedule");
+  if (which == 1) {
+    c->pgeo_el = g;
+    c->pk_el = pk;
+    c->grid_pipe_el = c->n_cu * nb;
+  } else {
+    c->pgeo_sw = g;
+    c->pk_sw = pk;
+    c->grid_pipe_sw = c->n_cu * nb;
+  }
+  return GNA_OK;
 }
 
 // which: 1 the local-energy kernel, 2 the sweep kernel, 3 both
@@ -1128,6 +1315,25 @@ gna_status inc_configure(gna_ctx* c, IncShape shp, int which) {
     *maxt = mt;
     return true;
   };
+  if (shp.S == 0) {   // the layer-pipelined kernels
+    for (int w = 1; w <= 2; ++w) {
+      if (!(which & w)) continue;
+      if (gna_status st = pipe_configure(c, shp, w)) return st;
+      if (w == 1) {
+        c->pipe_el = true;
+        c->inc_wide = shp.wide;
+        c->inc_maxt = c->pk_el.maxt;
+        c->inc_per_xcd = std::max(1, shp.per_xcd);
+        c->inc_chunk_cap = std::min(chunk_cap, kPipeMaskWords * 32);
+        c->grid_inc = c->grid_pipe_el;
+      } else {
+        c->pipe_sw = true;
+        c->inc_sw_wide = shp.wide;
+        c->inc_sw_maxt = c->pk_sw.maxt;
+      }
+    }
+    return GNA_OK;
+  }
   IncGeo ig{};
   int maxt = 0;
   if (shp.S < 0) {
@@ -1169,6 +1375,7 @@ gna_status inc_configure(gna_ctx* c, IncShape shp, int which) {
   c->ik.base = ik.base;   // the base pass does not depend on the shape
   c->grid_inc_base = g_base;
   if (which & 1) {
+    c->pipe_el = false;
     c->igeo = ig;
     c->ik.eloc = ik.eloc;
     c->inc_wide = shp.wide;
@@ -1178,6 +1385,7 @@ gna_status inc_configure(gna_ctx* c, IncShape shp, int which) {
     c->grid_inc = g_el;
   }
   if (which & 2) {
+    c->pipe_sw = false;
     c->igeo_sw = ig;
     c->ik.sweep = ik.sweep;
     c->inc_sw_wide = shp.wide;
@@ -1185,6 +1393,16 @@ gna_status inc_configure(gna_ctx* c, IncShape shp, int which) {
     c->grid_sweep_inc = g_sw;
   }
   return GNA_OK;
+}
+
+// the shapes in use (for restoring them after a failed change)
+IncShape shape_el(const gna_ctx* c) {
+  if (c->pipe_el) return IncShape{0, c->inc_wide, c->inc_per_xcd, 0};
+  return IncShape{c->igeo.S, c->inc_wide, c->inc_per_xcd, c->igeo.nw};
+}
+IncShape shape_sw(const gna_ctx* c) {
+  if (c->pipe_sw) return IncShape{0, c->inc_sw_wide, 1, 0};
+  return IncShape{c->igeo_sw.S, c->inc_sw_wide, 1, c->igeo_sw.nw};
 }
 
 }  // namespace
@@ -1520,6 +1738,59 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
         for (int nd : lst) pos[nd] = -1;
       }
     }
+    // bond tables of the pipelined kernels: header |C_0| .. |C_{L+1}|, node ids, then
+    // the pool tag (pool << 12 | offset in the pool slot) of every list position and
+    // of the neighbour positions of each row of C_L (see gna_pipe.h)
+    {
+      c->ball_cmax.assign(L + 2, 0);
+      c->ball_ringmax.assign(L + 2, 0);
+      for (int e = 0; e < E; ++e)
+        for (int l = 0; l <= L + 1; ++l) {
+          const int* ce = &cnt[(size_t)e * (L + 2)];
+          c->ball_cmax[l] = std::max(c->ball_cmax[l], ce[l]);
+          if (l >= 3) c->ball_ringmax[l] = std::max(c->ball_ringmax[l], ce[l] - ce[l - 1]);
+        }
+      const int nbt = max_ball * dmax;
+      const int tabw = (kPipeHdr + 2 * r8 + nbt + 7) / 8 * 8;
+      bool ok = E > 0 && L >= 1 && L <= kPipeMaxL && N <= 65535 && E <= 65535 && c->ball_cmax[2] < 4096 &&
+                tabw <= 8 * 64 * kPipeTabVec;
+      for (int sr = 3; sr <= L + 1; ++sr) ok = ok && c->ball_ringmax[sr] < 4096;
+      std::vector<uint16_t> pt;
+      if (ok) {
+        pt.assign((size_t)E * tabw, 0);
+        std::vector<int> pos(N, -1);
+        for (int e = 0; e < E; ++e) {
+          const std::vector<int>& lst = lists[e];
+          const int* ce = &cnt[(size_t)e * (L + 2)];
+          uint16_t* t = pt.data() + (size_t)e * tabw;
+          for (int l = 0; l <= L + 1; ++l) t[l] = (uint16_t)ce[l];
+          auto tag = [&](int p) {
+            if (p < ce[2]) return (uint16_t)p;   // pool 0: the prefix [0, |C_2|)
+            int sr = 3;
+            while (p >= ce[sr]) ++sr;            // ring sr: [|C_{sr-1}|, |C_sr|), pool sr - 2
+            return (uint16_t)(((sr - 2) << 12) | (p - ce[sr - 1]));
+          };
+          for (int r = 0; r < r8; ++r) {
+            t[kPipeHdr + r] = r < (int)lst.size() ? (uint16_t)lst[r] : (uint16_t)0xffff;
+            t[kPipeHdr + r8 + r] = r < (int)lst.size() ? tag(r) : (uint16_t)0;
+          }
+          for (size_t r = 0; r < lst.size(); ++r) pos[lst[r]] = (int)r;
+          for (int r = 0; r < ce[L]; ++r)
+            for (int d = 0; d < dmax; ++d)
+              t[kPipeHdr + 2 * r8 + r * dmax + d] = tag(pos[idx[(size_t)lst[r] * dmax + d]]);
+          for (int nd : lst) pos[nd] = -1;
+        }
+      }
+      c->pipe_ok = ok;
+      c->pipe_tabw = tabw;
+      if ((st = dev_alloc(c, &c->d_sched, (size_t)2 * kPipeMaxD * kMaxWaves * sizeof(uint2))) ||
+          (ok && (st = dev_alloc(c, &c->d_pipe_tab, pt.size() * 2))))
+        return bail(st, c->err);
+      if (ok) {
+        he = hipMemcpy(c->d_pipe_tab, pt.data(), pt.size() * 2, hipMemcpyHostToDevice);
+        if (he != hipSuccess) return bail(GNA_HIP_ERROR, std::string("hipMemcpy: ") + hipGetErrorString(he));
+      }
+    }
     c->inc_r8 = r8;
     c->inc_max_rows = max_rows;
     c->inc_max_ball = max_ball;
@@ -1679,11 +1950,26 @@ static gna_status run_sweep(gna_ctx* c, const double* theta, int8_t* spins, doub
     }
     if (gna_status st = check_launch(c, "k_inc_base")) return st;
     IncNet inc = make_inc(c);
-    IncGeo ig = c->igeo_sw;
-    const int grid_s = std::max(1, std::min(c->grid_sweep_inc, (B + ig.S - 1) / ig.S));
     int Bv = B, ns = n_sweeps;
     unsigned long long sd = seed, cb = counter_base;
     int* acc = n_accept;
+    if (c->pipe_sw) {
+      PipeGeo pg = c->pgeo_sw;
+      const int grid_p = std::max(1, std::min(c->grid_pipe_sw, (B + pg.D - 1) / pg.D));
+      const uint2* sched = c->d_sched + (size_t)kPipeMaxD * kMaxWaves;
+      const uint16_t* gtab = c->d_pipe_tab;
+      {
+        Timed tm(c, "k_sweep_pipe");
+        void* a2[] = {&net, &inc, &pg, &sched, &gtab, &spins, &planes, &Bv, &ns, &sd, &cb, &counter_dev, &acc};
+        hipError_t e = hipLaunchKernel(c->pk_sw.sweep, dim3(grid_p), dim3(64 * pg.nw), a2, (size_t)pg.lds_bytes,
+                                       c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "k_sweep_pipe");
+      }
+      if (gna_status st = check_launch(c, "k_sweep_pipe")) return st;
+      return run_logpsi(c, theta, spins, B, logpsi);
+    }
+    IncGeo ig = c->igeo_sw;
+    const int grid_s = std::max(1, std::min(c->grid_sweep_inc, (B + ig.S - 1) / ig.S));
     {
       Timed tm(c, "k_sweep_inc");
       void* a2[] = {&net, &inc, &ig, &spins, &planes, &Bv, &ns, &sd, &cb, &counter_dev, &acc};
@@ -1805,13 +2091,17 @@ gna_status gna_autotune(gna_ctx* c, const double* theta, const int8_t* spins, in
     return GNA_OK;
   }
   if (gna_status st = prepare(c, theta)) return st;
-  const IncShape before{c->igeo.S, c->inc_wide, c->inc_per_xcd, c->igeo.nw};
-  const IncShape before_sw{c->igeo_sw.S, c->inc_sw_wide, 1, c->igeo_sw.nw};
+  const IncShape before = shape_el(c);
+  const IncShape before_sw = shape_sw(c);
   // candidates: the four largest S that fit, both wave shapes, one or two samples per XCD
   std::vector<IncShape> cand;
   int smax = 0;
   for (int S = kIncMaxSwaps; S >= 1 && !smax; --S)
     if (inc_configure(c, IncShape{S, false, 2}, 1) == GNA_OK) smax = S;
+  for (int px = 1; px <= 2; ++px) {   // the layer-pipelined kernels, 8 or 16 waves
+    cand.push_back(IncShape{0, false, px, 0});
+    cand.push_back(IncShape{0, true, px, 0});
+  }
   for (int S = smax; S >= 1 && S > smax - 4; --S)
     for (int px = 1; px <= 2; ++px) {
       cand.push_back(IncShape{S, true, px, 0});
@@ -1901,12 +2191,12 @@ gna_status gna_autotune(gna_ctx* c, const double* theta, const int8_t* spins, in
   if ((st = inc_configure(c, best, 1)) != GNA_OK || (st = inc_configure(c, best_sw, 2)) != GNA_OK) return st;
   tune_store(c->tune_key, IncTune{best, best_sw});
   if (chosen) {
-    chosen[0] = best.S;
-    chosen[1] = c->inc_wide ? kMaxWaves : c->igeo.nw;   // 16: the one-tile-per-wave variant
+    chosen[0] = best.S;   // 0: the pipelined kernel
+    chosen[1] = c->pipe_el ? c->pgeo_el.nw : (c->inc_wide ? kMaxWaves : c->igeo.nw);   // 16: the 1024-thread variant
     chosen[2] = best.per_xcd;
     chosen[3] = (int32_t)(ms_el * 500.f);   // microseconds per local-energy call
     chosen[4] = best_sw.S;
-    chosen[5] = c->inc_sw_wide ? kMaxWaves : c->igeo_sw.nw;
+    chosen[5] = c->pipe_sw ? c->pgeo_sw.nw : (c->inc_sw_wide ? kMaxWaves : c->igeo_sw.nw);
     chosen[6] = c->inc_sw_maxt;
     chosen[7] = (int32_t)(ms_sw * 500.f);   // microseconds per one-sweep call
   }
@@ -1918,15 +2208,17 @@ gna_status gna_set_shape(gna_ctx* c, int32_t which, int32_t jobs_in_flight, int3
   if (c->eloc_mode != GNA_ELOC_INCREMENTAL)
     return fail(c, GNA_INVALID_ARG, "kernel shapes apply to the incremental mode only");
   if (which < 1 || which > 3) return fail(c, GNA_INVALID_ARG, "which must be 1 (local energy), 2 (sweep) or 3");
-  if (jobs_in_flight < 1 || jobs_in_flight > kIncMaxSwaps)
-    return fail(c, GNA_INVALID_ARG, "jobs_in_flight must be in [1, 8]");
+  if (jobs_in_flight < 0 || jobs_in_flight > kIncMaxSwaps)
+    return fail(c, GNA_INVALID_ARG, "jobs_in_flight must be 0 (pipelined) or in [1, 8]");
   if (waves != kMaxWaves && (waves < 1 || waves > kMaxWaves / 2))
     return fail(c, GNA_INVALID_ARG, "waves must be 16 or in [1, 8]");
+  if (jobs_in_flight == 0 && waves != kMaxWaves && waves != kMaxWaves / 2)
+    return fail(c, GNA_INVALID_ARG, "the pipelined kernels take 8 or 16 waves");
   if (samples_per_xcd < 1 || samples_per_xcd > 8) return fail(c, GNA_INVALID_ARG, "samples_per_xcd must be in [1, 8]");
-  const IncShape before{c->igeo.S, c->inc_wide, c->inc_per_xcd, c->igeo.nw};
-  const IncShape before_sw{c->igeo_sw.S, c->inc_sw_wide, 1, c->igeo_sw.nw};
+  const IncShape before = shape_el(c);
+  const IncShape before_sw = shape_sw(c);
   const bool wide = waves == kMaxWaves;
-  const IncShape sh{jobs_in_flight, wide, samples_per_xcd, wide ? 0 : waves};
+  const IncShape sh{jobs_in_flight, wide, samples_per_xcd, (wide || jobs_in_flight == 0) ? 0 : waves};
   gna_status st = GNA_OK;
   if (which & 1) st = inc_configure(c, sh, 1);
   if (st == GNA_OK && (which & 2)) st = inc_configure(c, sh, 2);
@@ -1978,9 +2270,12 @@ int32_t gna_config_info(const gna_ctx* c, int32_t* info, int32_t n) {
   if (!c || (n > 0 && !info)) return -1;
   const bool inc = c->eloc_mode == GNA_ELOC_INCREMENTAL;
   // waves: 16 names the one-tile-per-wave variant (it launches one wave per tile, at most 16)
-  const int32_t v[11] = {c->eloc_mode, inc ? c->igeo.S : 0, inc ? (c->inc_wide ? kMaxWaves : c->igeo.nw) : c->geo.wpc,
+  const int el_s = c->pipe_el ? 0 : c->igeo.S, sw_s = c->pipe_sw ? 0 : c->igeo_sw.S;
+  const int el_w = c->pipe_el ? c->pgeo_el.nw : (c->inc_wide ? kMaxWaves : c->igeo.nw);
+  const int sw_w = c->pipe_sw ? c->pgeo_sw.nw : (c->inc_sw_wide ? kMaxWaves : c->igeo_sw.nw);
+  const int32_t v[11] = {c->eloc_mode, inc ? el_s : 0, inc ? el_w : c->geo.wpc,
                          inc ? c->inc_maxt : c->tpw, inc ? c->inc_per_xcd : 0, c->prec, c->F, c->L,
-                         inc ? c->igeo_sw.S : 0, inc ? (c->inc_sw_wide ? kMaxWaves : c->igeo_sw.nw) : c->geo.wpc,
+                         inc ? sw_s : 0, inc ? sw_w : c->geo.wpc,
                          inc ? c->inc_sw_maxt : c->tpw};
   for (int k = 0; k < n && k < 11; ++k) info[k] = v[k];
   return 11;

@@ -1,0 +1,841 @@
+// Layer-pipelined incremental evaluation (local energy and Metropolis sweeps).
+//
+// The ball evaluation of an exchange (Section 3's log psi(s^ij) - log psi(s) from
+// the receptive field of the exchanged pair, as in gna_inc.h) has L dependent
+// layers of 1 to a few 16-row tiles each.  Advancing one exchange at a time
+// leaves most waves of a workgroup idle and pays two barriers per layer and
+// exchange.  Here a workgroup keeps D jobs in flight whose layers are staggered:
+// job slot j starts a job every D ticks (at ticks T = j mod D: its setup), and the
+// job computes layer l at tick T0 + extra + l.  A tick has two barriers; between
+// them every job in flight advances one layer, so a tick carries the tiles of
+// all L layers (one job each) and a job costs two barriers instead of 2L.
+//
+// Per tick, every wave runs its tiles from a schedule fixed by the host
+// (tick mod D, wave, register slot k) -> (job slot, tile); a tile belongs to the
+// same wave and registers for the whole job, so a layer's output rows stay in
+// registers (hn) as the next layer's input, as in the group kernel.
+//   phase A: message and self products of the tile (H'^{l-1} W), message rows into
+//            the job's LDS rows; base H^l rows of ring l+1 requested into the
+//            lanes of hn that the next layer reads from them; ring rows of the
+//            coming tick stored into LDS (requested at the end of the last tick)
+//   barrier
+//   phase B: gather of A_hat G over the job's LDS rows, activation, readout
+//            difference at layer L; the setup wave stores the table of a new job;
+//            every wave requests the ring rows of the next tick
+//   barrier
+// LDS rows of a job are not one buffer sized for the largest ball: rows of list
+// positions [0, |C_2|) (computed at layer 1 from the spins) and of each ring
+// [|C_{s-1}|, |C_s|), s >= 3 (copied from the base planes for the gather of
+// layer s-1) live in pools.  Pool pi holds positions of ring pi + 2 (pi = 0: the
+// prefix [0, |C_2|)) from layer pi + 1 to layer L, i.e. during L - pi ticks; since
+// jobs start one tick apart, L - pi slots of the pool suffice, slot = tick mod
+// (L - pi).  The setup wave converts the bond's table of list positions into
+// arena rows when the job starts.
+//
+// Arithmetic is the same instruction sequence per row as the full evaluation and
+// the group kernel (the rows are bit-identical); only the order of the FP64
+// readout sums over tiles and waves differs.
+#pragma once
+
+#include "gna_inc.h"
+
+namespace gna {
+
+constexpr int kPipeMaxD = 16;        // job slots
+constexpr int kPipeMaxK = 8;         // tile registers per wave
+constexpr int kPipeMaxL = 14;        // layers (the table header holds |C_0| .. |C_{L+1}|)
+constexpr int kPipeHdr = 16;         // uint16 header entries of a bond table
+constexpr int kPipeTabVec = 4;       // 16-byte table vectors per lane of the setup wave
+constexpr int kPipeMaskWords = 64;   // anti-aligned bond mask of a work item (2048 bonds)
+
+struct PipeGeo {
+  int nw, D, extra, sw;     // waves, job slots, idle ticks between setup and layer 1, setup wave
+  int row_elems;            // LDS row stride (Acc elements)
+  int pool_base[kPipeMaxL], pool_cnt[kPipeMaxL], pool_rows[kPipeMaxL];
+  int tabw;                 // uint16 entries of a bond table (global and LDS; multiple of 8)
+  int r8;                   // list positions per bond (multiple of 8)
+  int ntab;                 // LDS tables (L + 1)
+  int spw;                  // bytes per spin row in LDS
+  int off_w, off_arena, off_tab, off_sp, off_red, off_bias, off_emb, off_head, off_ev, off_edges, off_mask;
+  int xcd;
+  int lds_bytes;
+};
+
+// one layer's ring rows in a tick's copy plan
+struct PipeCopy {
+  int end;          // 16-byte vectors of the plan through this entry
+  int a;            // first list position
+  int tab;          // LDS table of the job (uint16 offset)
+  int pad;
+  long long src;    // element offset of the source plane G^{l-1} of the job's sample
+};
+
+// job state of a workgroup (LDS)
+struct PipeState {
+  // per job slot, written by the setup wave and read by every wave
+  int valid[kPipeMaxD];
+  int flags[kPipeMaxD];
+  int e[kPipeMaxD];
+  int2 ij[kPipeMaxD];
+  long long pboff[kPipeMaxD];
+  int t1[kPipeMaxD];                          // table tick of the job
+  int tbo[kPipeMaxD];                         // its LDS table (uint16 offset), from the table tick on
+  unsigned short hdr[kPipeMaxD][kPipeHdr];    // |C_0| .. |C_{L+1}| of its bond, from the table tick on
+  // setup wave only
+  int item[kPipeMaxD];                        // local energy: work item of the job
+  int spb[kPipeMaxD];                         // local energy: sample held in the slot's spin row
+  int chain[kPipeMaxD], nacc[kPipeMaxD], pend[kPipeMaxD];   // sampler: the slot's chain
+  long long tstep[kPipeMaxD];
+  double u[kPipeMaxD];
+  int rowbase[kPipeMaxL];                     // first arena row of each pool slot of the job converted
+  PipeCopy plan[2][kPipeMaxL];                // ring-row copies of the next tick (by tick parity)
+  int nplan[2];
+  int done;
+};
+
+// ReLU and layer normalisation of a node row in place: the same operations, in the
+// same order, as relu_ln_row (its y and h in the one array)
+template <class Acc, int NS>
+__device__ __forceinline__ void relu_ln_inplace(Acc (&x)[NS]) {
+  constexpr int F = 4 * NS;
+  Acc s = 0;
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    x[i] = x[i] > (Acc)0 ? x[i] : (Acc)0;
+    s += x[i];
+  }
+  const Acc mu = quad_sum(s) / (Acc)F;
+  Acc v = 0;
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    const Acc d = x[i] - mu;
+    v += d * d;
+  }
+  const Acc r = (Acc)1 / sqrt(quad_sum(v) / (Acc)F + (Acc)kLnEps);
+#pragma unroll
+  for (int i = 0; i < NS; ++i) x[i] = (x[i] - mu) * r;
+}
+
+template <class P, int F, int MAXT, int NT, int NCOPY, bool SWEEP>
+__device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, const PipeGeo& pg,
+                                          const uint2* __restrict__ sched, const uint16_t* __restrict__ gtab,
+                                          int8_t* spins, int B, typename P::Acc* planes, int n_chunks, int chunk,
+                                          double* __restrict__ partial, int* __restrict__ cnt_out, int n_sweeps,
+                                          unsigned long long seed, unsigned long long counter_base,
+                                          const unsigned long long* __restrict__ counter_dev,
+                                          int* __restrict__ n_accept) {
+  using Acc = typename P::Acc;
+  using CF = typename P::CF;
+  using WT = typename P::WT;
+  using V4 = unsigned int __attribute__((ext_vector_type(4)));
+  constexpr int NS = F / 4, MT = F / 16, KSB = F / P::KS, VEC = P::VEC;
+  constexpr int VPR = F * (int)sizeof(Acc) / 16;   // 16-byte vectors per row
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ PipeState st;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int q = lane >> 4, col = lane & 15;
+  const int nw = pg.nw, D = pg.D, extra = pg.extra, Lr = net.L, dm = inc.dmax, r8 = pg.r8;
+  const int ntab = pg.ntab, tabw = pg.tabw;
+  const size_t plane = (size_t)net.g.npad * F;
+  const long long per = 2LL * Lr * (long long)plane;   // planes of one sample / chain
+  const int row_bytes = pg.row_elems * (int)sizeof(Acc);
+
+  WT* wl = reinterpret_cast<WT*>(smem + pg.off_w);
+  Acc* arena = reinterpret_cast<Acc*>(smem + pg.off_arena);
+  uint16_t* tabs = reinterpret_cast<uint16_t*>(smem + pg.off_tab);
+  int8_t* sp = reinterpret_cast<int8_t*>(smem + pg.off_sp);
+  double* red = reinterpret_cast<double*>(smem + pg.off_red);   // [tick parity][2][kMaxWaves]
+  Acc* sbias = reinterpret_cast<Acc*>(smem + pg.off_bias);
+  Acc* semb = reinterpret_cast<Acc*>(smem + pg.off_emb);
+  double* shead = reinterpret_cast<double*>(smem + pg.off_head);
+  Acc* sev = reinterpret_cast<Acc*>(smem + pg.off_ev);
+  unsigned* sedge = reinterpret_cast<unsigned*>(smem + pg.off_edges);   // i | j << 16
+  unsigned* smask = reinterpret_cast<unsigned*>(smem + pg.off_mask);
+
+  // ---- weights, node tables and bond endpoints -> LDS
+  {
+    const WT* src = reinterpret_cast<const WT*>(net.wfrag);
+    for (int k = threadIdx.x; k < 2 * F * F; k += NT) wl[k] = src[k];
+    for (int k = threadIdx.x; k < F; k += NT) sbias[k] = reinterpret_cast<const Acc*>(net.bias)[P::lc(k / NS, k % NS)];
+    for (int k = threadIdx.x; k < 2 * F; k += NT) semb[k] = reinterpret_cast<const Acc*>(net.emb)[k];
+    for (int k = threadIdx.x; k < F; k += NT) {
+      const int f = P::lc(k / NS, k % NS);
+      shead[k] = net.head_a[f];
+      shead[F + k] = net.head_p[f];
+    }
+    const Acc* ev = reinterpret_cast<const Acc*>(inc.ell_val);
+    for (int k = threadIdx.x; k < net.n * dm; k += NT) sev[k] = ev[k];
+    for (int k = threadIdx.x; k < net.ne; k += NT) {
+      const int2 ij = net.edges[k];
+      sedge[k] = (unsigned)ij.x | ((unsigned)ij.y << 16);
+    }
+    for (int k = threadIdx.x; k < 4 * kMaxWaves; k += NT) red[k] = 0.0;
+  }
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  const long long total = (long long)n_sweeps * net.n;
+  if constexpr (SWEEP) {
+    if (counter_dev) counter_base += *counter_dev;   // graph replays read the current base
+  }
+  // local energy: XCD-aware order of the work items (as the group kernel)
+  const int X = pg.xcd;
+  const int per_x = gridDim.x / X;
+  const int xid = blockIdx.x % X, slotx = blockIdx.x / X;
+  const long long per_xcd_items = SWEEP ? 0 : (long long)((B - xid + X - 1) / X) * n_chunks;
+  if (threadIdx.x < kPipeMaxD) {
+    const int j = threadIdx.x;
+    st.valid[j] = 0;
+    st.spb[j] = -1;
+    if constexpr (SWEEP) {
+      const int b = blockIdx.x + j * gridDim.x;
+      st.chain[j] = (j < D && b < B) ? b : -1;
+      st.nacc[j] = 0;
+      st.pend[j] = -1;
+      st.tstep[j] = 0;
+    }
+  }
+  if (threadIdx.x == 0) {
+    st.done = 0;
+    st.nplan[0] = st.nplan[1] = 0;
+  }
+  __syncthreads();
+  if constexpr (SWEEP) {   // the slots' first chains
+    for (int j = 0; j < D; ++j)
+      if (st.chain[j] >= 0)
+        for (int k = threadIdx.x; k < net.n; k += NT) sp[j * pg.spw + k] = spins[(size_t)st.chain[j] * net.n + k];
+    __syncthreads();
+  }
+
+  // ---- ring-row copies (all waves share them).  plan_ends: the plan's cumulative
+  // vector counts (uniform); copy_find: item idx -> source vector and LDS byte offset
+  auto plan_ends = [&](int pb, int (&ends)[kPipeMaxL]) {
+    const int np = __builtin_amdgcn_readfirstlane(st.nplan[pb]);
+#pragma unroll
+    for (int x = 0; x < kPipeMaxL; ++x) ends[x] = x < np ? __builtin_amdgcn_readfirstlane(st.plan[pb][x].end) : 0;
+    return np;
+  };
+  auto copy_find = [&](int pb, const int (&ends)[kPipeMaxL], int np, int idx, const V4*& src, int& dst) -> bool {
+    int e = np, start = 0;
+#pragma unroll
+    for (int x = kPipeMaxL - 1; x >= 0; --x)
+      if (x < np && idx < ends[x]) e = x;
+    if (e >= np) return false;
+#pragma unroll
+    for (int x = 0; x + 1 < kPipeMaxL; ++x)
+      if (x + 1 == e) start = ends[x];
+    const PipeCopy& c = st.plan[pb][e];
+    const int rel = idx - start;
+    const int p = c.a + rel / VPR, v = rel % VPR;
+    const int node = tabs[c.tab + kPipeHdr + p], arow = tabs[c.tab + kPipeHdr + r8 + p];
+    src = reinterpret_cast<const V4*>(planes + c.src + (size_t)node * F) + v;
+    dst = pg.off_arena + arow * row_bytes + 16 * v;
+    return true;
+  };
+  V4 cvv[NCOPY];   // ring rows of the next tick, requested before the barrier
+  int cdst[NCOPY];
+#pragma unroll
+  for (int u = 0; u < NCOPY; ++u) cdst[u] = -1;
+  auto copy_store = [&](int T) {   // phase A: this tick's ring rows -> LDS
+#pragma unroll
+    for (int u = 0; u < NCOPY; ++u)
+      if (cdst[u] >= 0) *reinterpret_cast<V4*>(smem + cdst[u]) = cvv[u];
+    int ends[kPipeMaxL];
+    const int np = plan_ends(T & 1, ends);
+    if (np > 0 && ends[np - 1] > NCOPY * NT) {   // rare: more rows than registers
+      for (int idx = threadIdx.x + NCOPY * NT; idx < ends[np - 1]; idx += NT) {
+        const V4* src;
+        int dst;
+        if (copy_find(T & 1, ends, np, idx, src, dst)) *reinterpret_cast<V4*>(smem + dst) = *src;
+      }
+    }
+  };
+  // phase B: the next tick's ring rows -> registers; every thread issues NCOPY loads
+  // (an idle one reads the first plane vector), so that waits for older loads can
+  // leave these in flight
+  auto copy_load = [&](int T) {
+    int ends[kPipeMaxL];
+    const int np = plan_ends((T + 1) & 1, ends);
+#pragma unroll
+    for (int u = 0; u < NCOPY; ++u) {
+      const V4* src = reinterpret_cast<const V4*>(planes);
+      int dst = -1;
+      if (!copy_find((T + 1) & 1, ends, np, threadIdx.x + u * NT, src, dst)) {
+        src = reinterpret_cast<const V4*>(planes);
+        dst = -1;
+      }
+      cvv[u] = *src;
+      cdst[u] = dst;
+    }
+  };
+
+  if (wv == pg.sw) {
+    // ======================= the setup wave =======================
+    V4 tv[kPipeTabVec];   // a job's table (global -> registers), stored at its table tick
+#pragma unroll
+    for (int u = 0; u < kPipeTabVec; ++u) tv[u] = V4{0u, 0u, 0u, 0u};
+    int tjob = -1;        // slot of the job whose table tv holds
+    // local energy: the stream of work items of this workgroup and the sums of the
+    // current one (wave-uniform, kept in registers)
+    long long jj = (long long)slotx - per_x;
+    int it = -1, sb = -1, e0 = 0, clen = 0, cursor = 0, issued = 0;
+    bool sdone = SWEEP;
+    int acc_item = -1, acc_n = 0;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int inflight = 0;
+    int8_t* ss = sp + D * pg.spw;   // the stream's sample
+    auto flush = [&]() {
+      if (acc_item >= 0 && lane == 0) {
+        double* o = partial + 4 * (size_t)acc_item;
+        o[0] = a0; o[1] = a1; o[2] = a2; o[3] = a3;
+        cnt_out[acc_item] = acc_n;
+      }
+    };
+    for (int T = 0;; ++T) {
+      const int tau = T % D;
+      // ---- phase A: the copy plan of the next tick (lane lp - 2 takes the job at
+      // layer lp = 2..L); the table of the job whose table tick this is, its pool
+      // tags (pool << 12 | offset) turned into arena rows; this tick's ring rows
+      {
+        const int tn = T + 1, pb = tn & 1, lp = lane + 2;
+        int n = 0, a = 0, tbo = 0;
+        long long src = 0;
+        if (lp <= Lr) {
+          const int t0 = tn - extra - lp;   // setup tick of the job at layer lp
+          const int j = t0 >= 0 ? t0 % D : 0;
+          const int vj = st.valid[j], tb_j = st.tbo[j], h0 = st.hdr[j][lp], h1 = st.hdr[j][lp + 1];
+          const long long pb_j = st.pboff[j];
+          if (t0 >= 0 && vj) {
+            tbo = tb_j;
+            a = h0;
+            n = (h1 - h0) * VPR;
+            src = pb_j + (long long)(Lr + lp - 1) * (long long)plane;
+          }
+        }
+        int end = n;   // inclusive prefix sum over the lanes
+#pragma unroll
+        for (int o = 1; o < kPipeMaxL; o <<= 1) {
+          const int v = __shfl_up(end, o, 64);
+          if (lane >= o) end += v;
+        }
+        if (lp <= Lr) {
+          PipeCopy& c = st.plan[pb][lane];
+          c.end = end;
+          c.a = a;
+          c.tab = tbo;
+          c.src = src;
+        }
+        if (lane == 0) st.nplan[pb] = Lr - 1;
+      }
+      if (tjob >= 0) {
+        if (lane < Lr) st.rowbase[lane] = pg.pool_base[lane] + (T % pg.pool_cnt[lane]) * pg.pool_rows[lane];
+        const int tbo = (T % ntab) * tabw;
+        uint16_t* tb = tabs + tbo;
+        const int nv = tabw / 8;
+#pragma unroll
+        for (int u = 0; u < kPipeTabVec; ++u) {
+          const int v = lane + 64 * u;
+          if (v >= nv) continue;
+          const V4 x = tv[u];
+          const int g = 8 * v;
+          if (g < kPipeHdr + r8) {
+            *reinterpret_cast<V4*>(tb + g) = x;   // header, node ids
+          } else {
+            unsigned o[4];
+#pragma unroll
+            for (int w4 = 0; w4 < 4; ++w4) {
+              const unsigned lo = x[w4] & 0xffffu, hi = x[w4] >> 16;
+              o[w4] = (unsigned)(st.rowbase[lo >> 12] + (int)(lo & 0xfffu)) |
+                      ((unsigned)(st.rowbase[hi >> 12] + (int)(hi & 0xfffu)) << 16);
+            }
+            *reinterpret_cast<V4*>(tb + g) = V4{o[0], o[1], o[2], o[3]};
+          }
+        }
+        if (lane < kPipeHdr) st.hdr[tjob][lane] = tb[lane];   // the header, for one-step lookups
+        if (lane == 0) st.tbo[tjob] = tbo;
+      }
+      copy_store(T);
+      __syncthreads();
+      // ---- phase B: this wave's readout slots, the job that left slot T mod D and
+      // the slot's next job, the table of the job whose table tick is the next tick,
+      // the next tick's ring rows
+      if (lane == 0) {
+        red[(T & 1) * 2 * kMaxWaves + wv] = 0.0;
+        red[(T & 1) * 2 * kMaxWaves + kMaxWaves + wv] = 0.0;
+      }
+      const int j0 = tau;
+      bool done = false;
+      if (__builtin_amdgcn_readfirstlane(st.valid[j0])) {   // its layer L ran last tick
+        // readout difference: the waves' partials, summed in a fixed order
+        const double* rd = red + ((T - 1) & 1) * 2 * kMaxWaves;
+        double da = lane < nw ? rd[lane & 15] : 0.0, dp = lane < nw ? rd[kMaxWaves + (lane & 15)] : 0.0;
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+          da += __shfl_xor(da, o, 64);
+          dp += __shfl_xor(dp, o, 64);
+        }
+        {
+          const unsigned long long ba = __double_as_longlong(da), bp = __double_as_longlong(dp);
+          da = __longlong_as_double((long long)(((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(ba >> 32)) << 32) |
+                                                (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)ba)));
+          dp = __longlong_as_double((long long)(((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(bp >> 32)) << 32) |
+                                                (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)bp)));
+        }
+        if constexpr (SWEEP) {
+          const int fl = __builtin_amdgcn_readfirstlane(st.flags[j0]);
+          if (fl & kJobReadout) {
+            const double u = st.u[j0];
+            if (u < exp(2.0 * da)) {   // accept: the planes already hold the new rows
+              if (lane == 0) {
+                int8_t* sj = sp + j0 * pg.spw;
+                const int2 ij = st.ij[j0];
+                const int8_t tmp = sj[ij.x];
+                sj[ij.x] = sj[ij.y];
+                sj[ij.y] = tmp;
+                ++st.nacc[j0];
+              }
+            } else if (lane == 0) {
+              st.pend[j0] = st.e[j0];   // reject: the restore job of this bond comes next
+            }
+            if (lane == 0) ++st.tstep[j0];
+          } else if (lane == 0) {
+            st.pend[j0] = -1;   // restored
+          }
+        } else {
+          const int item = __builtin_amdgcn_readfirstlane(st.item[j0]);
+          if (item != acc_item) {
+            flush();
+            acc_item = item;
+            a0 = a1 = a2 = a3 = 0.0;
+            acc_n = 0;
+          }
+          const double mm = exp(da);
+          double sn, cs;
+          sincos(dp, &sn, &cs);
+          inc_neumaier(a0, a1, mm * cs);
+          inc_neumaier(a2, a3, mm * sn);
+          ++acc_n;
+        }
+        if (lane == 0) st.valid[j0] = 0;
+        --inflight;
+      }
+      // ---- the next job of slot j0
+      int e = -1;
+      if constexpr (SWEEP) {
+        int flags = 0;
+        while (__builtin_amdgcn_readfirstlane(st.chain[j0]) >= 0) {
+          const int b = __builtin_amdgcn_readfirstlane(st.chain[j0]);
+          const int pend = __builtin_amdgcn_readfirstlane(st.pend[j0]);
+          if (pend >= 0) {
+            e = pend;
+            flags = 0;
+            break;
+          }
+          // draws t, t+1, ... of the chain, 64 at a time; identity steps are skipped
+          long long t = st.tstep[j0];
+          const int8_t* sj = sp + j0 * pg.spw;
+          while (t < total) {
+            const long long tu = t + lane;
+            const unsigned long long step = counter_base + (unsigned long long)tu;
+            uint32_t c[4] = {(uint32_t)step, (uint32_t)(step >> 32), (uint32_t)b, 0u};
+            philox4x32_10(c, k0, k1);
+            const int eu = (int)(((unsigned long long)c[0] * (unsigned long long)net.ne) >> 32);
+            const unsigned ij = sedge[eu];
+            const bool anti = tu < total && sj[ij & 0xffffu] != sj[ij >> 16];
+            const unsigned long long m = __ballot(anti);
+            if (m) {
+              const int us = __builtin_ctzll(m);
+              e = __builtin_amdgcn_readlane(eu, us);
+              const uint32_t c1 = (uint32_t)__builtin_amdgcn_readlane((int)c[1], us);
+              t += us;
+              if (lane == 0) {
+                st.tstep[j0] = t;
+                st.u[j0] = ((double)c1 + 0.5) * 2.3283064365386963e-10;   // 2^-32
+              }
+              break;
+            }
+            t += 64;
+          }
+          if (e >= 0) {
+            flags = kJobSwap | kJobReadout;
+            break;
+          }
+          // the chain is done: spins and acceptance count out, the slot's next chain in
+          for (int k = lane; k < net.n; k += 64) spins[(size_t)b * net.n + k] = sj[k];
+          const int nb = b + D * gridDim.x;
+          if (lane == 0) {
+            if (n_accept) n_accept[b] = st.nacc[j0];
+            st.chain[j0] = nb < B ? nb : -1;
+            st.nacc[j0] = 0;
+            st.pend[j0] = -1;
+            st.tstep[j0] = 0;
+          }
+          if (nb < B)
+            for (int k = lane; k < net.n; k += 64) sp[j0 * pg.spw + k] = spins[(size_t)nb * net.n + k];
+          __builtin_amdgcn_s_waitcnt(0);
+        }
+        if (e >= 0) {
+          if (lane == 0) {
+            st.valid[j0] = 1;
+            st.flags[j0] = flags;
+            st.e[j0] = e;
+            const unsigned ij = sedge[e];
+            st.ij[j0] = make_int2((int)(ij & 0xffffu), (int)(ij >> 16));
+            st.pboff[j0] = (long long)st.chain[j0] * per;
+            st.t1[j0] = T + extra;
+          }
+          ++inflight;
+        }
+        if (inflight == 0) {
+          int any = 0;
+          for (int j = 0; j < D; ++j) any |= st.chain[j] >= 0;
+          done = !__builtin_amdgcn_readfirstlane(any);
+        }
+      } else {
+        while (!sdone) {
+          // next anti-aligned bond of the current item
+          int found = -1;
+          for (int w = cursor >> 5; w < ((clen + 31) >> 5); ++w) {
+            unsigned m = __builtin_amdgcn_readfirstlane(smask[w]);
+            if (w == (cursor >> 5)) m &= ~0u << (cursor & 31);
+            if (m) {
+              found = (w << 5) + __builtin_ctz(m);
+              break;
+            }
+          }
+          if (found >= 0 && found < clen) {
+            e = e0 + found;
+            cursor = found + 1;
+            ++issued;
+            break;
+          }
+          // the item is exhausted: an item without exchanges reports zero sums now
+          if (it >= 0 && issued == 0 && lane == 0) {
+            double* o = partial + 4 * (size_t)it;
+            o[0] = o[1] = o[2] = o[3] = 0.0;
+            cnt_out[it] = 0;
+          }
+          jj += per_x;
+          if (jj >= per_xcd_items) {
+            sdone = true;
+            break;
+          }
+          const int b = xid + X * (int)(jj / n_chunks), cc = (int)(jj % n_chunks);
+          e0 = cc * chunk;
+          clen = max(0, min(net.ne, e0 + chunk) - e0);
+          if (b != sb) {
+            for (int k = lane; k < net.n; k += 64) ss[k] = spins[(size_t)b * net.n + k];
+            __builtin_amdgcn_s_waitcnt(0);
+            sb = b;
+          }
+          for (int g = 0; g < clen; g += 64) {
+            bool anti = false;
+            if (g + lane < clen) {
+              const unsigned ij = sedge[e0 + g + lane];
+              anti = ss[ij & 0xffffu] != ss[ij >> 16];
+            }
+            const unsigned long long m = __ballot(anti);
+            if (lane == 0) {
+              smask[g >> 5] = (unsigned)m;
+              smask[(g >> 5) + 1] = (unsigned)(m >> 32);
+            }
+          }
+          it = b * n_chunks + cc;
+          cursor = 0;
+          issued = 0;
+        }
+        if (e >= 0) {
+          if (__builtin_amdgcn_readfirstlane(st.spb[j0]) != sb) {   // the slot's spin row
+            const int* srcw = reinterpret_cast<const int*>(ss);
+            int* dstw = reinterpret_cast<int*>(sp + j0 * pg.spw);
+            for (int k = lane; k < pg.spw / 4; k += 64) dstw[k] = srcw[k];
+          }
+          if (lane == 0) {
+            st.spb[j0] = sb;
+            st.valid[j0] = 1;
+            st.flags[j0] = kJobSwap | kJobReadout;
+            st.e[j0] = e;
+            const unsigned ij = sedge[e];
+            st.ij[j0] = make_int2((int)(ij & 0xffffu), (int)(ij >> 16));
+            st.pboff[j0] = (long long)sb * per;
+            st.item[j0] = it;
+            st.t1[j0] = T + extra;
+          }
+          ++inflight;
+        }
+        if (sdone && inflight == 0) {
+          flush();
+          acc_item = -1;
+          done = true;
+        }
+      }
+      if (done && lane == 0) st.done = 1;
+      // ---- the table of the job whose table tick is the next tick
+      {
+        const int t0 = T + 1 - extra;
+        tjob = -1;
+        if (t0 >= 0) {
+          const int j1 = t0 % D;
+          if (__builtin_amdgcn_readfirstlane(st.valid[j1]) && __builtin_amdgcn_readfirstlane(st.t1[j1]) == T + 1) {
+            tjob = j1;
+            const V4* src = reinterpret_cast<const V4*>(gtab + (size_t)__builtin_amdgcn_readfirstlane(st.e[j1]) * tabw);
+            const int nv = tabw / 8;
+#pragma unroll
+            for (int u = 0; u < kPipeTabVec; ++u) tv[u] = src[min(lane + 64 * u, nv - 1)];
+          }
+        }
+      }
+      copy_load(T);
+      __syncthreads();
+      if (done) break;
+    }
+    return;
+  }
+
+  // ======================= the compute waves =======================
+  // MFMA A fragment of weight block blk (0 message, 1 self), K step stp, output tile tt
+  auto afr = [&](int blk, int stp, int tt) { return wl + (((blk * KSB + stp) * MT + tt) * 64 + lane) * VEC; };
+  // the B operands of a tile's layer input (rows r < rows; the others zero)
+  using BF = decltype(P::make_b((const Acc*)nullptr));
+  auto operands = [&](const Acc (&h)[NS], bool keep, BF (&bop)[KSB]) {
+#pragma unroll
+    for (int stp = 0; stp < KSB; ++stp) {
+      Acc x[VEC];
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) x[i] = keep ? h[stp * VEC + i] : (Acc)0;
+      bop[stp] = P::make_b(x);
+    }
+  };
+
+  Acc hn[MAXT][NS];   // a tile's layer input, held across ticks
+#pragma unroll
+  for (int k = 0; k < MAXT; ++k)
+#pragma unroll
+    for (int i = 0; i < NS; ++i) hn[k][i] = (Acc)0;
+
+  for (int T = 0;; ++T) {
+    const int tau = T % D;
+    const uint2 s2 = sched[tau * kMaxWaves + wv];
+    const unsigned long long s8 = (unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)s2.x) |
+                                  ((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)s2.y) << 32);
+    // this tick's tiles (wave-uniform): job slot, tile, layer, table, |C_{l-1}|, |C_l|,
+    // |C_{l+1}| and the rows of the message product (|C_2| at layer 1)
+    int tj[MAXT], tt[MAXT], tl[MAXT], ttb[MAXT], tSm[MAXT], tS[MAXT], tSp[MAXT], tM[MAXT];
+#pragma unroll
+    for (int k = 0; k < MAXT; ++k) {
+      const int ent = (int)((s8 >> (8 * k)) & 0xffu);
+      tl[k] = 0;
+      tj[k] = ent >> 4;
+      tt[k] = ent & 15;
+      if (ent == 0xff) continue;
+      const int l = (tau - tj[k] + D) % D - extra;
+      if (l < 1) continue;
+      const int j = tj[k];
+      const int v = st.valid[j], tbo = st.tbo[j];
+      const int hm = st.hdr[j][l - 1], h = st.hdr[j][l], hp = st.hdr[j][l + 1], h2 = st.hdr[j][2];
+      if (!__builtin_amdgcn_readfirstlane(v)) continue;
+      tl[k] = l;
+      ttb[k] = __builtin_amdgcn_readfirstlane(tbo);
+      tSm[k] = __builtin_amdgcn_readfirstlane(hm);
+      tS[k] = __builtin_amdgcn_readfirstlane(h);
+      tSp[k] = __builtin_amdgcn_readfirstlane(hp);
+      tM[k] = l == 1 ? __builtin_amdgcn_readfirstlane(h2) : tS[k];
+    }
+    // ======================= phase A =======================
+    // ---- message products G'^{l-1} = H'^{l-1} W_msg of the tiles (into LDS rows);
+    // at layer 1 the input is the embedding of the exchanged configuration's spins
+#pragma unroll
+    for (int k = 0; k < MAXT; ++k) {
+      const int l = tl[k], t = tt[k], j = tj[k];
+      if (l < 1 || t * 16 >= tM[k]) continue;
+      const uint16_t* tb = tabs + ttb[k];
+      const int r = t * 16 + col;
+      const bool rin = r < tM[k];
+      const int nd = rin ? (int)tb[kPipeHdr + r] : -1;
+      if (l == 1) {
+        int xs = 0;
+        if (rin) {
+          const int8_t* sj = sp + j * pg.spw;
+          const int2 ij = st.ij[j];
+          int8_t v = sj[nd];
+          if (st.flags[j] & kJobSwap) v = (nd == ij.x) ? sj[ij.y] : ((nd == ij.y) ? sj[ij.x] : v);
+          xs = v > 0 ? 1 : 0;
+        }
+#pragma unroll
+        for (int i = 0; i < NS; ++i) hn[k][i] = semb[xs * F + P::lc(q, i)];
+      }
+      BF bop[KSB];
+      operands(hn[k], rin, bop);
+      Acc* row = arena + (size_t)(rin ? tb[kPipeHdr + r8 + r] : 0) * pg.row_elems + q * NS;
+#pragma unroll
+      for (int t4 = 0; t4 < MT; ++t4) {
+        CF gs = CF{0, 0, 0, 0};
+#pragma unroll
+        for (int stp = 0; stp < KSB; ++stp) gs = P::mma(P::load_a(afr(0, stp, t4)), bop[stp], gs);
+        Acc gm[4] = {gs[0], gs[1], gs[2], gs[3]};
+        if (rin) lds_write<Acc, 4>(row + 4 * t4, gm);
+      }
+    }
+    // ---- ring rows of this tick -> LDS (requested at the end of the last tick)
+    copy_store(T);
+    // ---- sampler: G'^{l-1} changed on C_{l-1}: rows back from LDS into the chain's planes
+    if constexpr (SWEEP) {
+#pragma unroll
+      for (int k = 0; k < MAXT; ++k) {
+        const int l = tl[k], t = tt[k];
+        if (l < 1 || t * 16 >= tSm[k]) continue;
+        const uint16_t* tb = tabs + ttb[k];
+        const int r = t * 16 + col;
+        if (r < tSm[k]) {
+          const int nd = tb[kPipeHdr + r];
+          Acc g[NS];
+          lds_read<Acc, NS>(arena + (size_t)tb[kPipeHdr + r8 + r] * pg.row_elems + q * NS, g);
+          lds_write<Acc, NS>(planes + st.pboff[tj[k]] + (size_t)(Lr + l - 1) * plane + (size_t)nd * F + q * NS, g);
+        }
+      }
+    }
+    // ---- base H^l of ring l+1 into the lanes of hn that layer l+1 reads from it
+#pragma unroll
+    for (int k = 0; k < MAXT; ++k) {
+      const int l = tl[k], t = tt[k];
+      if (l < 1 || l >= Lr || t * 16 >= tSp[k] || t * 16 + 16 <= tS[k]) continue;
+      const int r = t * 16 + col;
+      if (r >= tS[k] && r < tSp[k]) {
+        const int nd = tabs[ttb[k] + kPipeHdr + r];
+        gmem_read<Acc, NS>(planes + st.pboff[tj[k]] + (size_t)(l - 1) * plane + (size_t)nd * F + q * NS, hn[k]);
+      }
+    }
+    // ---- base readout partials of the rows of C_L (tiles at layer L), requested
+    // before the barrier (with 16 waves, whose registers are scarce, in phase B)
+    constexpr bool kR0Early = NT < 1024;
+    double r0[MAXT][2];
+    auto r0_load = [&](int k) {
+      r0[k][0] = r0[k][1] = 0.0;
+      const int l = tl[k], t = tt[k];
+      if (l != Lr || t * 16 >= tS[k] || !(st.flags[tj[k]] & kJobReadout)) return;
+      const int r = t * 16 + col;
+      if (r < tS[k]) {
+        const int nd = tabs[ttb[k] + kPipeHdr + r];
+        const double* rp = reinterpret_cast<const double*>(planes + st.pboff[tj[k]] + (size_t)(Lr - 1) * plane) +
+                           (size_t)nd * 8 + q * 2;
+        r0[k][0] = rp[0];
+        r0[k][1] = rp[1];
+      }
+    };
+    if (kR0Early) {
+#pragma unroll
+      for (int k = 0; k < MAXT; ++k) r0_load(k);
+    }
+    __syncthreads();
+    // ======================= phase B =======================
+    // the next tick's ring rows: in flight during this phase (with 16 waves, whose
+    // registers are scarce, requested after it)
+    if (kR0Early) copy_load(T);
+    double wa = 0.0, wp = 0.0;   // this wave's readout differences of the job at layer L
+#pragma unroll
+    for (int k = 0; k < MAXT; ++k) {
+      const int l = tl[k], t = tt[k], j = tj[k];
+      if (l < 1 || t * 16 >= tS[k]) continue;
+      const uint16_t* tb = tabs + ttb[k];
+      const int r = t * 16 + col;
+      const bool in = r < tS[k];
+      const int nd = in ? (int)tb[kPipeHdr + r] : -1;
+      Acc* pw = planes + st.pboff[j];
+      const bool last = l == Lr;
+      const bool rd = last && (st.flags[j] & kJobReadout);
+      if (!kR0Early) r0_load(k);
+      // gather sum_d A_hat[n][d] G'^{l-1}[nbr(n, d)] over the job's LDS rows
+      Acc m[NS];
+#pragma unroll
+      for (int i = 0; i < NS; ++i) m[i] = (Acc)0;
+      if (in) {
+        const uint16_t* nbp = tb + kPipeHdr + 2 * r8 + r * dm;
+        for (int d = 0; d < dm; d += 4) {
+          const uint2 pv = *reinterpret_cast<const uint2*>(nbp + d);
+          const int pc[4] = {(int)(pv.x & 0xffffu), (int)(pv.x >> 16), (int)(pv.y & 0xffffu), (int)(pv.y >> 16)};
+          const Acc* wp4 = sev + nd * dm + d;
+          const Acc wt[4] = {wp4[0], wp4[1], wp4[2], wp4[3]};
+#pragma unroll
+          for (int uu = 0; uu < 4; ++uu) {
+            Acc rowv[NS];
+            lds_read<Acc, NS>(arena + (size_t)pc[uu] * pg.row_elems + q * NS, rowv);
+#pragma unroll
+            for (int i = 0; i < NS; ++i) m[i] += wt[uu] * rowv[i];
+            if (NT == 1024) __builtin_amdgcn_sched_barrier(0);   // one neighbour row in flight
+          }
+        }
+      }
+      // self product b + H'^{l-1} W_self on the rows of C_l, then the activation
+      {
+        BF bop[KSB];
+        operands(hn[k], in, bop);
+        const Acc* bias = sbias + q * NS;
+#pragma unroll
+        for (int t4 = 0; t4 < MT; ++t4) {
+          CF a;
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) a[rr] = bias[4 * t4 + rr];
+#pragma unroll
+          for (int stp = 0; stp < KSB; ++stp) a = P::mma(P::load_a(afr(1, stp, t4)), bop[stp], a);
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) m[4 * t4 + rr] += a[rr];   // pre-activation (the sum is commutative)
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < NS; ++i) m[i] = P::act(m[i]);
+#pragma unroll
+      for (int i = 0; i < NS; ++i) hn[k][i] = in ? m[i] : hn[k][i];
+      if (last && (rd || SWEEP)) {   // wave-uniform
+        const double* va = shead + q * NS;
+        const double* vp = shead + F + q * NS;
+        double ta1 = 0, tp1 = 0;
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+          ta1 += va[i] * (double)m[i];
+          tp1 += vp[i] * (double)m[i];
+        }
+        if (rd) {
+          double pa = in ? ta1 - r0[k][0] : 0.0;
+          double pp = in ? tp1 - r0[k][1] : 0.0;
+          wa += wave_sum_dpp(pa);
+          wp += wave_sum_dpp(pp);
+        }
+        if (SWEEP && in) {   // after the base partials were read
+          const double rv[2] = {ta1, tp1};
+          lds_write<double, 2>(reinterpret_cast<double*>(pw + (size_t)(Lr - 1) * plane) + (size_t)nd * 8 + q * 2, rv);
+        }
+      } else if (SWEEP && !last && in) {   // H^l changed on C_l
+        lds_write<Acc, NS>(pw + (size_t)(l - 1) * plane + (size_t)nd * F + q * NS, m);
+      }
+    }
+    if (lane == 0) {
+      red[(T & 1) * 2 * kMaxWaves + wv] = wa;
+      red[(T & 1) * 2 * kMaxWaves + kMaxWaves + wv] = wp;
+    }
+    if (!kR0Early) copy_load(T);
+    __syncthreads();
+    if (st.done) break;
+  }
+}
+
+template <class P, int F, int MAXT, int NT, int NCOPY>
+__global__ __launch_bounds__(NT) void k_eloc_pipe(Net net, IncNet inc, PipeGeo pg, const uint2* __restrict__ sched,
+                                                   const uint16_t* __restrict__ gtab, const int8_t* __restrict__ spins,
+                                                   int B, const typename P::Acc* __restrict__ planes, int n_chunks,
+                                                   int chunk, double* __restrict__ partial, int* __restrict__ cnt) {
+  pipe_body<P, F, MAXT, NT, NCOPY, false>(net, inc, pg, sched, gtab, const_cast<int8_t*>(spins), B,
+                                          const_cast<typename P::Acc*>(planes), n_chunks, chunk, partial, cnt, 0, 0,
+                                          0, nullptr, nullptr);
+}
+
+template <class P, int F, int MAXT, int NT, int NCOPY>
+__global__ __launch_bounds__(NT) void k_sweep_pipe(Net net, IncNet inc, PipeGeo pg, const uint2* __restrict__ sched,
+                                                    const uint16_t* __restrict__ gtab, int8_t* __restrict__ spins,
+                                                    typename P::Acc* planes, int B, int n_sweeps,
+                                                    unsigned long long seed, unsigned long long counter_base,
+                                                    const unsigned long long* __restrict__ counter_dev,
+                                                    int* __restrict__ n_accept) {
+  pipe_body<P, F, MAXT, NT, NCOPY, true>(net, inc, pg, sched, gtab, spins, B, planes, 1, 1, nullptr, nullptr, n_sweeps,
+                                         seed, counter_base, counter_dev, n_accept);
+}
+
+}  // namespace gna

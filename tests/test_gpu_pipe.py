@@ -1,0 +1,221 @@
+"""The layer-pipelined incremental kernels (shape jobs_in_flight = 0) against the
+group kernels: the same exchanged-configuration rows (bit-identical arithmetic), so
+local energies agree to the order of the final FP64 sums and the sampler takes the
+same decisions on the same Philox draws (trajectories and acceptance counts equal),
+for 8- and 16-wave workgroups, every incremental graph of the workloads and the
+reduced precisions; spot rows against the FP64 oracle."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda", 0)
+# energy per site of three spot rows at far-from-uniform weights against the oracle;
+# single-pass BF16's per-sample rounding does not average out over three rows
+# (the group kernel gives the same rows), hence its looser spot bound
+EPS_SITE = {"fp32": 1e-5, "bf16": 1e-3, "bf16_1x": 1e-2}
+
+CASES = [
+    # name, graph builder, F, L, B
+    ("kagome12", lambda: w.kagome(2, 2), 16, 2, 64),
+    ("kagome108", lambda: w.kagome(6, 6), 32, 4, 24),
+    ("tri144", lambda: w.triangular(12, 12), 32, 4, 12),
+    ("er100", lambda: w.erdos_renyi_connected(100, 0.06, 0), 32, 4, 16),
+]
+
+
+# graph and workgroup size whose tiles do not fit in the pipelined kernels' wave
+# registers: the Erdos-Renyi graph's 4-hop balls cover the graph from the first
+# layers on (26 tile registers live per tick), which 15 waves of two do not hold
+REFUSED = {("er100", 16)}
+
+
+def _ctx(n, e, F, L, prec, B, waves=None, px=2):
+    from paper_2011_12453_amd import GNA
+    shape = "group" if waves is None else f"pipelined/{waves}"
+    print(f"[gpu] pipe ctx N={n} E={len(e)} F={F} L={L} {prec} B={B} {shape}", file=sys.stderr, flush=True)
+    g = GNA(n, e, F, L, tied=True, precision=prec, max_batch=B, device=DEV, eloc_mode="incremental")
+    if waves is not None:
+        g.set_shape(0, waves, px)
+        info = g.config_info()
+        assert info["jobs_in_flight"] == 0 and info["sweep_jobs_in_flight"] == 0
+        assert info["waves"] == waves and info["sweep_waves"] == waves
+    return g
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _refused(n, e, F, L, prec, B, waves):
+    from paper_2011_12453_amd.binding import GnaError
+    g = _ctx(n, e, F, L, prec, B)
+    before = g.config_info()
+    with pytest.raises(GnaError):
+        g.set_shape(0, waves, 2)
+    assert g.config_info() == before
+    g.close()
+
+
+def _batch(n, B, seed):
+    s = w.random_sz0_spins(B, n, seed)
+    s[0] = 1   # a polarised row: no anti-aligned bond, no exchange (its work items are empty)
+    return s
+
+
+@pytest.mark.parametrize("waves", [8, 16])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16_1x"])
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_pipelined_local_energy_equals_group(case, prec, waves):
+    name, build, F, L, B = case
+    n, e = build()
+    if (name, waves) in REFUSED:
+        _refused(n, e, F, L, prec, B, waves)
+        return
+    theta = w.glorot_theta(F, L, True, seed=3, weight_scale=1.5, bias_std=0.3)
+    spins = _batch(n, B, 4000 + B)
+    th, sp = _dev(theta), _dev(spins)
+    ref = _ctx(n, e, F, L, prec, B)
+    el_r, nev_r = ref.local_energy(th, sp)
+    ref.close()
+    g = _ctx(n, e, F, L, prec, B, waves)
+    el, nev = g.local_energy(th, sp)
+    el2, _ = g.local_energy(th, sp[: B // 2 + 1])   # a smaller batch on the same context
+    g.close()
+    assert int(nev.item()) == int(nev_r.item()) == oracle.n_evals(spins, e)
+    scale = float(el_r.abs().max())
+    err = float((el - el_r).abs().max()) / scale
+    print(f"[gpu] pipelined {name} {prec} {waves} waves: eloc vs group rel {err:.2e}", file=sys.stderr, flush=True)
+    assert err < 1e-12   # same rows; only the order of the FP64 sums over waves and bonds differs
+    assert float((el2 - el[: B // 2 + 1]).abs().max()) <= 1e-12 * scale
+    # spot rows against the oracle, to the precision's bound
+    rows = [0, 1, B - 1]
+    ref_o = oracle.local_energy(theta, spins[rows], n, e, F, L, True)
+    site = abs(np.mean(el.cpu().numpy()[rows, 0]) - np.mean(ref_o.real)) / n / max(abs(np.mean(ref_o.real)) / n, 1e-2)
+    assert site < EPS_SITE[prec]
+
+
+@pytest.mark.parametrize("waves", [8, 16])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16_1x"])
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_pipelined_sampler_equals_group(case, prec, waves):
+    name, build, F, L, B = case
+    n, e = build()
+    if (name, waves) in REFUSED:
+        _refused(n, e, F, L, prec, B, waves)
+        return
+    theta = w.glorot_theta(F, L, True, seed=5, weight_scale=1.5, bias_std=0.3)
+    s0 = w.random_sz0_spins(B, n, 2000 + B)
+    out = []
+    for wv in (None, waves):
+        g = _ctx(n, e, F, L, prec, B, wv)
+        th, sp = _dev(theta), _dev(s0)
+        lp = g.logpsi(th, sp)
+        acc = g.metropolis_sweep(th, sp, lp, n_sweeps=2, seed=4242, counter_base=9)
+        el, _ = g.local_energy(th, sp)   # the planes the sweep left are rebuilt and agree
+        out.append((sp.cpu().numpy(), lp.cpu().numpy(), acc.cpu().numpy(), el.cpu().numpy()))
+        g.close()
+    (sr, lr, ar, er), (sq, lq, aq, eq) = out
+    print(f"[gpu] pipelined sampler {name} {prec} {waves} waves: accepted {aq.sum()} of {B * 2 * n} draws",
+          file=sys.stderr, flush=True)
+    assert np.array_equal(sq, sr) and np.array_equal(aq, ar) and np.array_equal(lq, lr)
+    assert np.max(np.abs(eq - er)) <= 1e-12 * np.max(np.abs(er))
+
+
+@pytest.mark.parametrize("waves", [8, 16])
+def test_pipelined_sweep_then_isgo_step(waves):
+    # gna_step skips the base pass after an incremental sweep (the planes are
+    # current): the pipelined sweep must leave them exactly as the group sweep does
+    n, e = w.kagome(6, 6)
+    F, L, B = 32, 4, 16
+    theta = w.glorot_theta(F, L, True, seed=6, weight_scale=1.5, bias_std=0.3)
+    s0 = w.random_sz0_spins(B, n, 17)
+    res = []
+    for wv in (None, waves):
+        g = _ctx(n, e, F, L, "bf16", B, wv)
+        th, sp = _dev(theta), _dev(s0)
+        lp = torch.empty(B, 2, dtype=torch.float64, device=DEV)
+        counter = torch.zeros(1, dtype=torch.int64, device=DEV)
+        grad, stats, el, acc = g.step(th, sp, lp, 1, 99, counter, 1e-3)
+        torch.cuda.synchronize()
+        res.append((sp.cpu(), acc.cpu(), el.cpu(), grad.cpu(), th.cpu()))
+        g.close()
+    (s1, a1, e1, g1, t1), (s2, a2, e2, g2, t2) = res
+    assert torch.equal(s1, s2) and torch.equal(a1, a2)
+    assert float((e1 - e2).abs().max()) <= 1e-12 * float(e1.abs().max())
+    assert float((g1 - g2).abs().max()) <= 1e-9 * float(g1.abs().max())
+
+
+def test_pipelined_small_batches_and_zero_sweeps():
+    n, e = w.kagome(2, 2)
+    theta = w.glorot_theta(16, 2, True, seed=2, weight_scale=1.5, bias_std=0.3)
+    s0 = w.random_sz0_spins(5, n, 3)
+    g = _ctx(n, e, 16, 2, "fp32", 8, 8)
+    ref = _ctx(n, e, 16, 2, "fp32", 8)
+    th = _dev(theta)
+    for B in (1, 2, 5):
+        el, _ = g.local_energy(th, _dev(s0[:B]))
+        el_r, _ = ref.local_energy(th, _dev(s0[:B]))
+        assert float((el - el_r).abs().max()) <= 1e-12 * float(el_r.abs().max())
+    sp = _dev(s0)
+    acc = g.metropolis_sweep(th, sp, g.logpsi(th, sp), n_sweeps=0, seed=1)
+    assert np.array_equal(sp.cpu().numpy(), s0) and int(acc.abs().sum()) == 0
+    sp1 = _dev(s0[:1])
+    g.metropolis_sweep(th, sp1, g.logpsi(th, sp1), n_sweeps=3, seed=1)
+    assert int(sp1.sum()) == 0
+    g.close()
+    ref.close()
+
+
+def test_pipelined_full_size_equals_group_and_oracle():
+    # 432-site Kagome, L = 6, F = 64, split BF16: the benchmark's own shape
+    p = w.preset("kagome432_L6F64")
+    n, e = p.build_graph()
+    F, L = p.n_features, p.n_layers
+    theta = w.glorot_theta(F, L, True, seed=p.theta_seed, weight_scale=1.5, bias_std=0.3)
+    spins = w.random_sz0_spins(48, n, p.spin_seed)
+    th, sp = _dev(theta), _dev(spins)
+    ref = _ctx(n, e, F, L, "bf16", 48)
+    el_r, _ = ref.local_energy(th, sp)
+    ref.close()
+    for waves in (8, 16):
+        g = _ctx(n, e, F, L, "bf16", 48, waves)
+        el, _ = g.local_energy(th, sp)
+        s1, s2 = sp[:16].clone(), sp[:16].clone()
+        a1 = g.metropolis_sweep(th, s1, g.logpsi(th, s1), n_sweeps=1, seed=77)
+        g.close()
+        r = _ctx(n, e, F, L, "bf16", 16)
+        a2 = r.metropolis_sweep(th, s2, r.logpsi(th, s2), n_sweeps=1, seed=77)
+        r.close()
+        err = float((el - el_r).abs().max()) / float(el_r.abs().max())
+        print(f"[gpu] pipelined kagome432 bf16 {waves} waves: eloc vs group rel {err:.2e}, "
+              f"accepted {int(a1.sum())}", file=sys.stderr, flush=True)
+        assert err < 1e-12
+        assert torch.equal(s1, s2) and torch.equal(a1, a2)
+    ref_o = oracle.local_energy(theta, spins[:2], n, e, F, L, True)
+    got = el_r.cpu().numpy()[:2, 0]
+    off = ref_o.real - len(e) / 4.0
+    assert np.max(np.abs(got - ref_o.real)) < 5e-2 * np.max(np.abs(off))
+
+
+def test_pipelined_shape_refusals():
+    from paper_2011_12453_amd.binding import GnaError
+    n, e = w.kagome(2, 2)
+    g = _ctx(n, e, 16, 2, "fp64", 8)   # no pipelined FP64 instantiation
+    before = g.config_info()
+    with pytest.raises(GnaError):
+        g.set_shape(0, 8, 1)
+    assert g.config_info() == before
+    g.close()
+    g = _ctx(n, e, 16, 2, "bf16", 8)
+    before = g.config_info()
+    with pytest.raises(GnaError):
+        g.set_shape(0, 6, 1)   # the pipelined kernels take 8 or 16 waves
+    assert g.config_info() == before
+    g.close()

@@ -205,7 +205,7 @@ def test_set_shape_rejects_bad_shapes():
     n, e = w.kagome(6, 6)
     g = _ctx(n, e, 32, 4, "bf16", 8, "incremental")
     before = g.config_info()
-    for args in ((0, 8, 1), (9, 8, 1), (2, 12, 1), (2, 8, 0), (8, 1, 1)):
+    for args in ((-1, 8, 1), (0, 6, 1), (9, 8, 1), (2, 12, 1), (2, 8, 0), (8, 1, 1)):
         with pytest.raises(GnaError):
             g.set_shape(*args)
         assert g.config_info() == before
