@@ -1240,7 +1240,13 @@ gna_status pipe_configure(gna_ctx* c, IncShape shp, int which) {
   g.off_ev = (int)o; o = al(o + (size_t)N * dmax * c->sz_Acc);
   g.off_edges = (int)o; o = al(o + (size_t)std::max(c->E, 1) * 4);
   g.off_mask = (int)o; o = al(o + (size_t)kPipeMaskWords * 4);
+  g.rows_max = 1;   // ring rows copied in one tick: rings 3 .. L+1, one job at each layer
+  for (int sr = 3; sr <= L + 1; ++sr) g.rows_max += c->ball_ringmax[sr];
+  g.off_rows = (int)o; o = al(o + (size_t)2 * g.rows_max * 8);
   g.lds_bytes = (int)o;
+  // the row list holds source offsets in 16-byte vectors of the planes as 32-bit words
+  if ((double)c->max_batch * 2 * L * c->geo.npad * F * c->sz_Acc / 16 >= 4294967296.0)
+    return fail(c, GNA_UNSUPPORTED, "pipelined kernels: the planes exceed 32-bit vector offsets");
   if (o + sizeof(PipeState) + 256 > c->lds_max)
     return fail(c, GNA_UNSUPPORTED, "pipelined kernels: the shape does not fit in LDS");
   std::vector<uint2> sched;

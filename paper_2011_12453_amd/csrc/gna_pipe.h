@@ -57,17 +57,10 @@ struct PipeGeo {
   int ntab;                 // LDS tables (L + 1)
   int spw;                  // bytes per spin row in LDS
   int off_w, off_arena, off_tab, off_sp, off_red, off_bias, off_emb, off_head, off_ev, off_edges, off_mask;
+  int off_rows;             // ring rows of a tick's copies: [2 (tick parity)][rows_max] uint2
+  int rows_max;             // ring rows copied in one tick at most
   int xcd;
   int lds_bytes;
-};
-
-// one layer's ring rows in a tick's copy plan
-struct PipeCopy {
-  int end;          // 16-byte vectors of the plan through this entry
-  int a;            // first list position
-  int tab;          // LDS table of the job (uint16 offset)
-  int pad;
-  long long src;    // element offset of the source plane G^{l-1} of the job's sample
 };
 
 // job state of a workgroup (LDS)
@@ -88,8 +81,7 @@ struct PipeState {
   long long tstep[kPipeMaxD];
   double u[kPipeMaxD];
   int rowbase[kPipeMaxL];                     // first arena row of each pool slot of the job converted
-  PipeCopy plan[2][kPipeMaxL];                // ring-row copies of the next tick (by tick parity)
-  int nplan[2];
+  int nrows[2];                               // ring rows copied in a tick (by tick parity)
   int done;
 };
 
@@ -196,7 +188,7 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
   }
   if (threadIdx.x == 0) {
     st.done = 0;
-    st.nplan[0] = st.nplan[1] = 0;
+    st.nrows[0] = st.nrows[1] = 0;
   }
   __syncthreads();
   if constexpr (SWEEP) {   // the slots' first chains
@@ -206,29 +198,16 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
     __syncthreads();
   }
 
-  // ---- ring-row copies (all waves share them).  plan_ends: the plan's cumulative
-  // vector counts (uniform); copy_find: item idx -> source vector and LDS byte offset
-  auto plan_ends = [&](int pb, int (&ends)[kPipeMaxL]) {
-    const int np = __builtin_amdgcn_readfirstlane(st.nplan[pb]);
-#pragma unroll
-    for (int x = 0; x < kPipeMaxL; ++x) ends[x] = x < np ? __builtin_amdgcn_readfirstlane(st.plan[pb][x].end) : 0;
-    return np;
-  };
-  auto copy_find = [&](int pb, const int (&ends)[kPipeMaxL], int np, int idx, const V4*& src, int& dst) -> bool {
-    int e = np, start = 0;
-#pragma unroll
-    for (int x = kPipeMaxL - 1; x >= 0; --x)
-      if (x < np && idx < ends[x]) e = x;
-    if (e >= np) return false;
-#pragma unroll
-    for (int x = 0; x + 1 < kPipeMaxL; ++x)
-      if (x + 1 == e) start = ends[x];
-    const PipeCopy& c = st.plan[pb][e];
-    const int rel = idx - start;
-    const int p = c.a + rel / VPR, v = rel % VPR;
-    const int node = tabs[c.tab + kPipeHdr + p], arow = tabs[c.tab + kPipeHdr + r8 + p];
-    src = reinterpret_cast<const V4*>(planes + c.src + (size_t)node * F) + v;
-    dst = pg.off_arena + arow * row_bytes + 16 * v;
+  // ---- ring-row copies (all waves share them): the rows of a tick are listed by the
+  // setup wave (source 16-byte vector in the planes, destination byte offset in LDS);
+  // item idx is vector idx % VPR of listed row idx / VPR
+  const uint2* rows_l = reinterpret_cast<const uint2*>(smem + pg.off_rows);
+  auto copy_find = [&](int pb, int nr, int idx, const V4*& src, int& dst) -> bool {
+    const int rw = idx / VPR, v = idx % VPR;
+    if (rw >= nr) return false;
+    const uint2 rc = rows_l[pb * pg.rows_max + rw];
+    src = reinterpret_cast<const V4*>(planes) + (size_t)rc.x + v;
+    dst = (int)rc.y + 16 * v;
     return true;
   };
   V4 cvv[NCOPY];   // ring rows of the next tick, requested before the barrier
@@ -239,27 +218,23 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
 #pragma unroll
     for (int u = 0; u < NCOPY; ++u)
       if (cdst[u] >= 0) *reinterpret_cast<V4*>(smem + cdst[u]) = cvv[u];
-    int ends[kPipeMaxL];
-    const int np = plan_ends(T & 1, ends);
-    if (np > 0 && ends[np - 1] > NCOPY * NT) {   // rare: more rows than registers
-      for (int idx = threadIdx.x + NCOPY * NT; idx < ends[np - 1]; idx += NT) {
-        const V4* src;
-        int dst;
-        if (copy_find(T & 1, ends, np, idx, src, dst)) *reinterpret_cast<V4*>(smem + dst) = *src;
-      }
+    const int nr = __builtin_amdgcn_readfirstlane(st.nrows[T & 1]);
+    for (int idx = threadIdx.x + NCOPY * NT; idx < nr * VPR; idx += NT) {   // rare: more rows than registers
+      const V4* src;
+      int dst;
+      if (copy_find(T & 1, nr, idx, src, dst)) *reinterpret_cast<V4*>(smem + dst) = *src;
     }
   };
   // phase B: the next tick's ring rows -> registers; every thread issues NCOPY loads
   // (an idle one reads the first plane vector), so that waits for older loads can
   // leave these in flight
   auto copy_load = [&](int T) {
-    int ends[kPipeMaxL];
-    const int np = plan_ends((T + 1) & 1, ends);
+    const int nr = __builtin_amdgcn_readfirstlane(st.nrows[(T + 1) & 1]);
 #pragma unroll
     for (int u = 0; u < NCOPY; ++u) {
       const V4* src = reinterpret_cast<const V4*>(planes);
       int dst = -1;
-      if (!copy_find((T + 1) & 1, ends, np, threadIdx.x + u * NT, src, dst)) {
+      if (!copy_find((T + 1) & 1, nr, threadIdx.x + u * NT, src, dst)) {
         src = reinterpret_cast<const V4*>(planes);
         dst = -1;
       }
@@ -292,10 +267,10 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
     };
     for (int T = 0;; ++T) {
       const int tau = T % D;
-      // ---- phase A: the copy plan of the next tick (lane lp - 2 takes the job at
-      // layer lp = 2..L); the table of the job whose table tick this is, its pool
-      // tags (pool << 12 | offset) turned into arena rows; this tick's ring rows
-      {
+      // ---- phase A: the list of the next tick's ring rows; the table of the job
+      // whose table tick this is, its pool tags (pool << 12 | offset) turned into
+      // arena rows; this tick's ring rows
+      {   // ring rows of the next tick: layer lp = 2..L in turn (lane lp - 2 looks up its job)
         const int tn = T + 1, pb = tn & 1, lp = lane + 2;
         int n = 0, a = 0, tbo = 0;
         long long src = 0;
@@ -307,24 +282,24 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
           if (t0 >= 0 && vj) {
             tbo = tb_j;
             a = h0;
-            n = (h1 - h0) * VPR;
+            n = h1 - h0;
             src = pb_j + (long long)(Lr + lp - 1) * (long long)plane;
           }
         }
-        int end = n;   // inclusive prefix sum over the lanes
-#pragma unroll
-        for (int o = 1; o < kPipeMaxL; o <<= 1) {
-          const int v = __shfl_up(end, o, 64);
-          if (lane >= o) end += v;
+        uint2* rl = reinterpret_cast<uint2*>(smem + pg.off_rows) + pb * pg.rows_max;
+        int start = 0;
+        for (int x = 0; x + 2 <= Lr; ++x) {   // entries in layer order, rows over the lanes
+          const int nx = __shfl(n, x, 64), ax = __shfl(a, x, 64), tx = __shfl(tbo, x, 64);
+          const long long sx = __shfl(src, x, 64);
+          for (int rw = lane; rw < nx; rw += 64) {
+            const int p = ax + rw;
+            const int node = tabs[tx + kPipeHdr + p], arow = tabs[tx + kPipeHdr + r8 + p];
+            rl[start + rw] = make_uint2((unsigned)((sx + (long long)node * F) / (16 / (int)sizeof(Acc))),
+                                        (unsigned)(pg.off_arena + arow * row_bytes));
+          }
+          start += nx;
         }
-        if (lp <= Lr) {
-          PipeCopy& c = st.plan[pb][lane];
-          c.end = end;
-          c.a = a;
-          c.tab = tbo;
-          c.src = src;
-        }
-        if (lane == 0) st.nplan[pb] = Lr - 1;
+        if (lane == 0) st.nrows[pb] = start;
       }
       if (tjob >= 0) {
         if (lane < Lr) st.rowbase[lane] = pg.pool_base[lane] + (T % pg.pool_cnt[lane]) * pg.pool_rows[lane];
@@ -617,39 +592,44 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
     const uint2 s2 = sched[tau * kMaxWaves + wv];
     const unsigned long long s8 = (unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)s2.x) |
                                   ((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)s2.y) << 32);
-    // this tick's tiles (wave-uniform): job slot, tile, layer, table, |C_{l-1}|, |C_l|,
-    // |C_{l+1}| and the rows of the message product (|C_2| at layer 1)
-    int tj[MAXT], tt[MAXT], tl[MAXT], ttb[MAXT], tSm[MAXT], tS[MAXT], tSp[MAXT], tM[MAXT];
+    // this tick's tiles (wave-uniform, packed): tk = layer | tile << 8 | slot << 12
+    // (layer 0: idle), tb = the job's LDS table, sz = |C_l| | |C_{l+1}| << 16,
+    // sm = |C_{l-1}| | message rows (|C_2| at layer 1, else |C_l|) << 16
+    int tk[MAXT], ttb[MAXT], tsz[MAXT], tsm[MAXT];
 #pragma unroll
     for (int k = 0; k < MAXT; ++k) {
       const int ent = (int)((s8 >> (8 * k)) & 0xffu);
-      tl[k] = 0;
-      tj[k] = ent >> 4;
-      tt[k] = ent & 15;
+      tk[k] = 0;
+      ttb[k] = tsz[k] = tsm[k] = 0;
       if (ent == 0xff) continue;
-      const int l = (tau - tj[k] + D) % D - extra;
+      const int j = ent >> 4;
+      const int l = (tau - j + D) % D - extra;
       if (l < 1) continue;
-      const int j = tj[k];
       const int v = st.valid[j], tbo = st.tbo[j];
       const int hm = st.hdr[j][l - 1], h = st.hdr[j][l], hp = st.hdr[j][l + 1], h2 = st.hdr[j][2];
       if (!__builtin_amdgcn_readfirstlane(v)) continue;
-      tl[k] = l;
+      tk[k] = l | (ent & 15) << 8 | j << 12;
       ttb[k] = __builtin_amdgcn_readfirstlane(tbo);
-      tSm[k] = __builtin_amdgcn_readfirstlane(hm);
-      tS[k] = __builtin_amdgcn_readfirstlane(h);
-      tSp[k] = __builtin_amdgcn_readfirstlane(hp);
-      tM[k] = l == 1 ? __builtin_amdgcn_readfirstlane(h2) : tS[k];
+      tsz[k] = __builtin_amdgcn_readfirstlane(h | hp << 16);
+      tsm[k] = __builtin_amdgcn_readfirstlane(hm | (l == 1 ? h2 : h) << 16);
     }
+    auto tl = [&](int k) { return tk[k] & 0xff; };
+    auto tt = [&](int k) { return (tk[k] >> 8) & 15; };
+    auto tj = [&](int k) { return tk[k] >> 12; };
+    auto tS = [&](int k) { return tsz[k] & 0xffff; };
+    auto tSp = [&](int k) { return tsz[k] >> 16; };
+    auto tSm = [&](int k) { return tsm[k] & 0xffff; };
+    auto tM = [&](int k) { return tsm[k] >> 16; };
     // ======================= phase A =======================
     // ---- message products G'^{l-1} = H'^{l-1} W_msg of the tiles (into LDS rows);
     // at layer 1 the input is the embedding of the exchanged configuration's spins
 #pragma unroll
     for (int k = 0; k < MAXT; ++k) {
-      const int l = tl[k], t = tt[k], j = tj[k];
-      if (l < 1 || t * 16 >= tM[k]) continue;
+      const int l = tl(k), t = tt(k), j = tj(k);
+      if (l < 1 || t * 16 >= tM(k)) continue;
       const uint16_t* tb = tabs + ttb[k];
       const int r = t * 16 + col;
-      const bool rin = r < tM[k];
+      const bool rin = r < tM(k);
       const int nd = rin ? (int)tb[kPipeHdr + r] : -1;
       if (l == 1) {
         int xs = 0;
@@ -681,27 +661,27 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
     if constexpr (SWEEP) {
 #pragma unroll
       for (int k = 0; k < MAXT; ++k) {
-        const int l = tl[k], t = tt[k];
-        if (l < 1 || t * 16 >= tSm[k]) continue;
+        const int l = tl(k), t = tt(k);
+        if (l < 1 || t * 16 >= tSm(k)) continue;
         const uint16_t* tb = tabs + ttb[k];
         const int r = t * 16 + col;
-        if (r < tSm[k]) {
+        if (r < tSm(k)) {
           const int nd = tb[kPipeHdr + r];
           Acc g[NS];
           lds_read<Acc, NS>(arena + (size_t)tb[kPipeHdr + r8 + r] * pg.row_elems + q * NS, g);
-          lds_write<Acc, NS>(planes + st.pboff[tj[k]] + (size_t)(Lr + l - 1) * plane + (size_t)nd * F + q * NS, g);
+          lds_write<Acc, NS>(planes + st.pboff[tj(k)] + (size_t)(Lr + l - 1) * plane + (size_t)nd * F + q * NS, g);
         }
       }
     }
     // ---- base H^l of ring l+1 into the lanes of hn that layer l+1 reads from it
 #pragma unroll
     for (int k = 0; k < MAXT; ++k) {
-      const int l = tl[k], t = tt[k];
-      if (l < 1 || l >= Lr || t * 16 >= tSp[k] || t * 16 + 16 <= tS[k]) continue;
+      const int l = tl(k), t = tt(k);
+      if (l < 1 || l >= Lr || t * 16 >= tSp(k) || t * 16 + 16 <= tS(k)) continue;
       const int r = t * 16 + col;
-      if (r >= tS[k] && r < tSp[k]) {
+      if (r >= tS(k) && r < tSp(k)) {
         const int nd = tabs[ttb[k] + kPipeHdr + r];
-        gmem_read<Acc, NS>(planes + st.pboff[tj[k]] + (size_t)(l - 1) * plane + (size_t)nd * F + q * NS, hn[k]);
+        gmem_read<Acc, NS>(planes + st.pboff[tj(k)] + (size_t)(l - 1) * plane + (size_t)nd * F + q * NS, hn[k]);
       }
     }
     // ---- base readout partials of the rows of C_L (tiles at layer L), requested
@@ -710,12 +690,12 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
     double r0[MAXT][2];
     auto r0_load = [&](int k) {
       r0[k][0] = r0[k][1] = 0.0;
-      const int l = tl[k], t = tt[k];
-      if (l != Lr || t * 16 >= tS[k] || !(st.flags[tj[k]] & kJobReadout)) return;
+      const int l = tl(k), t = tt(k);
+      if (l != Lr || t * 16 >= tS(k) || !(st.flags[tj(k)] & kJobReadout)) return;
       const int r = t * 16 + col;
-      if (r < tS[k]) {
+      if (r < tS(k)) {
         const int nd = tabs[ttb[k] + kPipeHdr + r];
-        const double* rp = reinterpret_cast<const double*>(planes + st.pboff[tj[k]] + (size_t)(Lr - 1) * plane) +
+        const double* rp = reinterpret_cast<const double*>(planes + st.pboff[tj(k)] + (size_t)(Lr - 1) * plane) +
                            (size_t)nd * 8 + q * 2;
         r0[k][0] = rp[0];
         r0[k][1] = rp[1];
@@ -733,11 +713,11 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
     double wa = 0.0, wp = 0.0;   // this wave's readout differences of the job at layer L
 #pragma unroll
     for (int k = 0; k < MAXT; ++k) {
-      const int l = tl[k], t = tt[k], j = tj[k];
-      if (l < 1 || t * 16 >= tS[k]) continue;
+      const int l = tl(k), t = tt(k), j = tj(k);
+      if (l < 1 || t * 16 >= tS(k)) continue;
       const uint16_t* tb = tabs + ttb[k];
       const int r = t * 16 + col;
-      const bool in = r < tS[k];
+      const bool in = r < tS(k);
       const int nd = in ? (int)tb[kPipeHdr + r] : -1;
       Acc* pw = planes + st.pboff[j];
       const bool last = l == Lr;
