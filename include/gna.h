@@ -225,15 +225,16 @@ gna_status gna_set_couplings(gna_ctx *ctx, double jz, double jxy, double hb, dou
 
 /* Tile and workgroup shapes of the incremental kernels chosen by measurement:
  * times gna_local_energy on (theta, spins[B]) for the candidate shapes (jobs in
- * flight per workgroup, 8 or 16 waves, one or two samples in flight per XCD),
+ * flight per workgroup, 8 or 16 waves, one or two samples in flight per XCD, and
+ * the layer-pipelined kernels, jobs_in_flight 0, with 8 or 16 waves),
  * then one Metropolis sweep of a copy of the batch (spins is not modified) for
  * the same candidates; each kernel keeps its fastest shape, for this context and
  * for every later context of the same signature (N, n_edges, degree histogram,
  * F, L, precision) in this process.  Unlike the compute calls it synchronises
  * the context's stream and allocates a temporary copy of the batch (B*N bytes
  * plus 12*B) for the call: call it after gna_init, outside any graph capture.
- * chosen [8] (host, may be NULL): local energy jobs in flight, waves, samples per
- * XCD, microseconds per call; sweep jobs in flight, waves, tiles per wave,
+ * chosen [8] (host, may be NULL): local energy jobs in flight (0: pipelined),
+ * waves, samples per XCD, microseconds per call; sweep jobs in flight, waves, tiles per wave,
  * microseconds per one-sweep call.  In GNA_ELOC_FULL mode there is nothing to
  * tune: returns GNA_OK, chosen zeros.  OUT_OF_MEMORY if the copy cannot be had.  */
 gna_status gna_autotune(gna_ctx *ctx, const double *theta, const int8_t *spins, int32_t B,
@@ -242,20 +243,27 @@ gna_status gna_autotune(gna_ctx *ctx, const double *theta, const int8_t *spins, 
 /* Pin the shape of the incremental kernels instead of measuring it (a shape
  * reported by gna_autotune or gna_config_info earlier, or one to profile).
  * which: 1 the local-energy kernel, 2 the sweep kernel, 3 both.  jobs_in_flight
- * in [1, 8] exchanged configurations per workgroup; waves 16 selects the
- * one-tile-per-wave variant (1024-thread bound: it launches one wave per tile, at
- * most 16), 1..8 the variant with up to four tiles per wave, capped at the jobs'
- * tile count (16-node tiles of the largest L-hop ball); samples_per_xcd in
+ * in [1, 8]: exchanged configurations per workgroup advanced layer by layer
+ * together; waves 16 selects the one-tile-per-wave variant (1024-thread bound: it
+ * launches one wave per tile, at most 16), 1..8 the variant with up to four tiles
+ * per wave, capped at the jobs' tile count (16-node tiles of the largest L-hop
+ * ball).  jobs_in_flight 0: the layer-pipelined kernels, L + 2 jobs per
+ * workgroup at staggered layers, each pair of barriers advancing every job by one
+ * layer; waves 8 or 16, one of them preparing the jobs; tanh with FP32 or BF16
+ * only, and only where the jobs' tiles fit in the waves' registers and their rows
+ * in LDS.  samples_per_xcd in
  * [1, 8] (local energy only).  gna_autotune and gna_config_info report waves
  * the same way, so a reported shape can be pinned again.
  * Results do not depend on the shape beyond the order of the final FP64 sums.
  * INVALID_ARG outside those ranges or in GNA_ELOC_FULL mode; UNSUPPORTED when the
- * shape does not fit in LDS or needs more than four tiles per wave; on error the
- * previous shapes stay.  Host-side; applies to every later call.              */
+ * shape does not fit in LDS or needs more than four tiles per wave (pipelined:
+ * more tiles than the waves' registers hold, FP64, or ReLU + layer
+ * normalisation); on error the previous shapes stay.  Host-side; applies to
+ * every later call.                                                          */
 gna_status gna_set_shape(gna_ctx *ctx, int32_t which, int32_t jobs_in_flight, int32_t waves,
                          int32_t samples_per_xcd);
 
-/* Shape in use (host array, n entries at most 11): eloc_mode, jobs in flight,
+/* Shape in use (host array, n entries at most 11): eloc_mode, jobs in flight (0: pipelined),
  * waves per workgroup, tiles per wave, samples per XCD, precision, F, L, then the
  * sweep kernel's jobs in flight, waves and tiles per wave (in GNA_ELOC_FULL mode
  * the full evaluator's waves and tiles per wave).  Returns 11, or -1 for a NULL

@@ -4,24 +4,29 @@
 // the receptive field of the exchanged pair, as in gna_inc.h) has L dependent
 // layers of 1 to a few 16-row tiles each.  Advancing one exchange at a time
 // leaves most waves of a workgroup idle and pays two barriers per layer and
-// exchange.  Here a workgroup keeps D jobs in flight whose layers are staggered:
-// job slot j starts a job every D ticks (at ticks T = j mod D: its setup), and the
-// job computes layer l at tick T0 + extra + l.  A tick has two barriers; between
-// them every job in flight advances one layer, so a tick carries the tiles of
-// all L layers (one job each) and a job costs two barriers instead of 2L.
+// exchange.  Here a workgroup keeps D = L + 1 + extra jobs in flight whose layers
+// are staggered: job slot j is set up at ticks T = j mod D, its table is staged at
+// tick T + extra and it computes layer l at tick T + extra + l.  A tick has two
+// barriers, and between them every job in flight advances one layer, so a tick
+// carries the tiles of all L layers (one job each) and a job costs two barriers
+// instead of 2L.
 //
-// Per tick, every wave runs its tiles from a schedule fixed by the host
-// (tick mod D, wave, register slot k) -> (job slot, tile); a tile belongs to the
-// same wave and registers for the whole job, so a layer's output rows stay in
-// registers (hn) as the next layer's input, as in the group kernel.
-//   phase A: message and self products of the tile (H'^{l-1} W), message rows into
-//            the job's LDS rows; base H^l rows of ring l+1 requested into the
-//            lanes of hn that the next layer reads from them; ring rows of the
-//            coming tick stored into LDS (requested at the end of the last tick)
+// One wave (the setup wave) prepares the jobs; the others compute tiles from a
+// schedule fixed by the host, (tick mod D, wave, register k) -> (job slot, tile).
+// A tile belongs to the same wave and registers for the whole job, so a layer's
+// output rows stay in registers (hn) as the next layer's input.
+//   phase A  compute waves: message products G'^{l-1} = H'^{l-1} W_msg into the
+//            job's LDS rows; this tick's ring rows stored into LDS (requested in
+//            the last tick); base H^l rows of ring l+1 requested into the lanes of
+//            hn that layer l+1 reads from them.  Setup wave: the list of the next
+//            tick's ring rows; a new job's bond table (requested in the last tick)
+//            stored with its list positions turned into LDS rows.
 //   barrier
-//   phase B: gather of A_hat G over the job's LDS rows, activation, readout
-//            difference at layer L; the setup wave stores the table of a new job;
-//            every wave requests the ring rows of the next tick
+//   phase B  compute waves: gather of A_hat G' over the job's LDS rows, self
+//            product, activation, readout difference at layer L; the next tick's
+//            ring rows requested.  Setup wave: the job that finished its layer L
+//            last tick (its local-energy term, or the sampler's decision), the
+//            slot's next job, the next table requested.
 //   barrier
 // LDS rows of a job are not one buffer sized for the largest ball: rows of list
 // positions [0, |C_2|) (computed at layer 1 from the spins) and of each ring
@@ -29,8 +34,8 @@
 // layer s-1) live in pools.  Pool pi holds positions of ring pi + 2 (pi = 0: the
 // prefix [0, |C_2|)) from layer pi + 1 to layer L, i.e. during L - pi ticks; since
 // jobs start one tick apart, L - pi slots of the pool suffice, slot = tick mod
-// (L - pi).  The setup wave converts the bond's table of list positions into
-// arena rows when the job starts.
+// (L - pi).  A bond's table carries each position's pool and offset, which the
+// setup wave turns into LDS rows when the job's table is staged.
 //
 // Arithmetic is the same instruction sequence per row as the full evaluation and
 // the group kernel (the rows are bit-identical); only the order of the FP64
