@@ -37,6 +37,14 @@
 // (L - pi).  A bond's table carries each position's pool and offset, which the
 // setup wave turns into LDS rows when the job's table is staged.
 //
+// In the sampler a proposal writes its recomputed rows into the chain's planes as
+// they are produced (rows read later in the same evaluation are never among them),
+// and a rejected proposal is followed by a restore job, the same ball for the
+// chain's configuration, which rewrites the old rows bit for bit.  At the
+// benchmark's near-uniform amplitudes almost every anti-aligned proposal is
+// accepted, so restores are rare (writing only after an accept would double the
+// jobs there).
+//
 // Arithmetic is the same instruction sequence per row as the full evaluation and
 // the group kernel (the rows are bit-identical); only the order of the FP64
 // readout sums over tiles and waves differs.
@@ -405,7 +413,7 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
         while (__builtin_amdgcn_readfirstlane(st.chain[j0]) >= 0) {
           const int b = __builtin_amdgcn_readfirstlane(st.chain[j0]);
           const int pend = __builtin_amdgcn_readfirstlane(st.pend[j0]);
-          if (pend >= 0) {
+          if (pend >= 0) {   // restore job: the chain's configuration, rows rewritten
             e = pend;
             flags = 0;
             break;
@@ -658,6 +666,7 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
         for (int stp = 0; stp < KSB; ++stp) gs = P::mma(P::load_a(afr(0, stp, t4)), bop[stp], gs);
         Acc gm[4] = {gs[0], gs[1], gs[2], gs[3]};
         if (rin) lds_write<Acc, 4>(row + 4 * t4, gm);
+        if (NT == 1024) __builtin_amdgcn_sched_barrier(0);   // one output tile at a time (128 VGPRs)
       }
     }
     // ---- ring rows of this tick -> LDS (requested at the end of the last tick)
@@ -763,6 +772,7 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
           for (int stp = 0; stp < KSB; ++stp) a = P::mma(P::load_a(afr(1, stp, t4)), bop[stp], a);
 #pragma unroll
           for (int rr = 0; rr < 4; ++rr) m[4 * t4 + rr] += a[rr];   // pre-activation (the sum is commutative)
+          if (NT == 1024) __builtin_amdgcn_sched_barrier(0);   // one output tile at a time (128 VGPRs)
         }
       }
 #pragma unroll
@@ -777,6 +787,7 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
         for (int i = 0; i < NS; ++i) {
           ta1 += va[i] * (double)m[i];
           tp1 += vp[i] * (double)m[i];
+          if (NT == 1024 && i % 4 == 3) __builtin_amdgcn_sched_barrier(0);   // four head weights in flight
         }
         if (rd) {
           double pa = in ? ta1 - r0[k][0] : 0.0;
