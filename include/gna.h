@@ -168,14 +168,16 @@ gna_status gna_local_energy(gna_ctx *ctx, const double *theta, const int8_t *spi
 /* gna_local_energy for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid allocation): the
  * same kernels and results, with the call's scratch (base log psi, per-work-item
- * partial sums and counts, and the evaluation counter when n_evals is NULL) in a
- * static device array of the library, 16 MiB on each GPU it runs on, held until
- * the process ends, instead of the context's workspace.  The call performs no
- * allocation of any kind; the context's persistent buffers (weight fragments,
- * and in GNA_ELOC_INCREMENTAL mode the base planes) come from gna_init.
- * Arguments as gna_local_energy.  GNA_INVALID_ARG, with nothing enqueued, when B
- * needs more scratch than the array holds (about B * (16 + 36 * bond chunks)
- * bytes; 2048 samples of the 432-site Kagome workload need under 10 MiB).
+ * partial sums and counts, the pipelined kernel's exchange terms, and the
+ * evaluation counter when n_evals is NULL) in a static device array of the
+ * library, 64 MiB on each GPU it runs on, held until the process ends, instead
+ * of the context's workspace.  The call performs no allocation of any kind; the
+ * context's persistent buffers (weight fragments, and in GNA_ELOC_INCREMENTAL
+ * mode the base planes) come from gna_init.  Arguments as gna_local_energy.
+ * GNA_INVALID_ARG, with nothing enqueued, when B needs more scratch than the
+ * array holds (about B * (16 + 36 * bond chunks) bytes, plus B * 16 * n_edges
+ * with the layer-pipelined local-energy kernel; 2048 samples of the 432-site
+ * Kagome workload need about 29 MiB).
  * Every call on one GPU shares that GPU's array: calls that overlap in time on
  * one GPU (two streams, two host threads, two contexts) race and must be
  * serialised by the caller.  GNA_HIP_ERROR if the array's address could not be

@@ -41,7 +41,7 @@ using namespace gna;
 // and counts, the evaluation counter): a file-scope device array, one copy per GPU,
 // held until the process ends.  Host code never passes its name to a kernel: the
 // device address of each GPU's copy comes from hipGetSymbolAddress at gna_init.
-constexpr size_t kStaticScratchBytes = (size_t)16 << 20;
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
 static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
 
 namespace {
@@ -181,6 +181,39 @@ __global__ void k_zero_i64(long long* p, int n) {
 // device-resident Philox counter base of the sampler: advanced by each step
 __global__ void k_add_u64(unsigned long long* p, unsigned long long d) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p += d;
+}
+
+// Per-item sums of the pipelined local energy's exchange terms (Section 3's E_x:
+// psi(s^ij) / psi(s) = exp(da + i dp) for each anti-aligned bond of the item, with
+// (da, dp) = terms[b][e]), compensated and in bond order: the order in which the
+// kernels that sum in place take them.
+__global__ void k_eloc_terms(const int8_t* __restrict__ spins, int N, const int2* __restrict__ edges, int E,
+                             int B, int n_chunks, int chunk, const double* __restrict__ terms,
+                             double* __restrict__ partial, int* __restrict__ cnt) {
+  const long long item = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (item >= (long long)B * n_chunks) return;
+  const int b = (int)(item / n_chunks), cc = (int)(item % n_chunks);
+  const int e0 = cc * chunk, e1 = min(E, e0 + chunk);
+  const int8_t* sb = spins + (size_t)b * N;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int n = 0;
+  for (int e = e0; e < e1; ++e) {
+    const int2 ij = edges[e];
+    if (sb[ij.x] == sb[ij.y]) continue;
+    const double* o = terms + 2 * ((size_t)b * E + e);
+    const double mm = exp(o[0]);
+    double sn, cs;
+    sincos(o[1], &sn, &cs);
+    inc_neumaier(a0, a1, mm * cs);
+    inc_neumaier(a2, a3, mm * sn);
+    ++n;
+  }
+  double* p = partial + 4 * item;
+  p[0] = a0;
+  p[1] = a1;
+  p[2] = a2;
+  p[3] = a3;
+  cnt[item] = n;
 }
 
 __global__ void k_eloc_finalize(const int8_t* __restrict__ spins, int N, const int2* __restrict__ edges,
@@ -728,6 +761,7 @@ struct gna_ctx {
   std::vector<int> ball_ringmax;   // max |C_s| - |C_{s-1}| over bonds, s = 3 .. L+1 (index s)
   uint2* d_sched = nullptr;        // [2][kPipeMaxD][kMaxWaves] tile schedules: local energy, sweep
   uint16_t* d_pipe_tab = nullptr;  // per bond: header, node ids, pool tags of positions and neighbours
+  double* d_terms = nullptr;       // pipelined local energy: [max_batch][E][2] exchange readout differences
   // reverse pass (FP32 for the FP32/BF16 modes, FP64 for FP64)
   Geo vgeo{};
   VKern vk{};
@@ -938,7 +972,7 @@ void eloc_chunks(const gna_ctx* c, int B, int* n_chunks_out, int* chunk_out) {
 // least B * n_chunks entries (eloc_chunks); NULL selects the context's workspace.
 gna_status run_eloc(gna_ctx* c, const double* theta, const int8_t* spins, int B, const double* base,
                     double* eloc, long long* nev, bool planes_ready = false, double* partial = nullptr,
-                    int* cnt = nullptr) {
+                    int* cnt = nullptr, double* terms = nullptr) {
   {
     Timed tm(c, "k_zero_i64");
     hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, c->stream, nev, 1);
@@ -951,6 +985,7 @@ gna_status run_eloc(gna_ctx* c, const double* theta, const int8_t* spins, int B,
   const int items = B * n_chunks;
   if (!partial) partial = c->d_partial;
   if (!cnt) cnt = c->d_cnt;
+  if (!terms) terms = c->d_terms;
   if (c->eloc_mode == GNA_ELOC_INCREMENTAL) {
     void* planes = c->d_inc_planes;
     double* lp_out = const_cast<double*>(base);   // the base pass also yields log psi(s)
@@ -970,12 +1005,18 @@ gna_status run_eloc(gna_ctx* c, const double* theta, const int8_t* spins, int B,
       const uint16_t* gtab = c->d_pipe_tab;
       {
         Timed tm(c, "k_eloc_pipe");
-        void* a2[] = {&net, &inc, &pg, &sched, &gtab, &spins, &B, &planes, &n_chunks, &ichunk, &partial, &cnt};
+        void* a2[] = {&net, &inc, &pg, &sched, &gtab, &spins, &B, &planes, &n_chunks, &ichunk, &terms};
         hipError_t e = hipLaunchKernel(c->pk_el.eloc, dim3(grid_p), dim3(64 * pg.nw), a2, (size_t)pg.lds_bytes,
                                        c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "k_eloc_pipe");
       }
       if (gna_status st = check_launch(c, "k_eloc_pipe")) return st;
+      {
+        Timed tm(c, "k_eloc_terms");
+        hipLaunchKernelGGL(k_eloc_terms, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, c->stream, spins, c->N,
+                           c->d_edges, c->E, B, n_chunks, ichunk, terms, partial, cnt);
+      }
+      if (gna_status st = check_launch(c, "k_eloc_terms")) return st;
       Timed tm(c, "k_eloc_finalize");
       hipLaunchKernelGGL(k_eloc_finalize, dim3((B + 255) / 256), dim3(256), 0, c->stream, spins, c->N,
                          c->d_edges, c->E, c->jz, c->jxy, c->hb, c->cb, B, n_chunks, partial, cnt, eloc, nev);
@@ -1120,13 +1161,19 @@ void tune_store(const std::string& key, const IncTune& v) {
 // Tile schedule of the pipelined kernels: job slot j (setup at ticks = j mod D)
 // runs layer l at tick j + extra + l (mod D).  Tile t (list positions 16t ..
 // 16t+15) of a job holds registers from the first layer it computes or receives
-// base rows for the next layer, to layer L; it is busy (products) at layer l when
-// 16t < max(rows of the message product, |C_l|).  Every (slot, tile) gets one
-// (wave, register) pair whose live ticks it does not share, the busiest ones
-// first, each on the compute wave least loaded at its busy ticks.  sched[tick mod
-// D][wave] packs the (slot << 4 | tile) of registers 0..7 (0xff: none).  False
-// when the tiles do not fit in maxt registers per wave.
-bool pipe_schedule(const std::vector<int>& cmax, int L, int D, int extra, int nw, int sw, int maxt,
+// base rows for the next layer, to layer L.  Every (slot, tile) gets one (wave,
+// register) pair whose live ticks it does not share, on the compute wave least
+// loaded at those ticks.  A tick's two phases end at barriers, so what counts is
+// the largest load of a wave in each phase: weighted, a tile's load at layer l is
+// its message product (phase A; 16t below the product's rows) plus a share for
+// base rows requested, and in phase B the gather, self product and activation
+// (16t < |C_l|) plus the operand conversion (l < L) or the readout (l = L), or the
+// conversion alone for a tile of base rows only; the heaviest tiles are placed
+// first.  Unweighted, the load is the number of tiles with products, and tiles are
+// placed in order of their first layer.  sched[tick mod D][wave] packs the
+// (slot << 4 | tile) of registers 0..7 (0xff: none).  False when the tiles do not
+// fit in maxt registers per wave.
+bool pipe_schedule(const std::vector<int>& cmax, int L, int D, int extra, int nw, int sw, int maxt, bool weighted,
                    std::vector<uint2>* sched, int* max_load) {
   auto rows_at = [&](int l) { return std::max(l == 1 ? cmax[2] : cmax[l], cmax[l]); };   // products at layer l
   int top = 0;
@@ -1137,13 +1184,32 @@ bool pipe_schedule(const std::vector<int>& cmax, int L, int D, int extra, int nw
   for (int t = 0; t < tmax; ++t)
     for (int l = L; l >= 1; --l)
       if (16 * t < rows_at(l) || (l < L && 16 * t < cmax[l + 1])) lf[t] = l;
-  struct Item { int j, t; };
+  // weighted loads in tenths: phase A, phase B of tile t at layer l
+  auto cost_a = [&](int t, int l) {
+    int a = 16 * t < rows_at(l) ? 10 : 0;
+    if (l < L && 16 * t < cmax[l + 1] && 16 * t + 16 > cmax[l]) a += 2;
+    return weighted ? a : (16 * t < rows_at(l) ? 1 : 0);
+  };
+  auto cost_b = [&](int t, int l) {
+    int b = 0;
+    if (16 * t < cmax[l]) b = 10 + (l < L ? 3 : 6);
+    else if (l < L && 16 * t < cmax[l + 1]) b = 3;
+    return weighted ? b : 0;
+  };
+  struct Item { int j, t, w; };
   std::vector<Item> items;
   for (int t = 0; t < tmax; ++t)
     for (int j = 0; j < D; ++j)
-      if (lf[t] <= L) items.push_back({j, t});
-  std::stable_sort(items.begin(), items.end(), [&](const Item& a, const Item& b) { return lf[a.t] < lf[b.t]; });
-  std::vector<int> occ((size_t)D * nw * maxt, -1), load((size_t)D * nw, 0);
+      if (lf[t] <= L) {
+        int wsum = 0;
+        for (int l = lf[t]; l <= L; ++l) wsum += cost_b(t, l);
+        items.push_back({j, t, wsum});
+      }
+  if (weighted)
+    std::stable_sort(items.begin(), items.end(), [&](const Item& a, const Item& b) { return a.w > b.w; });
+  else
+    std::stable_sort(items.begin(), items.end(), [&](const Item& a, const Item& b) { return lf[a.t] < lf[b.t]; });
+  std::vector<int> occ((size_t)D * nw * maxt, -1), la((size_t)D * nw, 0), lb((size_t)D * nw, 0);
   for (const Item& it : items) {
     int best_w = -1, best_k = -1;
     long long best_cost = 0;
@@ -1151,17 +1217,21 @@ bool pipe_schedule(const std::vector<int>& cmax, int L, int D, int extra, int nw
       if (w == sw) continue;
       for (int k = 0; k < maxt; ++k) {
         bool free_ = true;
-        int peak = 0, sum = 0;
+        int pa = 0, pb = 0, sum = 0;
         for (int l = lf[it.t]; l <= L && free_; ++l) {
           const int tau = (it.j + extra + l) % D;
-          if (occ[((size_t)tau * nw + w) * maxt + k] >= 0) free_ = false;
-          if (16 * it.t < rows_at(l)) {
-            peak = std::max(peak, load[(size_t)tau * nw + w] + 1);
-            sum += load[(size_t)tau * nw + w];
+          const size_t o = (size_t)tau * nw + w;
+          if (occ[o * maxt + k] >= 0) free_ = false;
+          const int ca = cost_a(it.t, l), cb = cost_b(it.t, l);
+          if (ca + cb > 0) {
+            pa = std::max(pa, la[o] + ca);
+            pb = std::max(pb, lb[o] + cb);
+            sum += la[o] + lb[o];
           }
         }
         if (!free_) continue;
-        const long long cost = (long long)peak * 1000000 + sum * 100 + k;
+        const long long cost = weighted ? ((long long)pb * 1000 + pa) * 100000 + (long long)sum * 10 + k
+                                        : (long long)pa * 1000000 + sum * 100 + k;
         if (best_w < 0 || cost < best_cost) {
           best_w = w;
           best_k = k;
@@ -1173,8 +1243,10 @@ bool pipe_schedule(const std::vector<int>& cmax, int L, int D, int extra, int nw
     if (best_w < 0) return false;
     for (int l = lf[it.t]; l <= L; ++l) {
       const int tau = (it.j + extra + l) % D;
-      occ[((size_t)tau * nw + best_w) * maxt + best_k] = it.j << 4 | it.t;
-      if (16 * it.t < rows_at(l)) ++load[(size_t)tau * nw + best_w];
+      const size_t o = (size_t)tau * nw + best_w;
+      occ[o * maxt + best_k] = it.j << 4 | it.t;
+      la[o] += cost_a(it.t, l);
+      lb[o] += cost_b(it.t, l);
     }
   }
   sched->assign((size_t)kPipeMaxD * kMaxWaves, uint2{0xffffffffu, 0xffffffffu});
@@ -1182,12 +1254,17 @@ bool pipe_schedule(const std::vector<int>& cmax, int L, int D, int extra, int nw
   for (int tau = 0; tau < D; ++tau)
     for (int w = 0; w < nw; ++w) {
       unsigned long long v = ~0ULL;
+      int busy = 0;
       for (int k = 0; k < maxt; ++k) {
         const int o = occ[((size_t)tau * nw + w) * maxt + k];
-        if (o >= 0) v = (v & ~(0xffULL << (8 * k))) | ((unsigned long long)o << (8 * k));
+        if (o >= 0) {
+          v = (v & ~(0xffULL << (8 * k))) | ((unsigned long long)o << (8 * k));
+          const int l = ((tau - (o >> 4) - extra) % D + D) % D;
+          if (l >= 1 && 16 * (o & 15) < rows_at(l)) ++busy;
+        }
       }
       (*sched)[(size_t)tau * kMaxWaves + w] = uint2{(unsigned)v, (unsigned)(v >> 32)};
-      ml = std::max(ml, load[(size_t)tau * nw + w]);
+      ml = std::max(ml, busy);
     }
   if (max_load) *max_load = ml;
   return true;
@@ -1251,7 +1328,8 @@ gna_status pipe_configure(gna_ctx* c, IncShape shp, int which) {
     return fail(c, GNA_UNSUPPORTED, "pipelined kernels: the shape does not fit in LDS");
   std::vector<uint2> sched;
   int ml = 0;
-  if (!pipe_schedule(c->ball_cmax, L, g.D, g.extra, g.nw, g.sw, pk.maxt, &sched, &ml))
+  if (!pipe_schedule(c->ball_cmax, L, g.D, g.extra, g.nw, g.sw, pk.maxt, true, &sched, &ml) &&
+      !pipe_schedule(c->ball_cmax, L, g.D, g.extra, g.nw, g.sw, pk.maxt, false, &sched, &ml))
     return fail(c, GNA_UNSUPPORTED, "pipelined kernels: the tiles do not fit in the wave registers");
   const void* fn = which == 1 ? pk.eloc : pk.sweep;
   if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, g.lds_bytes) != hipSuccess) {
@@ -1790,7 +1868,8 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
       c->pipe_ok = ok;
       c->pipe_tabw = tabw;
       if ((st = dev_alloc(c, &c->d_sched, (size_t)2 * kPipeMaxD * kMaxWaves * sizeof(uint2))) ||
-          (ok && (st = dev_alloc(c, &c->d_pipe_tab, pt.size() * 2))))
+          (ok && (st = dev_alloc(c, &c->d_pipe_tab, pt.size() * 2))) ||
+          (ok && (st = dev_alloc(c, &c->d_terms, MB * (size_t)std::max(1, E) * 2 * sizeof(double)))))
         return bail(st, c->err);
       if (ok) {
         he = hipMemcpy(c->d_pipe_tab, pt.data(), pt.size() * 2, hipMemcpyHostToDevice);
@@ -1910,15 +1989,18 @@ gna_status gna_local_energy_noalloc(gna_ctx* c, const double* theta, const int8_
     return fail(c, GNA_INVALID_ARG, "NULL pointer argument");
   if (!c->scratch_dev) return fail(c, GNA_HIP_ERROR, c->scratch_err);
   // scratch layout (256-byte aligned parts): evaluation counter, base log psi [B][2],
-  // per-item partial sums [B * n_chunks][4], per-item counts [B * n_chunks]
+  // per-item partial sums [B * n_chunks][4], per-item counts [B * n_chunks], and with
+  // the pipelined local-energy kernel its exchange terms [B][E][2]
   int n_chunks = 1, chunk = 1;
   eloc_chunks(c, std::max(B, 1), &n_chunks, &chunk);
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
   const size_t items = (size_t)B * n_chunks;
+  const bool piped = c->eloc_mode == GNA_ELOC_INCREMENTAL && c->pipe_el;
   const size_t off_base = 256;
   const size_t off_part = al(off_base + (size_t)B * 2 * sizeof(double));
   const size_t off_cnt = al(off_part + items * 4 * sizeof(double));
-  const size_t need = off_cnt + items * sizeof(int);
+  const size_t off_terms = al(off_cnt + items * sizeof(int));
+  const size_t need = piped ? off_terms + (size_t)B * std::max(1, c->E) * 2 * sizeof(double) : off_cnt + items * sizeof(int);
   if (need > kStaticScratchBytes)
     return fail(c, GNA_INVALID_ARG, "gna_local_energy_noalloc: B = " + std::to_string(B) + " needs " +
                                         std::to_string(need) + " bytes of static scratch, above the maximum of " +
@@ -1928,12 +2010,14 @@ gna_status gna_local_energy_noalloc(gna_ctx* c, const double* theta, const int8_
   double* base = reinterpret_cast<double*>(sc + off_base);
   double* partial = reinterpret_cast<double*>(sc + off_part);
   int* cnt = reinterpret_cast<int*>(sc + off_cnt);
+  double* terms = piped ? reinterpret_cast<double*>(sc + off_terms) : nullptr;
   if (gna_status st = prepare(c, theta)) return st;
   if (c->eloc_mode == GNA_ELOC_FULL)
     if (gna_status st = run_logpsi(c, theta, spins, B, base)) return st;
   // every item's partial sums and count are written by the kernel that owns the
-  // item; the counter is cleared by a fill kernel inside run_eloc
-  return run_eloc(c, theta, spins, B, base, eloc, nev, false, partial, cnt);
+  // item (every exchange term read is written first); the counter is cleared by a
+  // fill kernel inside run_eloc
+  return run_eloc(c, theta, spins, B, base, eloc, nev, false, partial, cnt, terms);
 }
 
 static gna_status run_sweep(gna_ctx* c, const double* theta, int8_t* spins, double* logpsi, int32_t B,

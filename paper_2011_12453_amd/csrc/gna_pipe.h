@@ -18,16 +18,22 @@
 //   phase A  compute waves: message products G'^{l-1} = H'^{l-1} W_msg into the
 //            job's LDS rows; this tick's ring rows stored into LDS (requested in
 //            the last tick); base H^l rows of ring l+1 requested into the lanes of
-//            hn that layer l+1 reads from them.  Setup wave: the list of the next
-//            tick's ring rows; a new job's bond table (requested in the last tick)
-//            stored with its list positions turned into LDS rows.
+//            hn that layer l+1 reads from them.  Setup wave: a new job's bond table
+//            (requested in the last tick) stored; the list of the next tick's ring
+//            rows.
 //   barrier
 //   phase B  compute waves: gather of A_hat G' over the job's LDS rows, self
-//            product, activation, readout difference at layer L; the next tick's
-//            ring rows requested.  Setup wave: the job that finished its layer L
-//            last tick (its local-energy term, or the sampler's decision), the
-//            slot's next job, the next table requested.
+//            product, activation, readout difference at layer L; the new table's
+//            list positions turned into LDS rows; the next tick's ring rows
+//            requested.  Setup wave: the readout difference of the job that
+//            finished its layer L last tick (written out for the local energy, whose
+//            terms k_eloc_terms sums in bond order; or the sampler's decision on
+//            it), the slot's next job, the next table requested.
 //   barrier
+// The setup wave's work is on the critical path of a tick when the compute waves
+// have few tiles each: it keeps the job state in registers (LDS round trips are
+// long under the compute waves' traffic) and the tag conversion, which needs none
+// of that state, is spread over the compute waves.
 // LDS rows of a job are not one buffer sized for the largest ball: rows of list
 // positions [0, |C_2|) (computed at layer 1 from the spins) and of each ring
 // [|C_{s-1}|, |C_s|), s >= 3 (copied from the base planes for the gather of
@@ -93,7 +99,8 @@ struct PipeState {
   int chain[kPipeMaxD], nacc[kPipeMaxD], pend[kPipeMaxD];   // sampler: the slot's chain
   long long tstep[kPipeMaxD];
   double u[kPipeMaxD];
-  int rowbase[kPipeMaxL];                     // first arena row of each pool slot of the job converted
+  int rowbase[kPipeMaxL];                     // first arena row of each pool slot of the job staged
+  int conv;                                   // LDS table staged this tick (uint16 offset), or -1
   int nrows[2];                               // ring rows copied in a tick (by tick parity)
   int done;
 };
@@ -121,11 +128,26 @@ __device__ __forceinline__ void relu_ln_inplace(Acc (&x)[NS]) {
   for (int i = 0; i < NS; ++i) x[i] = (x[i] - mu) * r;
 }
 
+// A tile's layer input is held in registers as its MFMA B operands: make_b of the
+// row's NS values, K step by K step, in the first KSB * sizeof(BF) bytes of the NS
+// words (the rest unused). Built once where the input is produced instead of before
+// each of the two products that read it.
+template <class P, int NS>
+__device__ __forceinline__ void pipe_to_ops(const typename P::Acc (&x)[NS], typename P::Acc (&h)[NS]) {
+  using BF = decltype(P::make_b((const typename P::Acc*)nullptr));
+  constexpr int KSB = NS / P::VEC;
+  static_assert(sizeof(typename P::Acc) == 4 && sizeof(BF) * KSB <= 4 * NS, "operands fit the input's words");
+  BF b[KSB];
+#pragma unroll
+  for (int stp = 0; stp < KSB; ++stp) b[stp] = P::make_b(&x[stp * P::VEC]);
+  __builtin_memcpy(h, b, sizeof(BF) * KSB);
+}
+
 template <class P, int F, int MAXT, int NT, int NCOPY, bool SWEEP>
 __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, const PipeGeo& pg,
                                           const uint2* __restrict__ sched, const uint16_t* __restrict__ gtab,
                                           int8_t* spins, int B, typename P::Acc* planes, int n_chunks, int chunk,
-                                          double* __restrict__ partial, int* __restrict__ cnt_out, int n_sweeps,
+                                          double* __restrict__ terms, int n_sweeps,
                                           unsigned long long seed, unsigned long long counter_base,
                                           const unsigned long long* __restrict__ counter_dev,
                                           int* __restrict__ n_accept) {
@@ -135,6 +157,7 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
   using V4 = unsigned int __attribute__((ext_vector_type(4)));
   constexpr int NS = F / 4, MT = F / 16, KSB = F / P::KS, VEC = P::VEC;
   constexpr int VPR = F * (int)sizeof(Acc) / 16;   // 16-byte vectors per row
+  static_assert(sizeof(Acc) == 4, "FP32 activations (FP64 is not pipelined)");
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ PipeState st;
   const int lane = threadIdx.x & 63;
@@ -156,14 +179,25 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
   double* shead = reinterpret_cast<double*>(smem + pg.off_head);
   Acc* sev = reinterpret_cast<Acc*>(smem + pg.off_ev);
   unsigned* sedge = reinterpret_cast<unsigned*>(smem + pg.off_edges);   // i | j << 16
-  unsigned* smask = reinterpret_cast<unsigned*>(smem + pg.off_mask);
 
   // ---- weights, node tables and bond endpoints -> LDS
   {
     const WT* src = reinterpret_cast<const WT*>(net.wfrag);
     for (int k = threadIdx.x; k < 2 * F * F; k += NT) wl[k] = src[k];
     for (int k = threadIdx.x; k < F; k += NT) sbias[k] = reinterpret_cast<const Acc*>(net.bias)[P::lc(k / NS, k % NS)];
-    for (int k = threadIdx.x; k < 2 * F; k += NT) semb[k] = reinterpret_cast<const Acc*>(net.emb)[k];
+    // the embedding of spin value s as lane group q's B operands, at semb + (2q + s) NS
+    for (int k = threadIdx.x; k < 8; k += NT) {
+      const int s = k & 1, qq = k >> 1;
+      Acc x[NS], h[NS];
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        x[i] = reinterpret_cast<const Acc*>(net.emb)[s * F + P::lc(qq, i)];
+        h[i] = (Acc)0;
+      }
+      pipe_to_ops<P, NS>(x, h);
+#pragma unroll
+      for (int i = 0; i < NS; ++i) semb[k * NS + i] = h[i];
+    }
     for (int k = threadIdx.x; k < F; k += NT) {
       const int f = P::lc(k / NS, k % NS);
       shead[k] = net.head_a[f];
@@ -256,92 +290,168 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
     }
   };
 
+  // work spread over the compute waves (all waves but the setup wave, the last):
+  // entry my of every stride, interleaved so that each wave takes a like share
+  const int ncw = nw - 1, stride = 64 * ncw, my = lane * ncw + wv;
+  // phase B: the pool tags (pool << 12 | offset) of the table staged this tick turned
+  // into LDS rows (the table is first read at the next tick)
+  auto tab_convert = [&]() {
+    const int tbo = __builtin_amdgcn_readfirstlane(st.conv);
+    if (tbo < 0) return;
+    uint16_t* tb = tabs + tbo;
+    const int nv = tabw / 8;
+    for (int v = (kPipeHdr + r8) / 8 + my; v < nv; v += stride) {
+      const V4 x = *reinterpret_cast<const V4*>(tb + 8 * v);
+      unsigned o[4];
+#pragma unroll
+      for (int w4 = 0; w4 < 4; ++w4) {
+        const unsigned lo = x[w4] & 0xffffu, hi = x[w4] >> 16;
+        o[w4] = (unsigned)(st.rowbase[lo >> 12] + (int)(lo & 0xfffu)) |
+                ((unsigned)(st.rowbase[hi >> 12] + (int)(hi & 0xfffu)) << 16);
+      }
+      *reinterpret_cast<V4*>(tb + 8 * v) = V4{o[0], o[1], o[2], o[3]};
+    }
+  };
+
   if (wv == pg.sw) {
     // ======================= the setup wave =======================
+    // This wave's work is on the critical path of a tick, and it shares its SIMD
+    // with compute waves: it issues at a higher priority than theirs.  The state of
+    // job slot j sits in lane j of the registers below; the copies in LDS are for
+    // the compute waves.  This wave writes LDS state and never waits for its own.
+    __builtin_amdgcn_s_setprio(3);
+    auto rl32 = [](int v, int j) { return __builtin_amdgcn_readlane(v, j); };
+    auto rl64 = [](unsigned long long v, int j) {
+      return (unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, j) |
+             ((unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), j) << 32);
+    };
+    int r_valid = 0, r_t1 = 0, r_e = 0, r_tbo = 0, r_flags = 0, r_spb = -1, r_si = 0, r_sk = 0;
+    unsigned r_ij = 0;
+    unsigned long long r_pboff = 0;
+    // sampler: the slot's chain, its accepted count, pending restore, next draw and
+    // the uniform draw of the job in flight
+    int r_chain = -1, r_nacc = 0, r_pend = -1;
+    unsigned long long r_tstep = 0, r_u = 0;   // r_u: the double's bits
+    if constexpr (SWEEP) {
+      const int b = blockIdx.x + lane * gridDim.x;
+      r_chain = (lane < D && b < B) ? b : -1;
+    }
+    // pool pi (lane pi): first LDS row and rows of a slot, slots, the slot of this tick
+    int p_base = 0, p_rows = 0, p_cnt = 1, p_slot = 0;
+#pragma unroll
+    for (int i = 0; i < kPipeMaxL; ++i)
+      if (lane == i && i < Lr) {
+        p_base = pg.pool_base[i];
+        p_rows = pg.pool_rows[i];
+        p_cnt = pg.pool_cnt[i];
+      }
     V4 tv[kPipeTabVec];   // a job's table (global -> registers), stored at its table tick
 #pragma unroll
     for (int u = 0; u < kPipeTabVec; ++u) tv[u] = V4{0u, 0u, 0u, 0u};
     int tjob = -1;        // slot of the job whose table tv holds
-    // local energy: the stream of work items of this workgroup and the sums of the
-    // current one (wave-uniform, kept in registers)
+    // local energy: the stream of work items of this workgroup; the current item's
+    // anti-aligned bonds (bit per bond, word w in lane w) and, for items of at most
+    // 64 bonds, each bond's endpoints (bond k in lane k)
     long long jj = (long long)slotx - per_x;
-    int it = -1, sb = -1, e0 = 0, clen = 0, cursor = 0, issued = 0;
+    int sb = -1, e0 = 0, clen = 0, cursor = 0;
+    unsigned r_mask = 0u, r_bij = 0u;
     bool sdone = SWEEP;
-    int acc_item = -1, acc_n = 0;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     int inflight = 0;
     int8_t* ss = sp + D * pg.spw;   // the stream's sample
-    auto flush = [&]() {
-      if (acc_item >= 0 && lane == 0) {
-        double* o = partial + 4 * (size_t)acc_item;
-        o[0] = a0; o[1] = a1; o[2] = a2; o[3] = a3;
-        cnt_out[acc_item] = acc_n;
-      }
-    };
     for (int T = 0;; ++T) {
       const int tau = T % D;
-      // ---- phase A: the list of the next tick's ring rows; the table of the job
-      // whose table tick this is, its pool tags (pool << 12 | offset) turned into
-      // arena rows; this tick's ring rows
-      {   // ring rows of the next tick: layer lp = 2..L in turn (lane lp - 2 looks up its job)
-        const int tn = T + 1, pb = tn & 1, lp = lane + 2;
-        int n = 0, a = 0, tbo = 0;
-        long long src = 0;
-        if (lp <= Lr) {
-          const int t0 = tn - extra - lp;   // setup tick of the job at layer lp
-          const int j = t0 >= 0 ? t0 % D : 0;
-          const int vj = st.valid[j], tb_j = st.tbo[j], h0 = st.hdr[j][lp], h1 = st.hdr[j][lp + 1];
-          const long long pb_j = st.pboff[j];
-          if (t0 >= 0 && vj) {
-            tbo = tb_j;
-            a = h0;
-            n = h1 - h0;
-            src = pb_j + (long long)(Lr + lp - 1) * (long long)plane;
-          }
-        }
-        uint2* rl = reinterpret_cast<uint2*>(smem + pg.off_rows) + pb * pg.rows_max;
-        int start = 0;
-        for (int x = 0; x + 2 <= Lr; ++x) {   // entries in layer order, rows over the lanes
-          const int nx = __shfl(n, x, 64), ax = __shfl(a, x, 64), tx = __shfl(tbo, x, 64);
-          const long long sx = __shfl(src, x, 64);
-          for (int rw = lane; rw < nx; rw += 64) {
-            const int p = ax + rw;
-            const int node = tabs[tx + kPipeHdr + p], arow = tabs[tx + kPipeHdr + r8 + p];
-            rl[start + rw] = make_uint2((unsigned)((sx + (long long)node * F) / (16 / (int)sizeof(Acc))),
-                                        (unsigned)(pg.off_arena + arow * row_bytes));
-          }
-          start += nx;
-        }
-        if (lane == 0) st.nrows[pb] = start;
-      }
+      // ---- phase A: the table of the job whose table tick this is, stored as read (the
+      // compute waves turn its pool tags into LDS rows in phase B), with the first LDS
+      // row of each pool slot of the job
       if (tjob >= 0) {
-        if (lane < Lr) st.rowbase[lane] = pg.pool_base[lane] + (T % pg.pool_cnt[lane]) * pg.pool_rows[lane];
+        if (lane < Lr) st.rowbase[lane] = p_base + p_slot * p_rows;
         const int tbo = (T % ntab) * tabw;
         uint16_t* tb = tabs + tbo;
         const int nv = tabw / 8;
 #pragma unroll
         for (int u = 0; u < kPipeTabVec; ++u) {
           const int v = lane + 64 * u;
-          if (v >= nv) continue;
-          const V4 x = tv[u];
-          const int g = 8 * v;
-          if (g < kPipeHdr + r8) {
-            *reinterpret_cast<V4*>(tb + g) = x;   // header, node ids
-          } else {
-            unsigned o[4];
+          if (v < nv) *reinterpret_cast<V4*>(tb + 8 * v) = tv[u];
+        }
+        // the header (entries 0..15: table vectors 0 and 1, in lanes 0 and 1)
+        if (lane < 2) {
+          unsigned* hw = reinterpret_cast<unsigned*>(&st.hdr[tjob][8 * lane]);
 #pragma unroll
-            for (int w4 = 0; w4 < 4; ++w4) {
-              const unsigned lo = x[w4] & 0xffffu, hi = x[w4] >> 16;
-              o[w4] = (unsigned)(st.rowbase[lo >> 12] + (int)(lo & 0xfffu)) |
-                      ((unsigned)(st.rowbase[hi >> 12] + (int)(hi & 0xfffu)) << 16);
-            }
-            *reinterpret_cast<V4*>(tb + g) = V4{o[0], o[1], o[2], o[3]};
+          for (int w = 0; w < 4; ++w) hw[w] = tv[0][w];
+        }
+        if (lane == tjob) r_tbo = tbo;
+        if (lane == 0) {
+          st.tbo[tjob] = tbo;
+          st.conv = tbo;
+        }
+      } else if (lane == 0) {
+        st.conv = -1;
+      }
+      // ---- the list of the next tick's ring rows, layer lp = 2..L in turn and the
+      // ring's rows in list order (source 16-byte vector in the planes, destination
+      // byte offset in LDS): lane x looks after layer x + 2, one round of header
+      // reads and one of table reads for all rows
+      {
+        const int tn = T + 1, pb = tn & 1;
+        uint2* rl = reinterpret_cast<uint2*>(smem + pg.off_rows) + pb * pg.rows_max;
+        int xj = -1, xt = 0;
+        unsigned long long xsrc = 0;
+        for (int x = 0; x + 2 <= Lr; ++x) {
+          const int t0 = tn - extra - (x + 2);   // setup tick of the job at layer x + 2
+          if (t0 < 0) break;
+          const int j = t0 % D;
+          if (!rl32(r_valid, j)) continue;
+          const int tbo = rl32(r_tbo, j);
+          const unsigned long long src = rl64(r_pboff, j) + (unsigned long long)(Lr + x + 1) * plane;
+          if (lane == x) {
+            xj = j;
+            xt = tbo;
+            xsrc = src;
           }
         }
-        if (lane < kPipeHdr) st.hdr[tjob][lane] = tb[lane];   // the header, for one-step lookups
-        if (lane == 0) st.tbo[tjob] = tbo;
+        int xh = 0, xn = 0, xs = 0;
+        if (xj >= 0) {
+          xh = st.hdr[xj][lane + 2];
+          xn = st.hdr[xj][lane + 3] - xh;
+        }
+        int nrow = 0;
+        for (int x = 0; x + 2 <= Lr; ++x) {
+          const int n = rl32(xn, x);
+          if (lane == x) xs = nrow;
+          nrow += n;
+        }
+        for (int base = 0; base < nrow; base += 128) {
+          int node[2], arow[2];
+          unsigned long long src[2];
+#pragma unroll
+          for (int k = 0; k < 2; ++k) {
+            const int idx = base + lane + 64 * k;
+            int p = 0, tbo = 0;
+            unsigned long long s0 = 0;
+            for (int x = 0; x + 2 <= Lr; ++x) {
+              const int s = rl32(xs, x), n = rl32(xn, x);
+              if (idx >= s && idx < s + n) {
+                p = rl32(xh, x) + idx - s;
+                tbo = rl32(xt, x);
+                s0 = rl64(xsrc, x);
+              }
+            }
+            node[k] = tabs[tbo + kPipeHdr + p];
+            arow[k] = tabs[tbo + kPipeHdr + r8 + p];
+            src[k] = s0;
+          }
+#pragma unroll
+          for (int k = 0; k < 2; ++k) {
+            const int idx = base + lane + 64 * k;
+            if (idx < nrow)
+              rl[idx] = make_uint2((unsigned)((src[k] + (unsigned long long)node[k] * F) / (16 / sizeof(Acc))),
+                                   (unsigned)(pg.off_arena + arow[k] * row_bytes));
+          }
+        }
+        if (lane == 0) st.nrows[pb] = nrow;
       }
       copy_store(T);
+      p_slot = p_slot + 1 == p_cnt ? 0 : p_slot + 1;   // the pool slots of the next tick
       __syncthreads();
       // ---- phase B: this wave's readout slots, the job that left slot T mod D and
       // the slot's next job, the table of the job whose table tick is the next tick,
@@ -352,92 +462,81 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
       }
       const int j0 = tau;
       bool done = false;
-      if (__builtin_amdgcn_readfirstlane(st.valid[j0])) {   // its layer L ran last tick
+      if (rl32(r_valid, j0)) {   // its layer L ran last tick
         // readout difference: the waves' partials, summed in a fixed order
         const double* rd = red + ((T - 1) & 1) * 2 * kMaxWaves;
-        double da = lane < nw ? rd[lane & 15] : 0.0, dp = lane < nw ? rd[kMaxWaves + (lane & 15)] : 0.0;
-#pragma unroll
-        for (int o = 1; o < 16; o <<= 1) {
-          da += __shfl_xor(da, o, 64);
-          dp += __shfl_xor(dp, o, 64);
-        }
-        {
-          const unsigned long long ba = __double_as_longlong(da), bp = __double_as_longlong(dp);
-          da = __longlong_as_double((long long)(((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(ba >> 32)) << 32) |
-                                                (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)ba)));
-          dp = __longlong_as_double((long long)(((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(bp >> 32)) << 32) |
-                                                (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)bp)));
-        }
+        const double da = wave_sum_dpp(lane < nw ? rd[lane] : 0.0);
+        const double dp = wave_sum_dpp(lane < nw ? rd[kMaxWaves + lane] : 0.0);
         if constexpr (SWEEP) {
-          const int fl = __builtin_amdgcn_readfirstlane(st.flags[j0]);
+          const int fl = rl32(r_flags, j0);
           if (fl & kJobReadout) {
-            const double u = st.u[j0];
+            const double u = __longlong_as_double((long long)rl64(r_u, j0));
             if (u < exp(2.0 * da)) {   // accept: the planes already hold the new rows
+              // the exchange (the pair's spins were read when the bond was drawn)
+              const unsigned ij = (unsigned)rl32((int)r_ij, j0);
+              const int si = rl32(r_si, j0), sk = rl32(r_sk, j0);
               if (lane == 0) {
                 int8_t* sj = sp + j0 * pg.spw;
-                const int2 ij = st.ij[j0];
-                const int8_t tmp = sj[ij.x];
-                sj[ij.x] = sj[ij.y];
-                sj[ij.y] = tmp;
-                ++st.nacc[j0];
+                sj[ij & 0xffffu] = (int8_t)sk;
+                sj[ij >> 16] = (int8_t)si;
               }
-            } else if (lane == 0) {
-              st.pend[j0] = st.e[j0];   // reject: the restore job of this bond comes next
+              if (lane == j0) ++r_nacc;
+            } else if (lane == j0) {
+              r_pend = r_e;   // reject: the restore job of this bond comes next
             }
-            if (lane == 0) ++st.tstep[j0];
-          } else if (lane == 0) {
-            st.pend[j0] = -1;   // restored
+            if (lane == j0) ++r_tstep;
+          } else if (lane == j0) {
+            r_pend = -1;   // restored
           }
-        } else {
-          const int item = __builtin_amdgcn_readfirstlane(st.item[j0]);
-          if (item != acc_item) {
-            flush();
-            acc_item = item;
-            a0 = a1 = a2 = a3 = 0.0;
-            acc_n = 0;
-          }
-          const double mm = exp(da);
-          double sn, cs;
-          sincos(dp, &sn, &cs);
-          inc_neumaier(a0, a1, mm * cs);
-          inc_neumaier(a2, a3, mm * sn);
-          ++acc_n;
+        } else if (lane == 0) {   // the exchange's term, summed in bond order by k_eloc_terms
+          double* o = terms + 2 * ((size_t)rl32(r_spb, j0) * net.ne + rl32(r_e, j0));
+          o[0] = da;
+          o[1] = dp;
         }
         if (lane == 0) st.valid[j0] = 0;
+        if (lane == j0) r_valid = 0;
         --inflight;
       }
       // ---- the next job of slot j0
       int e = -1;
       if constexpr (SWEEP) {
         int flags = 0;
-        while (__builtin_amdgcn_readfirstlane(st.chain[j0]) >= 0) {
-          const int b = __builtin_amdgcn_readfirstlane(st.chain[j0]);
-          const int pend = __builtin_amdgcn_readfirstlane(st.pend[j0]);
+        unsigned ij = 0u;
+        while (rl32(r_chain, j0) >= 0) {
+          const int b = rl32(r_chain, j0);
+          const int pend = rl32(r_pend, j0);
           if (pend >= 0) {   // restore job: the chain's configuration, rows rewritten
             e = pend;
+            ij = (unsigned)rl32((int)r_ij, j0);
             flags = 0;
             break;
           }
           // draws t, t+1, ... of the chain, 64 at a time; identity steps are skipped
-          long long t = st.tstep[j0];
+          unsigned long long t = rl64(r_tstep, j0);
           const int8_t* sj = sp + j0 * pg.spw;
-          while (t < total) {
-            const long long tu = t + lane;
-            const unsigned long long step = counter_base + (unsigned long long)tu;
+          while (t < (unsigned long long)total) {
+            const unsigned long long tu = t + lane;
+            const unsigned long long step = counter_base + tu;
             uint32_t c[4] = {(uint32_t)step, (uint32_t)(step >> 32), (uint32_t)b, 0u};
             philox4x32_10(c, k0, k1);
             const int eu = (int)(((unsigned long long)c[0] * (unsigned long long)net.ne) >> 32);
-            const unsigned ij = sedge[eu];
-            const bool anti = tu < total && sj[ij & 0xffffu] != sj[ij >> 16];
+            const unsigned iju = sedge[eu];
+            const int si = sj[iju & 0xffffu], sk = sj[iju >> 16];
+            const bool anti = tu < (unsigned long long)total && si != sk;
             const unsigned long long m = __ballot(anti);
             if (m) {
               const int us = __builtin_ctzll(m);
-              e = __builtin_amdgcn_readlane(eu, us);
-              const uint32_t c1 = (uint32_t)__builtin_amdgcn_readlane((int)c[1], us);
+              e = rl32(eu, us);
+              ij = (unsigned)rl32((int)iju, us);
+              const int siu = rl32(si, us), sku = rl32(sk, us);
+              const uint32_t c1 = (uint32_t)rl32((int)c[1], us);
               t += us;
-              if (lane == 0) {
-                st.tstep[j0] = t;
-                st.u[j0] = ((double)c1 + 0.5) * 2.3283064365386963e-10;   // 2^-32
+              const double u = ((double)c1 + 0.5) * 2.3283064365386963e-10;   // 2^-32
+              if (lane == j0) {
+                r_tstep = t;
+                r_u = (unsigned long long)__double_as_longlong(u);
+                r_si = siu;
+                r_sk = sku;
               }
               break;
             }
@@ -450,57 +549,52 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
           // the chain is done: spins and acceptance count out, the slot's next chain in
           for (int k = lane; k < net.n; k += 64) spins[(size_t)b * net.n + k] = sj[k];
           const int nb = b + D * gridDim.x;
-          if (lane == 0) {
-            if (n_accept) n_accept[b] = st.nacc[j0];
-            st.chain[j0] = nb < B ? nb : -1;
-            st.nacc[j0] = 0;
-            st.pend[j0] = -1;
-            st.tstep[j0] = 0;
+          const int nacc = rl32(r_nacc, j0);
+          if (lane == 0 && n_accept) n_accept[b] = nacc;
+          if (lane == j0) {
+            r_chain = nb < B ? nb : -1;
+            r_nacc = 0;
+            r_pend = -1;
+            r_tstep = 0;
           }
           if (nb < B)
             for (int k = lane; k < net.n; k += 64) sp[j0 * pg.spw + k] = spins[(size_t)nb * net.n + k];
           __builtin_amdgcn_s_waitcnt(0);
         }
         if (e >= 0) {
+          const unsigned long long pbo = (unsigned long long)rl32(r_chain, j0) * (unsigned long long)per;
           if (lane == 0) {
             st.valid[j0] = 1;
             st.flags[j0] = flags;
-            st.e[j0] = e;
-            const unsigned ij = sedge[e];
             st.ij[j0] = make_int2((int)(ij & 0xffffu), (int)(ij >> 16));
-            st.pboff[j0] = (long long)st.chain[j0] * per;
+            st.pboff[j0] = (long long)pbo;
             st.t1[j0] = T + extra;
+          }
+          if (lane == j0) {
+            r_valid = 1;
+            r_flags = flags;
+            r_e = e;
+            r_ij = ij;
+            r_pboff = pbo;
+            r_t1 = T + extra;
           }
           ++inflight;
         }
-        if (inflight == 0) {
-          int any = 0;
-          for (int j = 0; j < D; ++j) any |= st.chain[j] >= 0;
-          done = !__builtin_amdgcn_readfirstlane(any);
-        }
+        if (inflight == 0) done = !__ballot(lane < D && r_chain >= 0);
       } else {
+        int fidx = 0;
         while (!sdone) {
-          // next anti-aligned bond of the current item
-          int found = -1;
-          for (int w = cursor >> 5; w < ((clen + 31) >> 5); ++w) {
-            unsigned m = __builtin_amdgcn_readfirstlane(smask[w]);
-            if (w == (cursor >> 5)) m &= ~0u << (cursor & 31);
-            if (m) {
-              found = (w << 5) + __builtin_ctz(m);
-              break;
-            }
-          }
-          if (found >= 0 && found < clen) {
-            e = e0 + found;
-            cursor = found + 1;
-            ++issued;
+          // next anti-aligned bond of the current item at or after the cursor
+          const int cw = cursor >> 5;
+          unsigned mw = (lane >= cw && lane < ((clen + 31) >> 5)) ? r_mask : 0u;
+          if (lane == cw) mw &= ~0u << (cursor & 31);
+          const unsigned long long bal = __ballot(mw != 0u);
+          if (bal) {
+            const int fw = __builtin_ctzll(bal);
+            fidx = fw * 32 + __builtin_ctz((unsigned)rl32((int)mw, fw));
+            e = e0 + fidx;
+            cursor = fidx + 1;
             break;
-          }
-          // the item is exhausted: an item without exchanges reports zero sums now
-          if (it >= 0 && issued == 0 && lane == 0) {
-            double* o = partial + 4 * (size_t)it;
-            o[0] = o[1] = o[2] = o[3] = 0.0;
-            cnt_out[it] = 0;
           }
           jj += per_x;
           if (jj >= per_xcd_items) {
@@ -515,46 +609,48 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
             __builtin_amdgcn_s_waitcnt(0);
             sb = b;
           }
+          r_mask = 0u;
           for (int g = 0; g < clen; g += 64) {
             bool anti = false;
+            unsigned ij = 0u;
             if (g + lane < clen) {
-              const unsigned ij = sedge[e0 + g + lane];
+              ij = sedge[e0 + g + lane];
               anti = ss[ij & 0xffffu] != ss[ij >> 16];
             }
+            if (g == 0) r_bij = ij;
             const unsigned long long m = __ballot(anti);
-            if (lane == 0) {
-              smask[g >> 5] = (unsigned)m;
-              smask[(g >> 5) + 1] = (unsigned)(m >> 32);
-            }
+            if (lane == (g >> 5)) r_mask = (unsigned)m;
+            if (lane == (g >> 5) + 1) r_mask = (unsigned)(m >> 32);
           }
-          it = b * n_chunks + cc;
           cursor = 0;
-          issued = 0;
         }
         if (e >= 0) {
-          if (__builtin_amdgcn_readfirstlane(st.spb[j0]) != sb) {   // the slot's spin row
+          if (rl32(r_spb, j0) != sb) {   // the slot's spin row
             const int* srcw = reinterpret_cast<const int*>(ss);
             int* dstw = reinterpret_cast<int*>(sp + j0 * pg.spw);
             for (int k = lane; k < pg.spw / 4; k += 64) dstw[k] = srcw[k];
           }
+          const unsigned ij = clen <= 64 ? (unsigned)rl32((int)r_bij, fidx) : sedge[e];
+          const unsigned long long pbo = (unsigned long long)sb * (unsigned long long)per;
           if (lane == 0) {
-            st.spb[j0] = sb;
             st.valid[j0] = 1;
             st.flags[j0] = kJobSwap | kJobReadout;
-            st.e[j0] = e;
-            const unsigned ij = sedge[e];
             st.ij[j0] = make_int2((int)(ij & 0xffffu), (int)(ij >> 16));
-            st.pboff[j0] = (long long)sb * per;
-            st.item[j0] = it;
+            st.pboff[j0] = (long long)pbo;
             st.t1[j0] = T + extra;
+          }
+          if (lane == j0) {
+            r_valid = 1;
+            r_flags = kJobSwap | kJobReadout;
+            r_e = e;
+            r_ij = ij;
+            r_pboff = pbo;
+            r_spb = sb;
+            r_t1 = T + extra;
           }
           ++inflight;
         }
-        if (sdone && inflight == 0) {
-          flush();
-          acc_item = -1;
-          done = true;
-        }
+        if (sdone && inflight == 0) done = true;
       }
       if (done && lane == 0) st.done = 1;
       // ---- the table of the job whose table tick is the next tick
@@ -563,9 +659,9 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
         tjob = -1;
         if (t0 >= 0) {
           const int j1 = t0 % D;
-          if (__builtin_amdgcn_readfirstlane(st.valid[j1]) && __builtin_amdgcn_readfirstlane(st.t1[j1]) == T + 1) {
+          if (rl32(r_valid, j1) && rl32(r_t1, j1) == T + 1) {
             tjob = j1;
-            const V4* src = reinterpret_cast<const V4*>(gtab + (size_t)__builtin_amdgcn_readfirstlane(st.e[j1]) * tabw);
+            const V4* src = reinterpret_cast<const V4*>(gtab + (size_t)rl32(r_e, j1) * tabw);
             const int nv = tabw / 8;
 #pragma unroll
             for (int u = 0; u < kPipeTabVec; ++u) tv[u] = src[min(lane + 64 * u, nv - 1)];
@@ -582,19 +678,19 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
   // ======================= the compute waves =======================
   // MFMA A fragment of weight block blk (0 message, 1 self), K step stp, output tile tt
   auto afr = [&](int blk, int stp, int tt) { return wl + (((blk * KSB + stp) * MT + tt) * 64 + lane) * VEC; };
-  // the B operands of a tile's layer input (rows r < rows; the others zero)
-  using BF = decltype(P::make_b((const Acc*)nullptr));
-  auto operands = [&](const Acc (&h)[NS], bool keep, BF (&bop)[KSB]) {
-#pragma unroll
-    for (int stp = 0; stp < KSB; ++stp) {
-      Acc x[VEC];
-#pragma unroll
-      for (int i = 0; i < VEC; ++i) x[i] = keep ? h[stp * VEC + i] : (Acc)0;
-      bop[stp] = P::make_b(x);
-    }
+  // this lane group's slots of LDS row rw (row and stride fit 24-bit products)
+  auto lrow = [&](unsigned rw) {
+    return reinterpret_cast<Acc*>(reinterpret_cast<unsigned char*>(arena) + __umul24(rw, (unsigned)row_bytes)) + q * NS;
   };
+  // the B operands a tile holds (pipe_to_ops); a lane outside the rows a product
+  // computes holds anything: its MFMA column is never used
+  using BF = decltype(P::make_b((const Acc*)nullptr));
+  auto operands = [&](const Acc (&h)[NS], BF (&bop)[KSB]) { __builtin_memcpy(bop, h, sizeof(BF) * KSB); };
 
-  Acc hn[MAXT][NS];   // a tile's layer input, held across ticks
+  // a tile's layer input, held across ticks: B operands on the rows computed at the
+  // last layer, plain values on the ring rows requested for the next layer until
+  // phase B turns them into operands
+  Acc hn[MAXT][NS];
 #pragma unroll
   for (int k = 0; k < MAXT; ++k)
 #pragma unroll
@@ -633,6 +729,16 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
     auto tSp = [&](int k) { return tsz[k] >> 16; };
     auto tSm = [&](int k) { return tsm[k] & 0xffff; };
     auto tM = [&](int k) { return tsm[k] >> 16; };
+    // a phase ends at a barrier, so the waves with the most tiles in it set its
+    // length: they issue first (the setup wave above them all)
+    int n_a = 0, n_b = 0;
+#pragma unroll
+    for (int k = 0; k < MAXT; ++k) {
+      n_a += tl(k) >= 1 && tt(k) * 16 < tM(k);
+      n_b += tl(k) >= 1 && tt(k) * 16 < tS(k);
+    }
+    if (n_a >= 2) __builtin_amdgcn_s_setprio(2);
+    else __builtin_amdgcn_s_setprio(1);
     // ======================= phase A =======================
     // ---- message products G'^{l-1} = H'^{l-1} W_msg of the tiles (into LDS rows);
     // at layer 1 the input is the embedding of the exchanged configuration's spins
@@ -653,12 +759,11 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
           if (st.flags[j] & kJobSwap) v = (nd == ij.x) ? sj[ij.y] : ((nd == ij.y) ? sj[ij.x] : v);
           xs = v > 0 ? 1 : 0;
         }
-#pragma unroll
-        for (int i = 0; i < NS; ++i) hn[k][i] = semb[xs * F + P::lc(q, i)];
+        lds_read<Acc, NS>(semb + (2 * q + xs) * NS, hn[k]);
       }
       BF bop[KSB];
-      operands(hn[k], rin, bop);
-      Acc* row = arena + (size_t)(rin ? tb[kPipeHdr + r8 + r] : 0) * pg.row_elems + q * NS;
+      operands(hn[k], bop);
+      Acc* row = lrow(rin ? tb[kPipeHdr + r8 + r] : 0u);
 #pragma unroll
       for (int t4 = 0; t4 < MT; ++t4) {
         CF gs = CF{0, 0, 0, 0};
@@ -671,22 +776,6 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
     }
     // ---- ring rows of this tick -> LDS (requested at the end of the last tick)
     copy_store(T);
-    // ---- sampler: G'^{l-1} changed on C_{l-1}: rows back from LDS into the chain's planes
-    if constexpr (SWEEP) {
-#pragma unroll
-      for (int k = 0; k < MAXT; ++k) {
-        const int l = tl(k), t = tt(k);
-        if (l < 1 || t * 16 >= tSm(k)) continue;
-        const uint16_t* tb = tabs + ttb[k];
-        const int r = t * 16 + col;
-        if (r < tSm(k)) {
-          const int nd = tb[kPipeHdr + r];
-          Acc g[NS];
-          lds_read<Acc, NS>(arena + (size_t)tb[kPipeHdr + r8 + r] * pg.row_elems + q * NS, g);
-          lds_write<Acc, NS>(planes + st.pboff[tj(k)] + (size_t)(Lr + l - 1) * plane + (size_t)nd * F + q * NS, g);
-        }
-      }
-    }
     // ---- base H^l of ring l+1 into the lanes of hn that layer l+1 reads from it
 #pragma unroll
     for (int k = 0; k < MAXT; ++k) {
@@ -699,8 +788,9 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
       }
     }
     // ---- base readout partials of the rows of C_L (tiles at layer L), requested
-    // before the barrier (with 16 waves, whose registers are scarce, in phase B)
-    constexpr bool kR0Early = NT < 1024;
+    // before the barrier (with 16 waves, whose registers are scarce, in phase B,
+    // unless phase B stores rows: the sampler)
+    constexpr bool kR0Early = NT < 1024 || SWEEP;
     double r0[MAXT][2];
     auto r0_load = [&](int k) {
       r0[k][0] = r0[k][1] = 0.0;
@@ -719,7 +809,27 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
 #pragma unroll
       for (int k = 0; k < MAXT; ++k) r0_load(k);
     }
+    // ---- sampler: G'^{l-1} changed on C_{l-1}: rows back from LDS into the chain's
+    // planes, after this phase's loads (a wait for a load also waits for the stores
+    // issued before it)
+    if constexpr (SWEEP) {
+#pragma unroll
+      for (int k = 0; k < MAXT; ++k) {
+        const int l = tl(k), t = tt(k);
+        if (l < 1 || t * 16 >= tSm(k)) continue;
+        const uint16_t* tb = tabs + ttb[k];
+        const int r = t * 16 + col;
+        if (r < tSm(k)) {
+          const int nd = tb[kPipeHdr + r];
+          Acc g[NS];
+          lds_read<Acc, NS>(lrow(tb[kPipeHdr + r8 + r]), g);
+          lds_write<Acc, NS>(planes + st.pboff[tj(k)] + (size_t)(Lr + l - 1) * plane + (size_t)nd * F + q * NS, g);
+        }
+      }
+    }
     __syncthreads();
+    if (n_b >= 2) __builtin_amdgcn_s_setprio(2);
+    else __builtin_amdgcn_s_setprio(1);
     // ======================= phase B =======================
     // the next tick's ring rows: in flight during this phase (with 16 waves, whose
     // registers are scarce, requested after it)
@@ -728,7 +838,16 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
 #pragma unroll
     for (int k = 0; k < MAXT; ++k) {
       const int l = tl(k), t = tt(k), j = tj(k);
-      if (l < 1 || t * 16 >= tS(k)) continue;
+      if (l < 1) continue;
+      if (t * 16 >= tS(k)) {   // no row of C_l: ring rows of layer l + 1 only
+        if (l < Lr && t * 16 < tSp(k)) {
+          Acc x[NS];
+#pragma unroll
+          for (int i = 0; i < NS; ++i) x[i] = hn[k][i];
+          pipe_to_ops<P, NS>(x, hn[k]);
+        }
+        continue;
+      }
       const uint16_t* tb = tabs + ttb[k];
       const int r = t * 16 + col;
       const bool in = r < tS(k);
@@ -737,31 +856,35 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
       const bool last = l == Lr;
       const bool rd = last && (st.flags[j] & kJobReadout);
       if (!kR0Early) r0_load(k);
-      // gather sum_d A_hat[n][d] G'^{l-1}[nbr(n, d)] over the job's LDS rows
+      // gather sum_d A_hat[n][d] G'^{l-1}[nbr(n, d)] over the job's LDS rows; the sum
+      // starts from the first product (a lane outside C_l leaves m unset: never used)
       Acc m[NS];
-#pragma unroll
-      for (int i = 0; i < NS; ++i) m[i] = (Acc)0;
       if (in) {
-        const uint16_t* nbp = tb + kPipeHdr + 2 * r8 + r * dm;
-        for (int d = 0; d < dm; d += 4) {
+        const uint16_t* nbp = tb + kPipeHdr + 2 * r8 + __umul24((unsigned)r, (unsigned)dm);
+        const Acc* wpn = sev + __umul24((unsigned)nd, (unsigned)dm);
+        auto four = [&](int d, bool first) {
           const uint2 pv = *reinterpret_cast<const uint2*>(nbp + d);
-          const int pc[4] = {(int)(pv.x & 0xffffu), (int)(pv.x >> 16), (int)(pv.y & 0xffffu), (int)(pv.y >> 16)};
-          const Acc* wp4 = sev + nd * dm + d;
-          const Acc wt[4] = {wp4[0], wp4[1], wp4[2], wp4[3]};
+          const unsigned pc[4] = {pv.x & 0xffffu, pv.x >> 16, pv.y & 0xffffu, pv.y >> 16};
+          const Acc wt[4] = {wpn[d], wpn[d + 1], wpn[d + 2], wpn[d + 3]};
 #pragma unroll
           for (int uu = 0; uu < 4; ++uu) {
             Acc rowv[NS];
-            lds_read<Acc, NS>(arena + (size_t)pc[uu] * pg.row_elems + q * NS, rowv);
+            lds_read<Acc, NS>(lrow(pc[uu]), rowv);
+            // fused products in neighbour order, as the sum from zero of the full
+            // evaluation (written out: contraction may otherwise fuse either product)
 #pragma unroll
-            for (int i = 0; i < NS; ++i) m[i] += wt[uu] * rowv[i];
+            for (int i = 0; i < NS; ++i)
+              m[i] = __builtin_fmaf(wt[uu], rowv[i], (first && uu == 0) ? 0.0f : m[i]);
             if (NT == 1024) __builtin_amdgcn_sched_barrier(0);   // one neighbour row in flight
           }
-        }
+        };
+        four(0, true);   // dm >= 4
+        for (int d = 4; d < dm; d += 4) four(d, false);
       }
       // self product b + H'^{l-1} W_self on the rows of C_l, then the activation
       {
         BF bop[KSB];
-        operands(hn[k], in, bop);
+        operands(hn[k], bop);
         const Acc* bias = sbias + q * NS;
 #pragma unroll
         for (int t4 = 0; t4 < MT; ++t4) {
@@ -777,8 +900,12 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
       }
 #pragma unroll
       for (int i = 0; i < NS; ++i) m[i] = P::act(m[i]);
+      if (l < Lr) {   // the next layer's input: the rows computed and the ring rows requested
+        Acc x[NS];
 #pragma unroll
-      for (int i = 0; i < NS; ++i) hn[k][i] = in ? m[i] : hn[k][i];
+        for (int i = 0; i < NS; ++i) x[i] = in ? m[i] : hn[k][i];
+        pipe_to_ops<P, NS>(x, hn[k]);
+      }
       if (last && (rd || SWEEP)) {   // wave-uniform
         const double* va = shead + q * NS;
         const double* vp = shead + F + q * NS;
@@ -807,6 +934,7 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
       red[(T & 1) * 2 * kMaxWaves + wv] = wa;
       red[(T & 1) * 2 * kMaxWaves + kMaxWaves + wv] = wp;
     }
+    tab_convert();
     if (!kR0Early) copy_load(T);
     __syncthreads();
     if (st.done) break;
@@ -817,10 +945,10 @@ template <class P, int F, int MAXT, int NT, int NCOPY>
 __global__ __launch_bounds__(NT) void k_eloc_pipe(Net net, IncNet inc, PipeGeo pg, const uint2* __restrict__ sched,
                                                    const uint16_t* __restrict__ gtab, const int8_t* __restrict__ spins,
                                                    int B, const typename P::Acc* __restrict__ planes, int n_chunks,
-                                                   int chunk, double* __restrict__ partial, int* __restrict__ cnt) {
+                                                   int chunk, double* __restrict__ terms) {
   pipe_body<P, F, MAXT, NT, NCOPY, false>(net, inc, pg, sched, gtab, const_cast<int8_t*>(spins), B,
-                                          const_cast<typename P::Acc*>(planes), n_chunks, chunk, partial, cnt, 0, 0,
-                                          0, nullptr, nullptr);
+                                          const_cast<typename P::Acc*>(planes), n_chunks, chunk, terms, 0, 0, 0,
+                                          nullptr, nullptr);
 }
 
 template <class P, int F, int MAXT, int NT, int NCOPY>
@@ -830,8 +958,8 @@ __global__ __launch_bounds__(NT) void k_sweep_pipe(Net net, IncNet inc, PipeGeo 
                                                     unsigned long long seed, unsigned long long counter_base,
                                                     const unsigned long long* __restrict__ counter_dev,
                                                     int* __restrict__ n_accept) {
-  pipe_body<P, F, MAXT, NT, NCOPY, true>(net, inc, pg, sched, gtab, spins, B, planes, 1, 1, nullptr, nullptr, n_sweeps,
-                                         seed, counter_base, counter_dev, n_accept);
+  pipe_body<P, F, MAXT, NT, NCOPY, true>(net, inc, pg, sched, gtab, spins, B, planes, 1, 1, nullptr, n_sweeps, seed,
+                                         counter_base, counter_dev, n_accept);
 }
 
 }  // namespace gna

@@ -56,7 +56,7 @@ def test_noalloc_equals_local_energy_twice(mode, prec):
 def test_noalloc_refuses_batches_beyond_its_scratch():
     from paper_2011_12453_amd import GNA, GnaError
     n, e = w.kagome(2, 2)
-    B = 1 << 20                  # ~0.1 KB of scratch per sample: far above the 16 MiB array
+    B = 1 << 21                  # at least 52 bytes of scratch per sample: above the 64 MiB array
     g = GNA(n, e, 16, 2, tied=True, precision="fp64", max_batch=B, device=DEV, eloc_mode="full",
             act_budget_bytes=1 << 20)
     th = _dev(w.glorot_theta(16, 2, True, seed=1))
