@@ -19,8 +19,7 @@
 //            job's LDS rows; this tick's ring rows stored into LDS (requested in
 //            the last tick); base H^l rows of ring l+1 requested into the lanes of
 //            hn that layer l+1 reads from them.  Setup wave: a new job's bond table
-//            (requested in the last tick) stored; the list of the next tick's ring
-//            rows.
+//            (requested in the last tick) stored.
 //   barrier
 //   phase B  compute waves: gather of A_hat G' over the job's LDS rows, self
 //            product, activation, readout difference at layer L; the new table's
@@ -28,7 +27,8 @@
 //            requested.  Setup wave: the readout difference of the job that
 //            finished its layer L last tick (written out for the local energy, whose
 //            terms k_eloc_terms sums in bond order; or the sampler's decision on
-//            it), the slot's next job, the next table requested.
+//            it), the slot's next job, the next table requested, the list of the
+//            ring rows of the tick after next.
 //   barrier
 // The setup wave's work is on the critical path of a tick when the compute waves
 // have few tiles each: it keeps the job state in registers (LDS round trips are
@@ -41,7 +41,7 @@
 // prefix [0, |C_2|)) from layer pi + 1 to layer L, i.e. during L - pi ticks; since
 // jobs start one tick apart, L - pi slots of the pool suffice, slot = tick mod
 // (L - pi).  A bond's table carries each position's pool and offset, which the
-// setup wave turns into LDS rows when the job's table is staged.
+// compute waves turn into LDS rows when the job's table is staged.
 //
 // In the sampler a proposal writes its recomputed rows into the chain's planes as
 // they are produced (rows read later in the same evaluation are never among them),
@@ -100,6 +100,7 @@ struct PipeState {
   long long tstep[kPipeMaxD];
   double u[kPipeMaxD];
   int rowbase[kPipeMaxL];                     // first arena row of each pool slot of the job staged
+  unsigned short rb[kPipeMaxD][kPipeMaxL];    // setup wave: the same for each job slot's job
   int conv;                                   // LDS table staged this tick (uint16 offset), or -1
   int nrows[2];                               // ring rows copied in a tick (by tick parity)
   int done;
@@ -364,7 +365,11 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
       // compute waves turn its pool tags into LDS rows in phase B), with the first LDS
       // row of each pool slot of the job
       if (tjob >= 0) {
-        if (lane < Lr) st.rowbase[lane] = p_base + p_slot * p_rows;
+        if (lane < Lr) {
+          const int rbase = p_base + p_slot * p_rows;
+          st.rowbase[lane] = rbase;
+          st.rb[tjob][lane] = (unsigned short)rbase;
+        }
         const int tbo = (T % ntab) * tabw;
         uint16_t* tb = tabs + tbo;
         const int nv = tabw / 8;
@@ -386,69 +391,6 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
         }
       } else if (lane == 0) {
         st.conv = -1;
-      }
-      // ---- the list of the next tick's ring rows, layer lp = 2..L in turn and the
-      // ring's rows in list order (source 16-byte vector in the planes, destination
-      // byte offset in LDS): lane x looks after layer x + 2, one round of header
-      // reads and one of table reads for all rows
-      {
-        const int tn = T + 1, pb = tn & 1;
-        uint2* rl = reinterpret_cast<uint2*>(smem + pg.off_rows) + pb * pg.rows_max;
-        int xj = -1, xt = 0;
-        unsigned long long xsrc = 0;
-        for (int x = 0; x + 2 <= Lr; ++x) {
-          const int t0 = tn - extra - (x + 2);   // setup tick of the job at layer x + 2
-          if (t0 < 0) break;
-          const int j = t0 % D;
-          if (!rl32(r_valid, j)) continue;
-          const int tbo = rl32(r_tbo, j);
-          const unsigned long long src = rl64(r_pboff, j) + (unsigned long long)(Lr + x + 1) * plane;
-          if (lane == x) {
-            xj = j;
-            xt = tbo;
-            xsrc = src;
-          }
-        }
-        int xh = 0, xn = 0, xs = 0;
-        if (xj >= 0) {
-          xh = st.hdr[xj][lane + 2];
-          xn = st.hdr[xj][lane + 3] - xh;
-        }
-        int nrow = 0;
-        for (int x = 0; x + 2 <= Lr; ++x) {
-          const int n = rl32(xn, x);
-          if (lane == x) xs = nrow;
-          nrow += n;
-        }
-        for (int base = 0; base < nrow; base += 128) {
-          int node[2], arow[2];
-          unsigned long long src[2];
-#pragma unroll
-          for (int k = 0; k < 2; ++k) {
-            const int idx = base + lane + 64 * k;
-            int p = 0, tbo = 0;
-            unsigned long long s0 = 0;
-            for (int x = 0; x + 2 <= Lr; ++x) {
-              const int s = rl32(xs, x), n = rl32(xn, x);
-              if (idx >= s && idx < s + n) {
-                p = rl32(xh, x) + idx - s;
-                tbo = rl32(xt, x);
-                s0 = rl64(xsrc, x);
-              }
-            }
-            node[k] = tabs[tbo + kPipeHdr + p];
-            arow[k] = tabs[tbo + kPipeHdr + r8 + p];
-            src[k] = s0;
-          }
-#pragma unroll
-          for (int k = 0; k < 2; ++k) {
-            const int idx = base + lane + 64 * k;
-            if (idx < nrow)
-              rl[idx] = make_uint2((unsigned)((src[k] + (unsigned long long)node[k] * F) / (16 / sizeof(Acc))),
-                                   (unsigned)(pg.off_arena + arow[k] * row_bytes));
-          }
-        }
-        if (lane == 0) st.nrows[pb] = nrow;
       }
       copy_store(T);
       p_slot = p_slot + 1 == p_cnt ? 0 : p_slot + 1;   // the pool slots of the next tick
@@ -667,6 +609,74 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
             for (int u = 0; u < kPipeTabVec; ++u) tv[u] = src[min(lane + 64 * u, nv - 1)];
           }
         }
+      }
+      // ---- the list of the ring rows of the tick after next, layer lp = 2..L in turn
+      // and the ring's rows in list order (source 16-byte vector in the planes,
+      // destination byte offset in LDS).  Ring lp + 1 of a job lives in pool lp - 1
+      // in list order, so only the node ids come from the job's table.  Lane x looks
+      // after layer x + 2: one round of header reads, one of node-id reads.
+      {
+        const int tn = T + 2, pb = tn & 1;
+        uint2* rl = reinterpret_cast<uint2*>(smem + pg.off_rows) + pb * pg.rows_max;
+        int xj = -1, xt = 0;
+        unsigned long long xsrc = 0;
+        if (tn - extra - 2 >= 0) {
+          const int j2 = (tn - extra - 2) % D;   // slot of the job at layer 2
+          for (int x = 0; x + 2 <= Lr; ++x) {
+            if (tn - extra - (x + 2) < 0) break;
+            const int j = j2 - x < 0 ? j2 - x + D : j2 - x;
+            if (!rl32(r_valid, j)) continue;
+            const int tbo = rl32(r_tbo, j);
+            const unsigned long long src = rl64(r_pboff, j) + (unsigned long long)(Lr + x + 1) * plane;
+            if (lane == x) {
+              xj = j;
+              xt = tbo;
+              xsrc = src;
+            }
+          }
+        }
+        int xh = 0, xn = 0, xs = 0, xb = 0;
+        if (xj >= 0) {
+          xh = st.hdr[xj][lane + 2];
+          xn = st.hdr[xj][lane + 3] - xh;
+          xb = st.rb[xj][lane + 1];
+        }
+        int nrow = 0;
+        for (int x = 0; x + 2 <= Lr; ++x) {
+          const int n = rl32(xn, x);
+          if (lane == x) xs = nrow;
+          nrow += n;
+        }
+        for (int base = 0; base < nrow; base += 128) {
+          int node[2], arow[2];
+          unsigned long long src[2];
+#pragma unroll
+          for (int k = 0; k < 2; ++k) {
+            const int idx = base + lane + 64 * k;
+            int p = 0, tbo = 0, ar = 0;
+            unsigned long long s0 = 0;
+            for (int x = 0; x + 2 <= Lr; ++x) {
+              const int s = rl32(xs, x), n = rl32(xn, x);
+              if (idx >= s && idx < s + n) {
+                p = rl32(xh, x) + idx - s;
+                ar = rl32(xb, x) + idx - s;
+                tbo = rl32(xt, x);
+                s0 = rl64(xsrc, x);
+              }
+            }
+            node[k] = tabs[tbo + kPipeHdr + p];
+            arow[k] = ar;
+            src[k] = s0;
+          }
+#pragma unroll
+          for (int k = 0; k < 2; ++k) {
+            const int idx = base + lane + 64 * k;
+            if (idx < nrow)
+              rl[idx] = make_uint2((unsigned)((src[k] + (unsigned long long)node[k] * F) / (16 / sizeof(Acc))),
+                                   (unsigned)(pg.off_arena + arow[k] * row_bytes));
+          }
+        }
+        if (lane == 0) st.nrows[pb] = nrow;
       }
       copy_load(T);
       __syncthreads();
