@@ -1316,7 +1316,6 @@ gna_status pipe_configure(gna_ctx* c, IncShape shp, int which) {
   g.off_head = (int)o; o = al(o + (size_t)2 * (F + 3) * 8);
   g.off_ev = (int)o; o = al(o + (size_t)N * dmax * c->sz_Acc);
   g.off_edges = (int)o; o = al(o + (size_t)std::max(c->E, 1) * 4);
-  g.off_mask = (int)o; o = al(o + (size_t)kPipeMaskWords * 4);
   g.rows_max = 1;   // ring rows copied in one tick: rings 3 .. L+1, one job at each layer
   for (int sr = 3; sr <= L + 1; ++sr) g.rows_max += c->ball_ringmax[sr];
   g.off_rows = (int)o; o = al(o + (size_t)2 * g.rows_max * 8);

@@ -65,7 +65,7 @@ constexpr int kPipeMaxK = 8;         // tile registers per wave
 constexpr int kPipeMaxL = 14;        // layers (the table header holds |C_0| .. |C_{L+1}|)
 constexpr int kPipeHdr = 16;         // uint16 header entries of a bond table
 constexpr int kPipeTabVec = 4;       // 16-byte table vectors per lane of the setup wave
-constexpr int kPipeMaskWords = 64;   // anti-aligned bond mask of a work item (2048 bonds)
+constexpr int kPipeMaskWords = 64;   // anti-aligned bond mask of a work item (2048 bonds, a word per lane)
 
 struct PipeGeo {
   int nw, D, extra, sw;     // waves, job slots, idle ticks between setup and layer 1, setup wave
@@ -75,7 +75,7 @@ struct PipeGeo {
   int r8;                   // list positions per bond (multiple of 8)
   int ntab;                 // LDS tables (L + 1)
   int spw;                  // bytes per spin row in LDS
-  int off_w, off_arena, off_tab, off_sp, off_red, off_bias, off_emb, off_head, off_ev, off_edges, off_mask;
+  int off_w, off_arena, off_tab, off_sp, off_red, off_bias, off_emb, off_head, off_ev, off_edges;
   int off_rows;             // ring rows of a tick's copies: [2 (tick parity)][rows_max] uint2
   int rows_max;             // ring rows copied in one tick at most
   int xcd;
@@ -84,21 +84,15 @@ struct PipeGeo {
 
 // job state of a workgroup (LDS)
 struct PipeState {
-  // per job slot, written by the setup wave and read by every wave
+  // per job slot, written by the setup wave (which keeps its own copies in registers)
+  // and read by the compute waves
   int valid[kPipeMaxD];
   int flags[kPipeMaxD];
-  int e[kPipeMaxD];
   int2 ij[kPipeMaxD];
   long long pboff[kPipeMaxD];
   int t1[kPipeMaxD];                          // table tick of the job
   int tbo[kPipeMaxD];                         // its LDS table (uint16 offset), from the table tick on
   unsigned short hdr[kPipeMaxD][kPipeHdr];    // |C_0| .. |C_{L+1}| of its bond, from the table tick on
-  // setup wave only
-  int item[kPipeMaxD];                        // local energy: work item of the job
-  int spb[kPipeMaxD];                         // local energy: sample held in the slot's spin row
-  int chain[kPipeMaxD], nacc[kPipeMaxD], pend[kPipeMaxD];   // sampler: the slot's chain
-  long long tstep[kPipeMaxD];
-  double u[kPipeMaxD];
   int rowbase[kPipeMaxL];                     // first arena row of each pool slot of the job staged
   unsigned short rb[kPipeMaxD][kPipeMaxL];    // setup wave: the same for each job slot's job
   int conv;                                   // LDS table staged this tick (uint16 offset), or -1
@@ -222,29 +216,19 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
   const int per_x = gridDim.x / X;
   const int xid = blockIdx.x % X, slotx = blockIdx.x / X;
   const long long per_xcd_items = SWEEP ? 0 : (long long)((B - xid + X - 1) / X) * n_chunks;
-  if (threadIdx.x < kPipeMaxD) {
-    const int j = threadIdx.x;
-    st.valid[j] = 0;
-    st.spb[j] = -1;
-    if constexpr (SWEEP) {
-      const int b = blockIdx.x + j * gridDim.x;
-      st.chain[j] = (j < D && b < B) ? b : -1;
-      st.nacc[j] = 0;
-      st.pend[j] = -1;
-      st.tstep[j] = 0;
-    }
-  }
+  if (threadIdx.x < kPipeMaxD) st.valid[threadIdx.x] = 0;
   if (threadIdx.x == 0) {
     st.done = 0;
     st.nrows[0] = st.nrows[1] = 0;
   }
-  __syncthreads();
-  if constexpr (SWEEP) {   // the slots' first chains
-    for (int j = 0; j < D; ++j)
-      if (st.chain[j] >= 0)
-        for (int k = threadIdx.x; k < net.n; k += NT) sp[j * pg.spw + k] = spins[(size_t)st.chain[j] * net.n + k];
-    __syncthreads();
+  if constexpr (SWEEP) {   // the slots' first chains: chain blockIdx.x + j gridDim.x in slot j
+    for (int j = 0; j < D; ++j) {
+      const int b = blockIdx.x + j * gridDim.x;
+      if (b < B)
+        for (int k = threadIdx.x; k < net.n; k += NT) sp[j * pg.spw + k] = spins[(size_t)b * net.n + k];
+    }
   }
+  __syncthreads();
 
   // ---- ring-row copies (all waves share them): the rows of a tick are listed by the
   // setup wave (source 16-byte vector in the planes, destination byte offset in LDS);
