@@ -690,15 +690,17 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
 #pragma unroll
     for (int i = 0; i < NS; ++i) hn[k][i] = (Acc)0;
 
-  for (int T = 0;; ++T) {
-    const int tau = T % D;
-    const uint2 s2 = sched[tau * kMaxWaves + wv];
-    const unsigned long long s8 = (unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)s2.x) |
-                                  ((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)s2.y) << 32);
-    // this tick's tiles (wave-uniform, packed): tk = layer | tile << 8 | slot << 12
-    // (layer 0: idle), tb = the job's LDS table, sz = |C_l| | |C_{l+1}| << 16,
-    // sm = |C_{l-1}| | message rows (|C_2| at layer 1, else |C_l|) << 16
-    int tk[MAXT], ttb[MAXT], tsz[MAXT], tsm[MAXT];
+  // the wave's schedule: lane tau holds its registers' (slot, tile) at ticks tau mod D
+  const uint2 my_sched = lane < D ? sched[lane * kMaxWaves + wv] : make_uint2(~0u, ~0u);
+  // a tick's tiles (wave-uniform, packed): tk = layer | tile << 8 | slot << 12
+  // (layer 0: idle), tb = the job's LDS table, sz = |C_l| | |C_{l+1}| << 16,
+  // sm = |C_{l-1}| | message rows (|C_2| at layer 1, else |C_l|) << 16.  Decoded for
+  // the next tick at the end of phase B (the jobs at layers 1..L then are set up and
+  // staged), so that its LDS reads complete under the barrier.
+  int tk[MAXT], ttb[MAXT], tsz[MAXT], tsm[MAXT];
+  auto decode = [&](int tau) {
+    const unsigned long long s8 = (unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)my_sched.x, tau) |
+                                  ((unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)my_sched.y, tau) << 32);
 #pragma unroll
     for (int k = 0; k < MAXT; ++k) {
       const int ent = (int)((s8 >> (8 * k)) & 0xffu);
@@ -706,7 +708,7 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
       ttb[k] = tsz[k] = tsm[k] = 0;
       if (ent == 0xff) continue;
       const int j = ent >> 4;
-      const int l = (tau - j + D) % D - extra;
+      const int l = (tau - j < 0 ? tau - j + D : tau - j) - extra;
       if (l < 1) continue;
       const int v = st.valid[j], tbo = st.tbo[j];
       const int hm = st.hdr[j][l - 1], h = st.hdr[j][l], hp = st.hdr[j][l + 1], h2 = st.hdr[j][2];
@@ -716,6 +718,9 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
       tsz[k] = __builtin_amdgcn_readfirstlane(h | hp << 16);
       tsm[k] = __builtin_amdgcn_readfirstlane(hm | (l == 1 ? h2 : h) << 16);
     }
+  };
+  decode(0);
+  for (int T = 0, tau = 0;; ++T, tau = tau + 1 == D ? 0 : tau + 1) {
     auto tl = [&](int k) { return tk[k] & 0xff; };
     auto tt = [&](int k) { return (tk[k] >> 8) & 15; };
     auto tj = [&](int k) { return tk[k] >> 12; };
@@ -929,6 +934,7 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
       red[(T & 1) * 2 * kMaxWaves + kMaxWaves + wv] = wp;
     }
     tab_convert();
+    decode(tau + 1 == D ? 0 : tau + 1);
     if (!kR0Early) copy_load(T);
     __syncthreads();
     if (st.done) break;
