@@ -1249,10 +1249,17 @@ bool pipe_schedule(const std::vector<int>& cmax, int L, int D, int extra, int nw
       lb[o] += cost_b(it.t, l);
     }
   }
+  // bytes 6 and 7 of an entry: the waves with fewer phase-B tiles than the busiest
+  // at that tick (the light waves, which take the tick's table conversion) and the
+  // wave's rank among them (0xff: not light)
+  if (maxt > 6) return false;
   sched->assign((size_t)kPipeMaxD * kMaxWaves, uint2{0xffffffffu, 0xffffffffu});
   int ml = 0;
-  for (int tau = 0; tau < D; ++tau)
+  for (int tau = 0; tau < D; ++tau) {
+    std::vector<int> nb(nw, 0);
+    int nb_max = 0;
     for (int w = 0; w < nw; ++w) {
+      if (w == sw) continue;
       unsigned long long v = ~0ULL;
       int busy = 0;
       for (int k = 0; k < maxt; ++k) {
@@ -1261,11 +1268,23 @@ bool pipe_schedule(const std::vector<int>& cmax, int L, int D, int extra, int nw
           v = (v & ~(0xffULL << (8 * k))) | ((unsigned long long)o << (8 * k));
           const int l = ((tau - (o >> 4) - extra) % D + D) % D;
           if (l >= 1 && 16 * (o & 15) < rows_at(l)) ++busy;
+          if (l >= 1 && 16 * (o & 15) < cmax[l]) ++nb[w];
         }
       }
       (*sched)[(size_t)tau * kMaxWaves + w] = uint2{(unsigned)v, (unsigned)(v >> 32)};
       ml = std::max(ml, busy);
+      nb_max = std::max(nb_max, nb[w]);
     }
+    int nlight = 0;
+    for (int w = 0; w < nw; ++w)
+      if (w != sw && nb[w] < nb_max) ++nlight;
+    for (int w = 0, rank = 0; w < nw; ++w) {
+      if (w == sw) continue;
+      const bool light = nlight == 0 || nb[w] < nb_max;   // all compute waves when equal
+      unsigned& hi = (*sched)[(size_t)tau * kMaxWaves + w].y;
+      hi = (hi & 0xffffu) | (unsigned)(nlight == 0 ? nw - 1 : nlight) << 16 | (unsigned)(light ? rank++ : 0xff) << 24;
+    }
+  }
   if (max_load) *max_load = ml;
   return true;
 }

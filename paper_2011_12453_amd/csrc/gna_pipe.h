@@ -33,7 +33,7 @@
 // The setup wave's work is on the critical path of a tick when the compute waves
 // have few tiles each: it keeps the job state in registers (LDS round trips are
 // long under the compute waves' traffic) and the tag conversion, which needs none
-// of that state, is spread over the compute waves.
+// of that state, is spread over the compute waves with fewer tiles in the phase.
 // LDS rows of a job are not one buffer sized for the largest ball: rows of list
 // positions [0, |C_2|) (computed at layer 1 from the spins) and of each ring
 // [|C_{s-1}|, |C_s|), s >= 3 (copied from the base planes for the gather of
@@ -275,17 +275,16 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
     }
   };
 
-  // work spread over the compute waves (all waves but the setup wave, the last):
-  // entry my of every stride, interleaved so that each wave takes a like share
-  const int ncw = nw - 1, stride = 64 * ncw, my = lane * ncw + wv;
   // phase B: the pool tags (pool << 12 | offset) of the table staged this tick turned
-  // into LDS rows (the table is first read at the next tick)
-  auto tab_convert = [&]() {
+  // into LDS rows (the table is first read at the next tick), by the waves with fewer
+  // tiles in this phase than the busiest (the schedule names them: nlight waves,
+  // this wave's rank among them, 0xff when not one of them)
+  auto tab_convert = [&](int nlight, int rank) {
     const int tbo = __builtin_amdgcn_readfirstlane(st.conv);
-    if (tbo < 0) return;
+    if (tbo < 0 || rank == 0xff) return;
     uint16_t* tb = tabs + tbo;
     const int nv = tabw / 8;
-    for (int v = (kPipeHdr + r8) / 8 + my; v < nv; v += stride) {
+    for (int v = (kPipeHdr + r8) / 8 + lane * nlight + rank; v < nv; v += 64 * nlight) {
       const V4 x = *reinterpret_cast<const V4*>(tb + 8 * v);
       unsigned o[4];
 #pragma unroll
@@ -698,9 +697,12 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
   // the next tick at the end of phase B (the jobs at layers 1..L then are set up and
   // staged), so that its LDS reads complete under the barrier.
   int tk[MAXT], ttb[MAXT], tsz[MAXT], tsm[MAXT];
+  int c_nlight = 1, c_rank = 0xff;   // the tick's table conversion: light waves, this wave's rank
   auto decode = [&](int tau) {
     const unsigned long long s8 = (unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)my_sched.x, tau) |
                                   ((unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)my_sched.y, tau) << 32);
+    c_nlight = (int)((s8 >> 48) & 0xffu);
+    c_rank = (int)(s8 >> 56);
 #pragma unroll
     for (int k = 0; k < MAXT; ++k) {
       const int ent = (int)((s8 >> (8 * k)) & 0xffu);
@@ -933,7 +935,7 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
       red[(T & 1) * 2 * kMaxWaves + wv] = wa;
       red[(T & 1) * 2 * kMaxWaves + kMaxWaves + wv] = wp;
     }
-    tab_convert();
+    tab_convert(c_nlight, c_rank);
     decode(tau + 1 == D ? 0 : tau + 1);
     if (!kR0Early) copy_load(T);
     __syncthreads();
