@@ -693,21 +693,34 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
   const uint2 my_sched = lane < D ? sched[lane * kMaxWaves + wv] : make_uint2(~0u, ~0u);
   // a tick's tiles (wave-uniform, packed): tk = layer | tile << 8 | slot << 12
   // (layer 0: idle), tb = the job's LDS table, sz = |C_l| | |C_{l+1}| << 16,
-  // sm = |C_{l-1}| | message rows (|C_2| at layer 1, else |C_l|) << 16.  Decoded for
-  // the next tick at the end of phase B (the jobs at layers 1..L then are set up and
-  // staged), so that its LDS reads complete under the barrier.
+  // sm = |C_{l-1}| | message rows (|C_2| at layer 1, else |C_l|) << 16.
   int tk[MAXT], ttb[MAXT], tsz[MAXT], tsm[MAXT];
   int c_nlight = 1, c_rank = 0xff;   // the tick's table conversion: light waves, this wave's rank
+  // the same for the next tick, decoded at the start of phase B (the jobs at layers
+  // 1..L of the next tick are set up and staged by then) so that its LDS reads
+  // complete under the tiles' work
+  int nk[MAXT], ntb[MAXT], nsz[MAXT], nsm[MAXT], n_nlight = 1, n_rank = 0xff;
+  auto advance = [&]() {
+#pragma unroll
+    for (int k = 0; k < MAXT; ++k) {
+      tk[k] = nk[k];
+      ttb[k] = ntb[k];
+      tsz[k] = nsz[k];
+      tsm[k] = nsm[k];
+    }
+    c_nlight = n_nlight;
+    c_rank = n_rank;
+  };
   auto decode = [&](int tau) {
     const unsigned long long s8 = (unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)my_sched.x, tau) |
                                   ((unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)my_sched.y, tau) << 32);
-    c_nlight = (int)((s8 >> 48) & 0xffu);
-    c_rank = (int)(s8 >> 56);
+    n_nlight = (int)((s8 >> 48) & 0xffu);
+    n_rank = (int)(s8 >> 56);
 #pragma unroll
     for (int k = 0; k < MAXT; ++k) {
       const int ent = (int)((s8 >> (8 * k)) & 0xffu);
-      tk[k] = 0;
-      ttb[k] = tsz[k] = tsm[k] = 0;
+      nk[k] = 0;
+      ntb[k] = nsz[k] = nsm[k] = 0;
       if (ent == 0xff) continue;
       const int j = ent >> 4;
       const int l = (tau - j < 0 ? tau - j + D : tau - j) - extra;
@@ -715,13 +728,14 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
       const int v = st.valid[j], tbo = st.tbo[j];
       const int hm = st.hdr[j][l - 1], h = st.hdr[j][l], hp = st.hdr[j][l + 1], h2 = st.hdr[j][2];
       if (!__builtin_amdgcn_readfirstlane(v)) continue;
-      tk[k] = l | (ent & 15) << 8 | j << 12;
-      ttb[k] = __builtin_amdgcn_readfirstlane(tbo);
-      tsz[k] = __builtin_amdgcn_readfirstlane(h | hp << 16);
-      tsm[k] = __builtin_amdgcn_readfirstlane(hm | (l == 1 ? h2 : h) << 16);
+      nk[k] = l | (ent & 15) << 8 | j << 12;
+      ntb[k] = __builtin_amdgcn_readfirstlane(tbo);
+      nsz[k] = __builtin_amdgcn_readfirstlane(h | hp << 16);
+      nsm[k] = __builtin_amdgcn_readfirstlane(hm | (l == 1 ? h2 : h) << 16);
     }
   };
   decode(0);
+  advance();
   for (int T = 0, tau = 0;; ++T, tau = tau + 1 == D ? 0 : tau + 1) {
     auto tl = [&](int k) { return tk[k] & 0xff; };
     auto tt = [&](int k) { return (tk[k] >> 8) & 15; };
@@ -835,6 +849,7 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
     // the next tick's ring rows: in flight during this phase (with 16 waves, whose
     // registers are scarce, requested after it)
     if (kR0Early) copy_load(T);
+    decode(tau + 1 == D ? 0 : tau + 1);
     double wa = 0.0, wp = 0.0;   // this wave's readout differences of the job at layer L
 #pragma unroll
     for (int k = 0; k < MAXT; ++k) {
@@ -936,7 +951,7 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
       red[(T & 1) * 2 * kMaxWaves + kMaxWaves + wv] = wp;
     }
     tab_convert(c_nlight, c_rank);
-    decode(tau + 1 == D ? 0 : tau + 1);
+    advance();
     if (!kR0Early) copy_load(T);
     __syncthreads();
     if (st.done) break;
