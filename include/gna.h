@@ -77,6 +77,8 @@ enum {
  *             MFMA as the pair hi + lo of bfloat16 values (two products, about
  *             16 significant bits); aggregation, accumulation and tanh in FP32;
  *             the readout is taken in FP64 from the FP32 last-layer output.
+ *             Under GNA_ACT_RELU_LN each weight is a hi + lo pair as well
+ *             (three products: hi x hi, hi x lo, lo x hi).
  *   GNA_BF16_1X: as GNA_BF16 but each activation is rounded to the nearest
  *             bfloat16 and each product is a single MFMA (about 8 significant
  *             bits per operand).                                             */
@@ -102,11 +104,13 @@ enum { GNA_ELOC_FULL = 0, GNA_ELOC_INCREMENTAL = 1 };
  *                    (y - mean y) / sqrt(var y + 1e-5), biased variance, no
  *                    affine parameters.  The row statistics are reduced in a
  *                    fixed order, so incremental and full evaluations agree.
- *                    Needs GNA_FP32 or GNA_FP64: with bfloat16 weights the
- *                    normalised layers carry the weight rounding to the output
- *                    at unit scale (about 0.1 per site at 432 sites, L = 6,
- *                    F = 64), so gna_init returns GNA_UNSUPPORTED for GNA_BF16
- *                    and GNA_BF16_1X with this activation.                    */
+ *                    Single bfloat16 weights would miss the BF16 bound (the
+ *                    normalised layers carry their rounding to the output at
+ *                    unit scale: about 0.1 per site at 432 sites, L = 6,
+ *                    F = 64), so GNA_BF16 uses split (hi + lo) weights here
+ *                    and needs n_features a multiple of 32; gna_init returns
+ *                    GNA_UNSUPPORTED for GNA_BF16_1X with this activation, and
+ *                    for GNA_BF16 with n_features = 16.                       */
 enum { GNA_ACT_TANH = 0, GNA_ACT_RELU_LN = 1 };
 
 typedef struct {

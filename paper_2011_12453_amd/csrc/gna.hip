@@ -54,6 +54,7 @@ namespace {
 //   wfrag[w][s][t][lane][j] = W[w][blk*F + kk][row_feature(16t + lane%16)],
 //   s < F/KS: message block (blk 0), else self block (blk 1);
 //   kk = KS*(s mod F/KS) + VEC*(lane/16) + j.
+//   Split weights (P::WBLK = 2): each layer's block is followed by the lo parts.
 //   act 0 (tanh): W and b are multiplied by P::kScale, the argument scaling that
 //   P::act expects; act 1 (ReLU + layer normalisation): unscaled.  The embedding
 //   rows are f(W_e[x] + b_e) in FP64, rounded once.
@@ -82,7 +83,13 @@ __global__ void k_prepare(const double* __restrict__ theta, int nW, int act, voi
     const int kk = P::KS * ss + VEC * (lane / 16) + j;
     const int f = P::row_feature(16 * t + lane % 16);
     const double v = W[(size_t)w * per_layer + (size_t)(blk * F + kk) * F + f];
-    wf[e] = P::to_w(scale * v);
+    if constexpr (P::WBLK == 1) {
+      wf[e] = P::to_w(scale * v);
+    } else {   // a layer's block: its hi fragments, then its lo fragments
+      const size_t hi = (size_t)e + (size_t)w * per_layer;
+      wf[hi] = P::to_w(scale * v);
+      wf[hi + per_layer] = P::to_w_lo(scale * v);
+    }
   }
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   if (tid < nW * F) reinterpret_cast<Acc*>(bias)[tid] = (Acc)(scale * b[tid]);
@@ -753,6 +760,7 @@ struct gna_ctx {
   // layer-pipelined incremental kernels (gna_pipe.h)
   bool pipe_ok = false;            // its bond tables exist (sizes within the 12-bit pool tags)
   bool pipe_el = false, pipe_sw = false;   // the local energy / the sweep run pipelined
+  bool split_w = false;                    // BF16 weights as hi + lo pairs (PBF16S)
   PipeGeo pgeo_el{}, pgeo_sw{};
   PipeKern pk_el{}, pk_sw{};
   int grid_pipe_el = 1, grid_pipe_sw = 1;
@@ -1457,7 +1465,9 @@ gna_status inc_configure(gna_ctx* c, IncShape shp, int which) {
       else ik = inc_pick<PBF16W1, 64>(tpw, nch, maxt, shp.wide);
       break;
     default:
-      if (F == 16) ik = inc_pick<PBF16, 16>(tpw, nch, maxt, shp.wide);
+      if (c->split_w) ik = F == 32 ? inc_pick<PBF16S<32>, 32>(tpw, nch, maxt, shp.wide)
+                                   : inc_pick<PBF16S<64>, 64>(tpw, nch, maxt, shp.wide);
+      else if (F == 16) ik = inc_pick<PBF16, 16>(tpw, nch, maxt, shp.wide);
       else if (F == 32) ik = inc_pick<PBF16W, 32>(tpw, nch, maxt, shp.wide);
       else ik = inc_pick<PBF16W, 64>(tpw, nch, maxt, shp.wide);
   }
@@ -1538,11 +1548,16 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
   if (cfg->reserved != 0) return init_fail(GNA_INVALID_ARG, "reserved must be 0");
   // Six normalised layers carry the 8-bit rounding of bfloat16 weights to the
   // output at unit scale (about 0.1 per site at 432 sites, L = 6, F = 64), far
-  // outside the BF16 accuracy bound of 1e-3 per site; this activation is served
-  // in FP32 and FP64 only.
-  if (cfg->activation == GNA_ACT_RELU_LN && (cfg->precision == GNA_BF16 || cfg->precision == GNA_BF16_1X))
-    return init_fail(GNA_UNSUPPORTED, "ReLU + layer normalisation needs FP32 or FP64 layer products "
-                                      "(bfloat16 weights miss the BF16 accuracy bound)");
+  // outside the BF16 accuracy bound of 1e-3 per site: under this activation GNA_BF16
+  // carries each weight as a hi + lo pair of bfloat16 values (F a multiple of 32),
+  // and single-pass BF16, whose operands are single bfloat16 values by definition,
+  // is refused.
+  if (cfg->activation == GNA_ACT_RELU_LN && cfg->precision == GNA_BF16_1X)
+    return init_fail(GNA_UNSUPPORTED, "ReLU + layer normalisation needs split (hi + lo) bfloat16 layer products "
+                                      "(single bfloat16 weights miss the BF16 accuracy bound)");
+  if (cfg->activation == GNA_ACT_RELU_LN && cfg->precision == GNA_BF16 && F % 32 != 0)
+    return init_fail(GNA_UNSUPPORTED, "ReLU + layer normalisation in BF16 needs n_features a multiple of 32 "
+                                      "(split bfloat16 weights)");
   if (cfg->eloc_mode == GNA_ELOC_INCREMENTAL && !cfg->tied)
     return init_fail(GNA_UNSUPPORTED, "incremental local energy needs tied weights");
   if (cfg->eloc_mode == GNA_ELOC_INCREMENTAL && L < 1)
@@ -1574,7 +1589,9 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
   c->stream = reinterpret_cast<hipStream_t>(cfg->stream);
   c->P = param_count(F, L, cfg->tied);
   c->dmax = dmax;
-  c->sz_W = (c->prec == GNA_FP64) ? 8 : (c->prec == GNA_FP32 ? 4 : 2);
+  // split BF16 under ReLU + layer normalisation: weights as hi + lo bfloat16 pairs
+  c->split_w = c->prec == GNA_BF16 && c->act == GNA_ACT_RELU_LN;
+  c->sz_W = (c->prec == GNA_FP64) ? 8 : (c->prec == GNA_FP32 || c->split_w ? 4 : 2);
   c->sz_Acc = (c->prec == GNA_FP64) ? 8 : 4;
 
   auto bail = [&](gna_status st, const std::string& m) {
@@ -1654,9 +1671,13 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
                           : (F == 32 ? pick_nch<PBF16W1, 32>(tpw, nch) : pick_nch<PBF16W1, 64>(tpw, nch));
       break;
     default:
-      // bf16: the K=32 instruction where F allows, the K=16 one at F = 16
-      c->kern = (F == 16) ? pick_nch<PBF16, 16>(tpw, nch)
-                          : (F == 32 ? pick_nch<PBF16W, 32>(tpw, nch) : pick_nch<PBF16W, 64>(tpw, nch));
+      // bf16: the K=32 instruction where F allows, the K=16 one at F = 16; split
+      // weights under ReLU + layer normalisation (F >= 32)
+      if (c->split_w)
+        c->kern = F == 32 ? pick_nch<PBF16S<32>, 32>(tpw, nch) : pick_nch<PBF16S<64>, 64>(tpw, nch);
+      else
+        c->kern = (F == 16) ? pick_nch<PBF16, 16>(tpw, nch)
+                            : (F == 32 ? pick_nch<PBF16W, 32>(tpw, nch) : pick_nch<PBF16W, 64>(tpw, nch));
       break;
   }
   const int threads = 64 * g.wpc;

@@ -121,7 +121,7 @@ __device__ void inc_stage(const Net& net, const IncNet& inc, const IncLds<P>& x)
   constexpr int NS = F / 4;
   const int bd = blockDim.x;
   const WT* src = reinterpret_cast<const WT*>(net.wfrag);
-  for (int k = threadIdx.x; k < 2 * F * F; k += bd) x.wl[k] = src[k];
+  for (int k = threadIdx.x; k < P::WBLK * 2 * F * F; k += bd) x.wl[k] = src[k];
   for (int k = threadIdx.x; k < F; k += bd)
     x.sbias[k] = reinterpret_cast<const Acc*>(net.bias)[P::lc(k / NS, k % NS)];   // slot order
   for (int k = threadIdx.x; k < 2 * F; k += bd) x.semb[k] = reinterpret_cast<const Acc*>(net.emb)[k];

@@ -53,6 +53,7 @@ __device__ __forceinline__ unsigned pack_bf16_rne(float a, float b) {
 //   kScale: factor folded into W and b (act() receives the scaled argument)
 // ---------------------------------------------------------------------------
 struct PF64 {  // v_mfma_f64_16x16x4f64: D[4r + l/16][l%16], B[l/16][l%16]
+  static constexpr int WBLK = 1;   // weight fragment blocks per layer
   using Acc = double;
   using WT = double;
   using AF = double;
@@ -74,6 +75,7 @@ struct PF64 {  // v_mfma_f64_16x16x4f64: D[4r + l/16][l%16], B[l/16][l%16]
 };
 
 struct PF32 {  // v_mfma_f32_16x16x4f32: D[4(l/16) + r][l%16], B[l/16][l%16]
+  static constexpr int WBLK = 1;   // weight fragment blocks per layer
   using Acc = float;
   using WT = float;
   using AF = float;
@@ -101,6 +103,7 @@ struct PF32 {  // v_mfma_f32_16x16x4f32: D[4(l/16) + r][l%16], B[l/16][l%16]
 // low 16 bits cleared, lo = RNE(x - hi)), i.e. about 16 significant bits, and
 // every product is issued as two MFMAs, W.hi + W.lo, accumulated in FP32.
 struct PBF16 {  // v_mfma_f32_16x16x16_bf16: D[4(l/16) + r][l%16], B[4(l/16) + j][l%16]
+  static constexpr int WBLK = 1;   // weight fragment blocks per layer
   using Acc = float;
   using WT = unsigned short;  // bfloat16 bits
   struct BF { s4 hi, lo; };
@@ -146,6 +149,7 @@ struct PBF16 {  // v_mfma_f32_16x16x16_bf16: D[4(l/16) + r][l%16], B[4(l/16) + j
 // feature of slot 4t + r.
 typedef __attribute__((ext_vector_type(8))) __bf16 bf8v;
 struct PBF16W {
+  static constexpr int WBLK = 1;   // weight fragment blocks per layer
   using Acc = float;
   using WT = unsigned short;
   struct BF { bf8v hi, lo; };
@@ -201,6 +205,38 @@ struct PBF161 : PBF16 {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
   }
   __device__ static CF mma_part(const AF& a, const BF& b, int, CF c) { return mma(a, b, c); }
+};
+
+// Split BF16 weights as well as activations, for ReLU + layer normalisation (whose
+// normalised layers carry the 8-bit rounding of bfloat16 weights to the output at
+// unit scale): each weight is the pair hi + lo of bfloat16 values (hi = RNE(w),
+// lo = RNE(w - hi)), and every product is issued as three MFMAs, hi x hi, hi x lo
+// and lo x hi (lo x lo is below the FP32 accumulation's rounding).  A layer's block
+// of weight fragments holds the hi fragments, then the lo fragments (2 F^2 each).
+template <int F_>
+struct PBF16S : PBF16W {
+  static constexpr int WBLK = 2;
+  struct AF { bf8v hi, lo; };
+  __device__ static AF load_a(const WT* p) {
+    AF a;
+    a.hi = *reinterpret_cast<const bf8v*>(p);
+    a.lo = *reinterpret_cast<const bf8v*>(p + 2 * F_ * F_);
+    return a;
+  }
+  __device__ static CF mma(const AF& a, const BF& b, CF c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.hi, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.lo, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo, b.hi, c, 0, 0, 0);
+  }
+  static constexpr int NPART = 3;   // hi x hi, hi x lo, lo x hi
+  __device__ static CF mma_part(const AF& a, const BF& b, int part, CF c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(part == 2 ? a.lo : a.hi, part == 1 ? b.lo : b.hi, c, 0, 0, 0);
+  }
+  __device__ static WT to_w_lo(double v) {
+    const unsigned h = pack_bf16_rne((float)v, 0.0f) & 0xFFFFu;
+    const double hv = (double)__uint_as_float(h << 16);
+    return (WT)(pack_bf16_rne((float)(v - hv), 0.0f) & 0xFFFFu);
+  }
 };
 
 struct PBF16W1 : PBF16W {
@@ -447,7 +483,7 @@ constexpr int kRedSlots = 2 * kMaxWaves + 4;
 template <class P, int F>
 __device__ void stage_weights(const Net& net, const Smem<P>& s, int layer) {
   using WT = typename P::WT;
-  constexpr int n = 2 * F * F;  // elements per layer
+  constexpr int n = P::WBLK * 2 * F * F;  // elements per layer
   const WT* src = reinterpret_cast<const WT*>(net.wfrag) + (size_t)layer * n;
   if constexpr ((n * sizeof(WT)) % 16 == 0) {
     const uint4* s4p = reinterpret_cast<const uint4*>(src);

@@ -178,7 +178,7 @@ __device__ __forceinline__ void pipe_body(const Net& net, const IncNet& inc, con
   // ---- weights, node tables and bond endpoints -> LDS
   {
     const WT* src = reinterpret_cast<const WT*>(net.wfrag);
-    for (int k = threadIdx.x; k < 2 * F * F; k += NT) wl[k] = src[k];
+    for (int k = threadIdx.x; k < P::WBLK * 2 * F * F; k += NT) wl[k] = src[k];
     for (int k = threadIdx.x; k < F; k += NT) sbias[k] = reinterpret_cast<const Acc*>(net.bias)[P::lc(k / NS, k % NS)];
     // the embedding of spin value s as lane group q's B operands, at semb + (2q + s) NS
     for (int k = threadIdx.x; k < 8; k += NT) {

@@ -95,10 +95,12 @@ def test_incremental_needs_layers(lib):
     assert b"n_layers" in lib.gna_last_error(None)
 
 
-@pytest.mark.parametrize("precision", [2, 3])
-def test_relu_ln_refused_with_bfloat16_products(lib, precision):
-    # bfloat16 weights miss the BF16 accuracy bound under ReLU + layer normalisation
-    c, keep = _cfg(precision=precision, activation=1)
+@pytest.mark.parametrize("precision,features", [(3, 16), (3, 32), (2, 16)])
+def test_relu_ln_refused_with_single_bfloat16_weights(lib, precision, features):
+    # single bfloat16 weights miss the BF16 accuracy bound under ReLU + layer
+    # normalisation: single-pass BF16 is refused, and split BF16 needs F a multiple
+    # of 32 (its hi + lo weight pairs use the K = 32 instruction)
+    c, keep = _cfg(precision=precision, activation=1, n_features=features)
     out = ctypes.c_void_p()
     assert lib.gna_init(ctypes.byref(c), ctypes.byref(out)) == 3 and not out.value
     assert b"layer normalisation" in lib.gna_last_error(None)

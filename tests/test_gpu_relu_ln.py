@@ -1,13 +1,14 @@
 """GPU parity of the paper's own nonlinearity (Section 2: ReLU followed by a layer
 normalisation over the F features of a node) against the FP64 oracle: log psi and
-the local energy in FP64 and FP32, the incremental local energy and sampler
-against the full ones, the reverse pass and the ISGO gradient.
+the local energy in FP64, FP32 and split BF16, the incremental local energy and
+sampler against the full ones, the reverse pass and the ISGO gradient.
 
-Tolerances follow the tanh tests: energy per site FP64 1e-10, FP32 1e-5; per-sample
-bounds are looser where stated, with the reason.  Every comparison gives the oracle
-exactly the parameters the GPU receives.  The library refuses this activation with
-bfloat16 layer products (its 8-bit weights miss the BF16 bound at unit-scale
-normalised layers); that refusal is checked without a GPU in test_abi.py.
+Tolerances follow the tanh tests: energy per site FP64 1e-10, FP32 1e-5, BF16 1e-3;
+per-sample bounds are looser where stated, with the reason.  Every comparison gives
+the oracle exactly the parameters the GPU receives.  Under this activation split
+BF16 carries each weight as a hi + lo pair of bfloat16 values (single bfloat16
+weights miss the BF16 bound at unit-scale normalised layers, so single-pass BF16 is
+refused, as is split BF16 at F = 16; checked without a GPU in test_abi.py).
 """
 import sys
 
@@ -49,10 +50,12 @@ def _site_err(got, ref, n):
     return abs(e - r) / max(abs(r), 1e-2)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_logpsi_and_local_energy_match_oracle(case, prec):
     name, build, F, L, tied, B = case
+    if prec == "bf16" and F % 32:
+        pytest.skip("split BF16 under this activation needs F a multiple of 32 (refusal tested in test_abi.py)")
     n, e = build()
     theta = w.glorot_theta(F, L, tied, seed=0, bias_std=0.1)
     spins = np.concatenate([w.random_sz0_spins(B - 1, n, 1000 + B), w.random_spins(1, n, 5)])
@@ -71,14 +74,16 @@ def test_logpsi_and_local_energy_match_oracle(case, prec):
     site = _site_err(el[:, 0], el_ref.real, n)
     print(f"[gpu] relu_ln {name} {prec}: logpsi rel {lp_err:.2e} eloc rel {el_err:.2e} e/site rel {site:.2e}",
           file=sys.stderr, flush=True)
-    tol = {"fp64": (1e-12, 1e-11, 1e-10), "fp32": (1e-5, 1e-4, 1e-5)}[prec]
+    tol = {"fp64": (1e-12, 1e-11, 1e-10), "fp32": (1e-5, 1e-4, 1e-5), "bf16": (1e-3, 1e-2, 1e-3)}[prec]
     assert lp_err < tol[0] and el_err < tol[1] and site < tol[2]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
 @pytest.mark.parametrize("case", [c for c in CASES if c[4]], ids=[c[0] for c in CASES if c[4]])
 def test_incremental_local_energy_equals_full(case, prec):
     name, build, F, L, tied, B = case
+    if prec == "bf16" and F % 32:
+        pytest.skip("split BF16 under this activation needs F a multiple of 32")
     n, e = build()
     theta = w.glorot_theta(F, L, tied, seed=2, weight_scale=1.5, bias_std=0.3)
     spins = np.concatenate([w.random_sz0_spins(B, n, 3000 + B), w.random_spins(2, n, 78)])
@@ -99,10 +104,10 @@ def test_incremental_local_energy_equals_full(case, prec):
     assert np.max(np.abs(ei - ef)) < 1e-12 * scale
     err = np.max(np.abs(ei[:, 0] - ref.real) + np.abs(ei[:, 1] - ref.imag)) / scale
     print(f"[gpu] relu_ln incremental {name} {prec}: eloc rel {err:.2e}", file=sys.stderr, flush=True)
-    assert err < {"fp64": 1e-11, "fp32": 1e-4}[prec]
+    assert err < {"fp64": 1e-11, "fp32": 1e-4, "bf16": 1e-2}[prec]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
 def test_incremental_sampler_matches_full_sampler(prec):
     n, e = w.kagome(6, 6)
     F, L = 32, 4
@@ -198,17 +203,17 @@ def test_isgo_grad_hard_core_bosons_matches_oracle(mode):
     assert stats[3] == pytest.approx(rs["ess"], rel=1e-12) and stats[6] == rs["n_evals"]
 
 
-@pytest.mark.parametrize("bias_std", [0.0, 0.1])
-def test_full_size_sampled_parity(bias_std):
-    # 432-site Kagome, 6 tied layers of width 64, incremental local energy, FP32,
-    # the whole batch of 64 in one launch; the oracle checks sampled rows on the
-    # same parameters
+@pytest.mark.parametrize("prec,bias_std", [("fp32", 0.0), ("fp32", 0.1), ("bf16", 0.0), ("bf16", 0.1)])
+def test_full_size_sampled_parity(prec, bias_std):
+    # 432-site Kagome, 6 tied layers of width 64, incremental local energy, FP32 or
+    # split BF16, the whole batch of 64 in one launch; the oracle checks sampled rows
+    # on the same parameters
     p = w.preset("kagome432_L6F64")
     n, e = p.build_graph()
     F, L = p.n_features, p.n_layers
     theta = w.glorot_theta(F, L, True, seed=p.theta_seed, bias_std=bias_std)
     spins = w.random_sz0_spins(64, n, p.spin_seed)
-    g = _ctx(n, e, F, L, True, "fp32", 64, "incremental")
+    g = _ctx(n, e, F, L, True, prec, 64, "incremental")
     el, nev = g.local_energy(_dev(theta), _dev(spins))
     el = el.cpu().numpy()
     lp = g.logpsi(_dev(theta), _dev(spins)).cpu().numpy()
@@ -223,10 +228,17 @@ def test_full_size_sampled_parity(bias_std):
     off = np.abs(ref - len(e) / 4.0)
     off_err = np.max(np.abs(el[rows, 0] + 1j * el[rows, 1] - ref)) / np.max(off)
     lp_err = np.max(np.abs(lp[rows] - lp_ref))
-    print(f"[gpu] relu_ln kagome432 fp32 bias {bias_std}: sampled eloc rel {err:.2e} e/site rel {site:.2e} "
+    print(f"[gpu] relu_ln kagome432 {prec} bias {bias_std}: sampled eloc rel {err:.2e} e/site rel {site:.2e} "
           f"off-diagonal err/part {off_err:.2e} logpsi abs {lp_err:.2e}", file=sys.stderr, flush=True)
     # with biases the post-ReLU rows are less sparse and the normalisation divides
     # by smaller deviations, which amplifies FP32 rounding through six layers: 2.8e-5
     # per site measured, against 1e-5 at the workload's zero-bias initialisation
-    assert site < (1e-5 if bias_std == 0.0 else 1e-4)
-    assert err < 1e-4 and off_err < 1e-3 and lp_err < 1e-3
+    if prec == "fp32":
+        assert site < (1e-5 if bias_std == 0.0 else 1e-4)
+        assert err < 1e-4 and off_err < 1e-3 and lp_err < 1e-3
+    else:
+        # the BF16 bound of 1e-3 per site holds at the workload's zero-bias
+        # initialisation; with biases the normalisation amplifies rounding through
+        # six layers (about 3x in FP32 above) and split BF16 measures 1.45e-3
+        assert site < (1e-3 if bias_std == 0.0 else 2e-3)
+        assert err < 1e-2 and off_err < 1e-1 and lp_err < 1e-1
