@@ -774,6 +774,7 @@ struct gna_ctx {
   Geo vgeo{};
   VKern vk{};
   int vgrid_fwd = 1, vgrid_dx = 1, vjp_rows = 1;
+  size_t vdx_lds = 0;   // k_vjp_dx: one layer's backward fragments and the adjacency
   void* d_vwfrag = nullptr;
   void* d_vbias = nullptr;
   void* d_vemb = nullptr;
@@ -1099,7 +1100,7 @@ gna_status run_vjp(gna_ctx* c, const double* theta, const int8_t* spins, int B, 
           Timed tm(c, "k_vjp_dx");
           void* args[] = {&v, &layer, &b0, &Bc, &cot, &planes};
           hipError_t e = hipLaunchKernel(c->vk.dx, dim3(std::min(Bc, c->vgrid_dx)), dim3(vthreads), args,
-                                         (size_t)2 * F * F * c->sz_Acc, c->stream);
+                                         c->vdx_lds, c->stream);
           if (e != hipSuccess) return hip_fail(c, e, "k_vjp_dx");
         }
         {
@@ -1781,7 +1782,9 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
       return nb;
     };
     c->vgrid_fwd = c->n_cu * vocc(c->vk.fwd, c->vgeo.lds_bytes);
-    c->vgrid_dx = c->n_cu * vocc(c->vk.dx, (int)vw_bytes);
+    // within the forward layout's LDS, which holds the same fragments and adjacency
+    c->vdx_lds = vw_bytes + (size_t)c->vgeo.npad * dmax * ((v64 ? 8 : 4) + 4);
+    c->vgrid_dx = c->n_cu * vocc(c->vk.dx, (int)c->vdx_lds);
     if (attr_fail) return bail(GNA_HIP_ERROR, "hipFuncSetAttribute: the reverse pass's LDS size was not accepted");
     c->vjp_rows = 2 * c->n_cu;
     c->nplanes = 2 * L + 5 + (c->act ? L : 0);   // + post-ReLU rows Y^1..Y^L

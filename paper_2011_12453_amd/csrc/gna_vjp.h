@@ -91,10 +91,19 @@ __global__ __launch_bounds__(512) void k_vjp_dx(VNet v, int layer, int b0, int B
   constexpr int NS = F / 4, MT = F / 16, KSB = F / 4;
   extern __shared__ __align__(16) unsigned char smem[];
   Acc* wfr = reinterpret_cast<Acc*>(smem);   // one layer of backward fragments
+  // the adjacency (ELL: A_hat value and neighbour of each node and slot), the same
+  // for every sample
+  Acc* sval = wfr + 2 * F * F;
+  int* sidx = reinterpret_cast<int*>(sval + (size_t)v.npad * v.dmax);
   const int wi = v.tied ? 0 : layer;
   {
     const Acc* src = reinterpret_cast<const Acc*>(v.wbwd) + (size_t)wi * 2 * F * F;
     for (int k = threadIdx.x; k < 2 * F * F; k += blockDim.x) wfr[k] = src[k];
+    const Acc* ev = reinterpret_cast<const Acc*>(v.ell_val);
+    for (int k = threadIdx.x; k < v.npad * v.dmax; k += blockDim.x) {
+      sval[k] = ev[k];
+      sidx[k] = v.ell_idx[k];
+    }
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, q = lane >> 4, col = lane & 15;
@@ -103,7 +112,8 @@ __global__ __launch_bounds__(512) void k_vjp_dx(VNet v, int layer, int b0, int B
   const int nW = v.tied ? 1 : v.L;
   const double* head_a = v.theta + 3 * F + (size_t)nW * (2 * F * F + F);
   const double* head_p = head_a + F + 3;
-  const Acc* ev = reinterpret_cast<const Acc*>(v.ell_val);
+  // neighbour rows requested together in the dX_msg sum (fewer with FP64 rows)
+  constexpr int NB = sizeof(Acc) == 8 ? 1 : 4;
   for (int b = blockIdx.x; b < Bc; b += gridDim.x) {
     Acc* pb = planes + b * per;
     const Acc* Hout = pb + (size_t)(layer + 1) * v.plane;
@@ -113,6 +123,24 @@ __global__ __launch_bounds__(512) void k_vjp_dx(VNet v, int layer, int b0, int B
     Acc* dXm = pb + (size_t)plane_dXm(v) * v.plane;
     const double ca = cot[2 * (size_t)(b0 + b)], cp = cot[2 * (size_t)(b0 + b) + 1];
     Acc dxs[TPW][NS];
+    // with FP32 rows the next tile's H' and dH' are requested before this tile's
+    // products (FP64 rows have no registers for it)
+    constexpr bool kPre = sizeof(Acc) == 4;
+    const bool top = layer == v.L - 1;
+    Acc hn_n[NS], dh_n[NS];
+    auto fetch = [&](int k) {
+      const int tile = wv + k * v.wpc;
+      if (tile >= v.ntiles) return;
+      const size_t off = (size_t)(tile * 16 + col) * F + q * NS;
+      lds_read<Acc, NS>(Hout + off, hn_n);
+      if (!top) {
+        lds_read<Acc, NS>(dHin + off, dh_n);
+      } else {
+#pragma unroll
+        for (int i = 0; i < NS; ++i) dh_n[i] = (Acc)0;   // seeded from the cotangents below
+      }
+    };
+    if (kPre) fetch(0);
 #pragma unroll
     for (int k = 0; k < TPW; ++k) {
       const int tile = wv + k * v.wpc;
@@ -121,15 +149,19 @@ __global__ __launch_bounds__(512) void k_vjp_dx(VNet v, int layer, int b0, int B
       const bool real = node < v.n;
       const size_t off = (size_t)node * F + q * NS;
       Acc hn[NS], dh[NS], dp[NS];
-      lds_read<Acc, NS>(Hout + off, hn);
-      if (layer == v.L - 1) {
+      if (!kPre) fetch(k);
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        hn[i] = hn_n[i];
+        dh[i] = dh_n[i];
+      }
+      if (kPre && k + 1 < TPW) fetch(k + 1);
+      if (top) {
 #pragma unroll
         for (int i = 0; i < NS; ++i) {
           const int f = P::lc(q, i);
           dh[i] = (Acc)(ca * head_a[f] + cp * head_p[f]);
         }
-      } else {
-        lds_read<Acc, NS>(dHin + off, dh);
       }
       if (v.act == 0) {
 #pragma unroll
@@ -172,11 +204,25 @@ __global__ __launch_bounds__(512) void k_vjp_dx(VNet v, int layer, int b0, int B
 #pragma unroll
       for (int i = 0; i < NS; ++i) acc[i] = dxs[k][i];
       if (node < v.n) {
-        for (int d = 0; d < v.dmax; ++d) {
-          const int nb = v.ell_idx[node * v.dmax + d];
-          const Acc a = ev[node * v.dmax + d];
+        const int* ip = sidx + node * v.dmax;
+        const Acc* vp = sval + node * v.dmax;
+        // the sum in neighbour order; NB rows in flight at a time
+        int d = 0;
+        for (; d + NB <= v.dmax; d += NB) {
+          Acc row[NB][NS];
+#pragma unroll
+          for (int u = 0; u < NB; ++u) lds_read<Acc, NS>(dXm + (size_t)ip[d + u] * F + q * NS, row[u]);
+#pragma unroll
+          for (int u = 0; u < NB; ++u) {
+            const Acc a = vp[d + u];
+#pragma unroll
+            for (int i = 0; i < NS; ++i) acc[i] += a * row[u][i];
+          }
+        }
+        for (; d < v.dmax; ++d) {
+          const Acc a = vp[d];
           Acc row[NS];
-          lds_read<Acc, NS>(dXm + (size_t)nb * F + q * NS, row);
+          lds_read<Acc, NS>(dXm + (size_t)ip[d] * F + q * NS, row);
 #pragma unroll
           for (int i = 0; i < NS; ++i) acc[i] += a * row[i];
         }
@@ -221,7 +267,7 @@ __global__ __launch_bounds__(256) void k_vjp_dw(VNet v, int layer, int Bc, const
   // m-tiles of this wave; with 2F/16 a multiple of 4 every wave has MTW of them
   constexpr bool ALL_M = (2 * MT) % 4 == 0;
   // U k-steps per round: all their loads are issued before their MFMAs
-  constexpr int U = 4;
+  constexpr int U = sizeof(Acc) == 4 ? 8 : 4;
   auto round = [&](auto u_const) {
     constexpr int UU = decltype(u_const)::value;
     Acc bf[UU][MT], af[UU][MTW];
