@@ -414,7 +414,16 @@ __global__ void k_vjp_reduce(const double* __restrict__ part, int nrows, int npa
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= npar) return;
   double s = 0.0, c = 0.0;
-  for (int r = 0; r < nrows; ++r) neumaier(s, c, part[(size_t)r * npar + k]);
+  // rows in order; 32 of them requested at a time
+  int r = 0;
+  for (; r + 32 <= nrows; r += 32) {
+    double x[32];
+#pragma unroll
+    for (int u = 0; u < 32; ++u) x[u] = part[(size_t)(r + u) * npar + k];
+#pragma unroll
+    for (int u = 0; u < 32; ++u) neumaier(s, c, x[u]);
+  }
+  for (; r < nrows; ++r) neumaier(s, c, part[(size_t)r * npar + k]);
   grad[k] = s + c;
 }
 
@@ -1120,7 +1129,7 @@ gna_status run_vjp(gna_ctx* c, const double* theta, const int8_t* spins, int B, 
     }
   }
   Timed tm(c, "k_vjp_reduce");
-  hipLaunchKernelGGL(k_vjp_reduce, dim3((int)((c->P + 255) / 256)), dim3(256), 0, c->stream, c->d_vjp_part, rows,
+  hipLaunchKernelGGL(k_vjp_reduce, dim3((int)((c->P + 63) / 64)), dim3(64), 0, c->stream, c->d_vjp_part, rows,
                      (int)c->P, grad);
   return check_launch(c, "k_vjp_reduce");
 }

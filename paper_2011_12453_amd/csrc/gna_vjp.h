@@ -364,19 +364,39 @@ __global__ __launch_bounds__(256) void k_vjp_tail(VNet v, int b0, int Bc, const 
     const double dz = ca * ha[fl] + cp * ha[F + 3 + fl];
     double z = 0;
     int nup = 0;
-    for (int node = rs; node < v.n; node += nrs) {
-      const size_t o = (size_t)node * F + p;
-      nup += sb[node] > 0;
-      const double dh0 = v.L > 0 ? (double)dH0[o] : dz;
+    auto one = [&](int8_t s, Acc dh, Acc h, Acc hl) {
+      nup += s > 0;
+      const double dh0 = v.L > 0 ? (double)dh : dz;
       double dp0;
       if (v.act == 0) {
-        const double h0 = (double)H0[o];
+        const double h0 = (double)h;
         dp0 = dh0 * (1.0 - h0 * h0);
       } else {   // the embedding row depends on the spin only: its VJP is applied to the sums
         dp0 = dh0;
       }
-      if (sb[node] > 0) e1 += dp0; else e0 += dp0;
-      z += (double)HL[o];
+      if (s > 0) e1 += dp0; else e0 += dp0;
+      z += (double)hl;
+    };
+    // this thread's nodes in order, eight requested at a time
+    constexpr int NU = 8;
+    int node = rs;
+    for (; node + (NU - 1) * nrs < v.n; node += NU * nrs) {
+      int8_t s4[NU];
+      Acc dh4[NU], h4[NU], hl4[NU];
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        const size_t o = (size_t)(node + u * nrs) * F + p;
+        s4[u] = sb[node + u * nrs];
+        dh4[u] = v.L > 0 ? dH0[o] : (Acc)0;
+        h4[u] = v.act == 0 ? H0[o] : (Acc)0;
+        hl4[u] = HL[o];
+      }
+#pragma unroll
+      for (int u = 0; u < NU; ++u) one(s4[u], dh4[u], h4[u], hl4[u]);
+    }
+    for (; node < v.n; node += nrs) {
+      const size_t o = (size_t)node * F + p;
+      one(sb[node], v.L > 0 ? dH0[o] : (Acc)0, v.act == 0 ? H0[o] : (Acc)0, HL[o]);
     }
     za += ca * z;
     zp += cp * z;
