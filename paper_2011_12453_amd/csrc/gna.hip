@@ -227,15 +227,25 @@ __global__ void k_eloc_finalize(const int8_t* __restrict__ spins, int N, const i
                                 int E, double jz, double jxy, double hb, double cb, int B, int n_chunks,
                                 const double* __restrict__ partial, const int* __restrict__ cnt,
                                 double* __restrict__ eloc, long long* n_evals) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  // one wave per sample: its lanes split the bonds of the diagonal and field sums
+  // (integers, exact in any order); lane 0 adds the exchange part
+  const int lane = threadIdx.x & 63;
+  const int b = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (b >= B) return;
   const int8_t* sb = spins + (size_t)b * N;
   long long diag = 0, field = 0;
-  for (int e = 0; e < E; ++e) {
-    const int si = sb[edges[e].x], sj = sb[edges[e].y];
+  for (int e = lane; e < E; e += 64) {
+    const int2 ij = edges[e];
+    const int si = sb[ij.x], sj = sb[ij.y];
     diag += si * sj;
     field += si + sj;
   }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    diag += __shfl_xor(diag, o, 64);
+    field += __shfl_xor(field, o, 64);
+  }
+  if (lane != 0) return;
   double sr = 0, cr = 0, si = 0, ci = 0;
   long long ne = 1;
   for (int c = 0; c < n_chunks; ++c) {
@@ -1036,7 +1046,7 @@ gna_status run_eloc(gna_ctx* c, const double* theta, const int8_t* spins, int B,
       }
       if (gna_status st = check_launch(c, "k_eloc_terms")) return st;
       Timed tm(c, "k_eloc_finalize");
-      hipLaunchKernelGGL(k_eloc_finalize, dim3((B + 255) / 256), dim3(256), 0, c->stream, spins, c->N,
+      hipLaunchKernelGGL(k_eloc_finalize, dim3((B + 3) / 4), dim3(256), 0, c->stream, spins, c->N,
                          c->d_edges, c->E, c->jz, c->jxy, c->hb, c->cb, B, n_chunks, partial, cnt, eloc, nev);
       return check_launch(c, "k_eloc_finalize");
     }
@@ -1057,7 +1067,7 @@ gna_status run_eloc(gna_ctx* c, const double* theta, const int8_t* spins, int B,
     if (gna_status st = launch(c, c->kern.eloc, grid, args, "k_eloc")) return st;
   }
   Timed tm(c, "k_eloc_finalize");
-  hipLaunchKernelGGL(k_eloc_finalize, dim3((B + 255) / 256), dim3(256), 0, c->stream, spins, c->N,
+  hipLaunchKernelGGL(k_eloc_finalize, dim3((B + 3) / 4), dim3(256), 0, c->stream, spins, c->N,
                      c->d_edges, c->E, c->jz, c->jxy, c->hb, c->cb, B, n_chunks, partial, cnt, eloc, nev);
   return check_launch(c, "k_eloc_finalize");
 }
