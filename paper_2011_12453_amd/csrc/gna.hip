@@ -223,6 +223,49 @@ __global__ void k_eloc_terms(const int8_t* __restrict__ spins, int N, const int2
   cnt[item] = n;
 }
 
+// log psi of each chain from the layer-L readout partials that its planes hold (the
+// incremental base pass writes them and the incremental sampler keeps them current):
+// the sum of the full evaluation, replayed in its order -- each lane adds its tiles'
+// partials in tile order, the wave sums its lanes (wave_sum), the waves' sums are
+// added in wave order, then the spin-count terms -- so the result is bitwise the
+// full evaluation's.  One wave per chain.
+__global__ void k_logpsi_planes(const unsigned char* __restrict__ planes, size_t per_bytes, size_t part_off,
+                                const int8_t* __restrict__ spins, int N, int B, int wpc, int tpw, int F,
+                                const double* __restrict__ head_a, const double* __restrict__ head_p,
+                                double* __restrict__ out) {
+  const int lane = threadIdx.x & 63, col = lane & 15, q = lane >> 4;
+  const int b = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (b >= B) return;
+  const double* part = reinterpret_cast<const double*>(planes + (size_t)b * per_bytes + part_off);
+  double a = 0.0, p = 0.0;
+  for (int w = 0; w < wpc; ++w) {
+    double pa = 0.0, pp = 0.0;
+    for (int k = 0; k < tpw; ++k) {
+      const int node = (w + k * wpc) * 16 + col;
+      if (node < N) {
+        pa += part[(size_t)node * 8 + q * 2];
+        pp += part[(size_t)node * 8 + q * 2 + 1];
+      }
+    }
+    pa = wave_sum(pa);
+    pp = wave_sum(pp);
+    a += pa;
+    p += pp;
+  }
+  const int8_t* sb = spins + (size_t)b * N;
+  int c = 0;
+  for (int k = lane; k < N; k += 64) c += sb[k] > 0 ? 1 : 0;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o, 64);
+  if (lane == 0) {
+    const double nup = (double)c, ndn = (double)N - nup;
+    a += head_a[F] * ndn + head_a[F + 1] * nup + head_a[F + 2];
+    p += head_p[F] * ndn + head_p[F + 1] * nup + head_p[F + 2];
+    out[2 * (size_t)b] = a;
+    out[2 * (size_t)b + 1] = p;
+  }
+}
+
 __global__ void k_eloc_finalize(const int8_t* __restrict__ spins, int N, const int2* __restrict__ edges,
                                 int E, double jz, double jxy, double hb, double cb, int B, int n_chunks,
                                 const double* __restrict__ partial, const int* __restrict__ cnt,
@@ -961,6 +1004,22 @@ gna_status run_logpsi(gna_ctx* c, const double* theta, const int8_t* spins, int 
   int grid = std::min(B, c->grid_logpsi);
   void* args[] = {&net, &spins, &B, &out};
   return launch(c, c->kern.logpsi, grid, args, "k_logpsi");
+}
+
+// log psi of the chains whose planes hold their current base pass (after the
+// incremental sampler), read from the readout partials; bitwise run_logpsi's result
+gna_status run_logpsi_planes(gna_ctx* c, const double* theta, const int8_t* spins, int B, double* out) {
+  if (B == 0) return GNA_OK;
+  if (c->L < 1) return run_logpsi(c, theta, spins, B, out);
+  const size_t plane = (size_t)c->geo.npad * c->F;
+  const size_t per_bytes = (size_t)2 * c->L * plane * c->sz_Acc;
+  const size_t part_off = (size_t)(c->L - 1) * plane * c->sz_Acc;
+  const Net net = make_net(c, theta);
+  Timed tm(c, "k_logpsi_planes");
+  hipLaunchKernelGGL(k_logpsi_planes, dim3((B + 3) / 4), dim3(256), 0, c->stream,
+                     reinterpret_cast<const unsigned char*>(c->d_inc_planes), per_bytes, part_off, spins, c->N, B,
+                     c->geo.wpc, c->tpw, c->F, net.head_a, net.head_p, out);
+  return check_launch(c, "k_logpsi_planes");
 }
 
 IncNet make_inc(const gna_ctx* c) {
@@ -2117,7 +2176,7 @@ static gna_status run_sweep(gna_ctx* c, const double* theta, int8_t* spins, doub
         if (e != hipSuccess) return hip_fail(c, e, "k_sweep_pipe");
       }
       if (gna_status st = check_launch(c, "k_sweep_pipe")) return st;
-      return run_logpsi(c, theta, spins, B, logpsi);
+      return run_logpsi_planes(c, theta, spins, B, logpsi);
     }
     IncGeo ig = c->igeo_sw;
     const int grid_s = std::max(1, std::min(c->grid_sweep_inc, (B + ig.S - 1) / ig.S));
@@ -2128,7 +2187,7 @@ static gna_status run_sweep(gna_ctx* c, const double* theta, int8_t* spins, doub
       if (e != hipSuccess) return hip_fail(c, e, "k_sweep_inc");
     }
     if (gna_status st = check_launch(c, "k_sweep_inc")) return st;
-    return run_logpsi(c, theta, spins, B, logpsi);
+    return run_logpsi_planes(c, theta, spins, B, logpsi);
   }
   int grid = std::min(B, c->grid_sweep);
   int Bv = B, ns = n_sweeps;

@@ -118,6 +118,8 @@ def test_pipelined_sampler_equals_group(case, prec, waves):
         th, sp = _dev(theta), _dev(s0)
         lp = g.logpsi(th, sp)
         acc = g.metropolis_sweep(th, sp, lp, n_sweeps=2, seed=4242, counter_base=9)
+        # log psi read from the planes the sweep left is bitwise the full evaluation's
+        assert torch.equal(lp, g.logpsi(th, sp))
         el, _ = g.local_energy(th, sp)   # the planes the sweep left are rebuilt and agree
         out.append((sp.cpu().numpy(), lp.cpu().numpy(), acc.cpu().numpy(), el.cpu().numpy()))
         g.close()
@@ -188,7 +190,9 @@ def test_pipelined_full_size_equals_group_and_oracle():
         g = _ctx(n, e, F, L, "bf16", 48, waves)
         el, _ = g.local_energy(th, sp)
         s1, s2 = sp[:16].clone(), sp[:16].clone()
-        a1 = g.metropolis_sweep(th, s1, g.logpsi(th, s1), n_sweeps=1, seed=77)
+        lp1 = g.logpsi(th, s1)
+        a1 = g.metropolis_sweep(th, s1, lp1, n_sweeps=1, seed=77)
+        assert torch.equal(lp1, g.logpsi(th, s1))   # from the planes: bitwise the full evaluation
         g.close()
         r = _ctx(n, e, F, L, "bf16", 16)
         a2 = r.metropolis_sweep(th, s2, r.logpsi(th, s2), n_sweeps=1, seed=77)
