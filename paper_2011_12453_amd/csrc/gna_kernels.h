@@ -767,12 +767,19 @@ __device__ void eval_config(const Net& net, const Smem<P>& s, int si, int sj,
           Acc m[CS];
 #pragma unroll
           for (int i = 0; i < CS; ++i) m[i] = (Acc)0;
-          for (int d = 0; d < net.dmax; ++d) {
-            Acc row[CS];
-            lds_read<Acc, CS>(hb + s.idx[node[k] * net.dmax + d] * g.row_elems + q * CS, row);
-            const Acc a = s.val[node[k] * net.dmax + d];
+          // in neighbour order, four rows requested at a time (the list is padded to a
+          // multiple of 4)
+          for (int d = 0; d < net.dmax; d += 4) {
+            Acc row[4][CS];
 #pragma unroll
-            for (int i = 0; i < CS; ++i) m[i] += a * row[i];
+            for (int u = 0; u < 4; ++u)
+              lds_read<Acc, CS>(hb + s.idx[node[k] * net.dmax + d + u] * g.row_elems + q * CS, row[u]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const Acc a = s.val[node[k] * net.dmax + d + u];
+#pragma unroll
+              for (int i = 0; i < CS; ++i) m[i] += a * row[u][i];
+            }
           }
           lds_write<Acc, CS>(store + (net.L + 1 + l) * plane + node[k] * F + q * NS + ch * CS, m);
         }
