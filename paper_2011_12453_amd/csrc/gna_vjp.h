@@ -381,18 +381,18 @@ __global__ __launch_bounds__(256) void k_vjp_tail(VNet v, int b0, int Bc, const 
     constexpr int NU = 8;
     int node = rs;
     for (; node + (NU - 1) * nrs < v.n; node += NU * nrs) {
-      int8_t s4[NU];
-      Acc dh4[NU], h4[NU], hl4[NU];
+      int8_t sv[NU];
+      Acc dhv[NU], hv[NU], hlv[NU];
 #pragma unroll
       for (int u = 0; u < NU; ++u) {
         const size_t o = (size_t)(node + u * nrs) * F + p;
-        s4[u] = sb[node + u * nrs];
-        dh4[u] = v.L > 0 ? dH0[o] : (Acc)0;
-        h4[u] = v.act == 0 ? H0[o] : (Acc)0;
-        hl4[u] = HL[o];
+        sv[u] = sb[node + u * nrs];
+        dhv[u] = v.L > 0 ? dH0[o] : (Acc)0;
+        hv[u] = v.act == 0 ? H0[o] : (Acc)0;
+        hlv[u] = HL[o];
       }
 #pragma unroll
-      for (int u = 0; u < NU; ++u) one(s4[u], dh4[u], h4[u], hl4[u]);
+      for (int u = 0; u < NU; ++u) one(sv[u], dhv[u], hv[u], hlv[u]);
     }
     for (; node < v.n; node += nrs) {
       const size_t o = (size_t)node * F + p;
