@@ -1864,7 +1864,7 @@ gna_status gna_init(const gna_config* cfg, gna_ctx** out) {
     c->vdx_lds = vw_bytes + (size_t)c->vgeo.npad * dmax * ((v64 ? 8 : 4) + 4);
     c->vgrid_dx = c->n_cu * vocc(c->vk.dx, (int)c->vdx_lds);
     if (attr_fail) return bail(GNA_HIP_ERROR, "hipFuncSetAttribute: the reverse pass's LDS size was not accepted");
-    c->vjp_rows = 2 * c->n_cu;
+    c->vjp_rows = 3 * c->n_cu;   // three 4-wave workgroups of k_vjp_dw per CU (164 registers per lane)
     c->nplanes = 2 * L + 5 + (c->act ? L : 0);   // + post-ReLU rows Y^1..Y^L
     const int64_t per_sample = (int64_t)c->nplanes * c->vgeo.npad * F * (int64_t)c->sz_Acc;
     const int64_t budget = cfg->act_budget_bytes ? cfg->act_budget_bytes : ((int64_t)16 << 30);
