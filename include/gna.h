@@ -198,8 +198,10 @@ gna_status gna_local_energy_noalloc(gna_ctx *ctx, const double *theta, const int
  * spins [B][N] and logpsi [B][2] are read and updated in place; logpsi must
  * hold the chains' current values (e.g. from gna_logpsi on this context).
  * In GNA_ELOC_INCREMENTAL mode the difference is taken from the recomputed
- * receptive field, and logpsi is overwritten at the end by the full evaluation
- * of the final configurations (bitwise what gna_logpsi returns for them).
+ * receptive field, and logpsi is overwritten at the end with log psi of the
+ * final configurations, summed from the per-node readout terms the sampler
+ * keeps current, in the full evaluation's order (bitwise what gna_logpsi
+ * returns for them).
  * n_accept: [B] int32 output (accepted swaps), may be NULL.                */
 gna_status gna_metropolis_sweep(gna_ctx *ctx, const double *theta, int8_t *spins,
                                 double *logpsi, int32_t B, int32_t n_sweeps,
